@@ -1,0 +1,44 @@
+"""FP64 CPU oracle for randomized HALS (Erichson, Mendible, Wihlborn, Kutz,
+"Randomized Nonnegative Matrix Factorization", arXiv:1711.02037).
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  It exists so that the HIP library can be
+checked against a plain, slow, obviously correct implementation written
+directly from the paper.  Only the test suite, the smoke check in
+``__graft_entry__`` and the ``cpu_baseline`` leg of ``bench.py`` may import it.
+The product path (``paper_1711_02037_amd``) never imports, calls or links it,
+and this package never imports the product.  The two share no code.
+
+Everything is NumPy in float64.  LAPACK (through ``numpy.linalg``) serves as
+the textbook routine for the QR factorisation; every other step is the
+algorithm of the paper written out in its own order and notation.
+
+Readings of passages that are silent, ambiguous or misprinted are listed in the
+module docstring of :mod:`oracle.rhals` and in the design document.
+
+Parity status: every public function here is pinned by ``tests/test_oracle_pins.py``
+against facts other than its own formula (closed forms, textbook routines,
+brute-force minimisers, an independent library implementation of
+coordinate-descent NMF, finite differences).  No function is "parity unpinned".
+"""
+
+from .rhals import (  # noqa: F401
+    GRAM_FULL,
+    GRAM_LOWDIM,
+    GRAM_MIXED,
+    ORDER_H_FIRST,
+    ORDER_W_FIRST,
+    clip,
+    qr_positive,
+    range_finder,
+    compress,
+    qb,
+    qb_streaming,
+    rhals_sweep,
+    hals_sweep,
+    rhals,
+    hals,
+    projected_gradient_sq,
+    projected_gradient_sq_compressed,
+    rel_error,
+    sketch_width,
+)
