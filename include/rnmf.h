@@ -1,0 +1,213 @@
+/*
+ * rnmf.h -- randomized HALS for nonnegative matrix factorisation on AMD
+ * MI355X (gfx950).  C ABI of librnmf.so.
+ *
+ * Method: N. B. Erichson, A. Mendible, S. Wihlborn, J. N. Kutz,
+ * "Randomized Nonnegative Matrix Factorization", arXiv:1711.02037.
+ *   X (m x n, X >= 0) ~ W H with W (m x k) >= 0 and H (k x n) >= 0,
+ *   minimising ||X - W H||_F^2 (Sec. 2.2, Eq. nmf_opt).
+ *   rnmf_sketch    : randomized range finder, Sec. 2.3 and Algorithm 1
+ *                    (sketch X Omega, q subspace iterations, QR).
+ *   rnmf_compress  : B = Q^T X, Sec. 2.3 and Algorithm 1.
+ *   rnmf_hals_step : compressed HALS sweeps, Sec. 3.2 and Algorithm 1, with
+ *                    the projected-gradient stop of Sec. 3.3.
+ *   rnmf_factorize : all of Algorithm 1 plus the relative error of Sec. 4.
+ *
+ * Conventions (every entry point):
+ *   - Matrices are dense and row-major.  X has a leading dimension ldx >= n
+ *     (elements); every other matrix is packed (leading dimension = columns).
+ *   - Every array pointer is DEVICE memory owned by the caller.  The library
+ *     never allocates device memory: scratch space is the caller's workspace
+ *     `ws` of at least rnmf_workspace_bytes(...) bytes, 256-byte aligned.
+ *     The workspace may be reused between calls once the previous call's work
+ *     on the stream has finished (stream order guarantees this).
+ *   - `stream` is a hipStream_t (cast to void*); NULL means the default
+ *     stream.  Every call only enqueues work on it, except rnmf_factorize,
+ *     which synchronises the stream to fill its report.
+ *   - Argument and shape errors are detected on the host before anything is
+ *     enqueued and return an error status; rnmf_last_error() then gives a
+ *     message (thread-local).  No function throws, exits or aborts.
+ *   - Conditions found on the device (non-finite or negative input, Cholesky
+ *     breakdown, a sweep that hit its spin limit) are written to a status word
+ *     at the start of the workspace, which every entry point clears when it
+ *     starts; rnmf_factorize reports them, and rnmf_read_status() fetches them
+ *     after an asynchronous call.
+ *   - Dtypes: in RNMF_PREC_F64 every array is double; in RNMF_PREC_F32 and
+ *     RNMF_PREC_BF16 every array is float, except X, which may also be given
+ *     as bfloat16 (RNMF_BF16) for RNMF_PREC_BF16.
+ */
+#ifndef RNMF_H
+#define RNMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rnmf_status {
+  RNMF_OK = 0,
+  RNMF_ERR_ARG = 1,            /* invalid scalar argument (k, p, q, flags ...)   */
+  RNMF_ERR_SHAPE = 2,          /* inconsistent or unsupported shape              */
+  RNMF_ERR_DTYPE = 3,          /* dtype not valid for the precision mode         */
+  RNMF_ERR_WORKSPACE = 4,      /* workspace NULL, too small or misaligned        */
+  RNMF_ERR_NONFINITE = 5,      /* NaN or Inf found in X or produced on device    */
+  RNMF_ERR_NEGATIVE_INPUT = 6, /* X has a negative entry (NMF needs X >= 0)      */
+  RNMF_ERR_NOT_SPD = 7,        /* Cholesky QR broke down even after the shift    */
+  RNMF_ERR_HIP = 8,            /* a HIP runtime call or kernel launch failed     */
+  RNMF_ERR_DEVICE_TIMEOUT = 9, /* a device-wide wait hit its spin limit          */
+  RNMF_NOT_CONVERGED = 10      /* informational: tol > 0 and max_iter was hit    */
+} rnmf_status;
+
+typedef enum rnmf_dtype { RNMF_F64 = 0, RNMF_F32 = 1, RNMF_BF16 = 2 } rnmf_dtype;
+
+/* Arithmetic of the passes over X.  F64 and F32 compute in that type.  BF16
+ * stores X as bfloat16 (cast once, round to nearest even) and runs the X
+ * passes on bf16 matrix cores with FP32 accumulation; the small operand
+ * (Omega or Q) is split into two bfloat16 terms so only X is rounded.  The
+ * orthonormalisation (Gram and Cholesky in FP64), the sweeps (FP32) and the
+ * final error (FP64 accumulation) are the same as in F32. */
+typedef enum rnmf_prec { RNMF_PREC_F64 = 0, RNMF_PREC_F32 = 1, RNMF_PREC_BF16 = 2 } rnmf_prec;
+
+/* Gram matrix used by the H update (Sec. 3.2).  FULL: S = W^T W for both the
+ * numerator and the scale, as in Algorithm 1 (default).  LOWDIM: S = W~^T W~
+ * for both, as in the printed rHALS H rule.  MIXED: W~^T W~ in the numerator
+ * with (W^T W)_jj as the scale, as the note after that rule suggests. */
+enum { RNMF_GRAM_FULL = 0, RNMF_GRAM_LOWDIM = 1, RNMF_GRAM_MIXED = 2 };
+/* Block order inside a sweep (Sec. 3.2, cyclic orders): H_FIRST updates all
+ * rows of H and then all columns of W, as Algorithm 1 (default); W_FIRST is the
+ * other blocked order. */
+enum { RNMF_ORDER_H_FIRST = 0, RNMF_ORDER_W_FIRST = 1 };
+/* Test matrix distribution when Omega is generated (Sec. 2.3 / Remark on the
+ * random test matrix): standard normal (default) or uniform on [0, 1). */
+enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
+
+/* opts.flags */
+#define RNMF_FLAG_CHECK_INPUT 0x1u      /* scan X for NaN/Inf/negative values  */
+#define RNMF_FLAG_NO_SHIFT 0x2u         /* no shifted Cholesky QR fallback     */
+#define RNMF_FLAG_EXACT_Q 0x4u          /* BF16: do not add one power iteration */
+
+typedef struct rnmf_opts {
+  int32_t k;          /* target rank, 1 <= k < min(m, n)                        */
+  int32_t p;          /* oversampling (paper default 20); l = min(k+p, m, n)    */
+  int32_t q;          /* subspace iterations (paper default 2); BF16 adds one    */
+  int32_t max_iter;   /* sweep cap                                               */
+  double tol;         /* projected-gradient ratio tolerance; <= 0: run max_iter */
+  uint64_t seed;      /* Philox key for Omega / W0 / H0 when they are NULL       */
+  int32_t prec;       /* rnmf_prec                                               */
+  int32_t omega_dist; /* RNMF_OMEGA_*                                            */
+  int32_t gram_mode;  /* RNMF_GRAM_*                                             */
+  int32_t order;      /* RNMF_ORDER_*                                            */
+  uint32_t flags;     /* RNMF_FLAG_*                                             */
+  int32_t reserved;   /* must be 0                                               */
+} rnmf_opts;
+
+typedef struct rnmf_report {
+  int32_t iters;      /* sweeps performed                                        */
+  int32_t l_eff;      /* sketch width actually used                              */
+  int32_t q_eff;      /* subspace iterations actually used                       */
+  int32_t qr_path;    /* bit0: a shifted Cholesky QR pass was needed             */
+  int32_t status;     /* rnmf_status of the run                                  */
+  int32_t reserved;
+  double rel_err;     /* ||X - W H||_F / ||X||_F, FP64 accumulation              */
+  double pg_ratio;    /* ||grad^P||^2 at the end / at the start (on Q B)         */
+  double ms_qb;       /* stream time of cast, sketch, compression and init (ms)  */
+  double ms_sweeps;   /* stream time of the sweep launch (ms)                    */
+  double ms_error;    /* stream time of the final error (ms)                     */
+} rnmf_report;
+
+/* Operation selector for rnmf_workspace_bytes. */
+enum { RNMF_OP_SKETCH = 0, RNMF_OP_COMPRESS = 1, RNMF_OP_HALS_STEP = 2,
+       RNMF_OP_FACTORIZE = 3, RNMF_OP_REL_ERROR = 4 };
+
+/* Fills opts with the paper's defaults: p = 20, q = 2 (Sec. 4, experimental
+ * setup), max_iter = 200, tol = 0, prec F32, Gaussian Omega, FULL Gram,
+ * H-first order, CHECK_INPUT set.  k is left 0 and must be set. */
+void rnmf_default_opts(rnmf_opts* opts);
+
+/* Bytes of workspace the operation needs for an m x n input (for
+ * RNMF_OP_HALS_STEP, m and n are the sizes of W's rows and H's columns).
+ * Returns 0 if the arguments are invalid (rnmf_last_error() says why). */
+size_t rnmf_workspace_bytes(int op, int64_t m, int64_t n, const rnmf_opts* opts);
+
+/* Static string for a status code (never NULL). */
+const char* rnmf_status_string(int status);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char* rnmf_last_error(void);
+
+/* Sketch width used for (k, p, m, n): min(k + p, m, n). */
+int32_t rnmf_sketch_width(int32_t k, int32_t p, int64_t m, int64_t n);
+
+/* Randomized range finder (Sec. 2.3; Algorithm 1 up to the final QR):
+ *   Y = X Omega; q times { Q = qr(Y); Q = qr(X^T Q); Y = X Q }; Q = qr(Y).
+ * X: m x n (ldx), dtype xt.  Omega: n x l test matrix in the factor dtype, or
+ * NULL to draw it from opts->seed (Philox4x32-10; normal by Box-Muller or
+ * uniform).  Q (out): m x l, orthonormal columns; qr is Cholesky QR repeated
+ * twice with the Gram and Cholesky factor in FP64, which yields the thin QR
+ * with positive diag(R); a shifted pass is prepended if the Gram is not
+ * numerically positive definite (unless RNMF_FLAG_NO_SHIFT).
+ * l_out (host, may be NULL) receives l.  Asynchronous. */
+rnmf_status rnmf_sketch(const void* X, int xt, int64_t m, int64_t n, int64_t ldx,
+                        const void* Omega, const rnmf_opts* opts, void* Q,
+                        int32_t* l_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Compression B = Q^T X (Sec. 2.3; Algorithm 1).  Q: m x l; B (out): l x n.
+ * Any n >= 1 is accepted (with X = W0 it also forms W~ = Q^T W0).  Only
+ * opts->prec is read.  The workspace query for RNMF_OP_COMPRESS sizes
+ * l = min(k + p, m).  Asynchronous. */
+rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t ldx,
+                          const void* Q, int32_t l, const rnmf_opts* opts, void* B,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* nsweeps sweeps of compressed HALS (Sec. 3.2; Algorithm 1), in place:
+ *   H phase: R = B^T W~, S (see gram_mode), rows j of H in turn:
+ *            H(j,:) <- max(0, H(j,:) + (R(:,j) - H^T S(:,j)) / S_jj)
+ *   W phase: T = B H^T, V = H H^T, columns j of W in turn:
+ *            W~(:,j) <- W~(:,j) + (T(:,j) - W~ V(:,j)) / V_jj
+ *            W(:,j)  <- max(0, Q W~(:,j));  W~(:,j) <- Q^T W(:,j)
+ * A block whose scale S_jj or V_jj is exactly zero is skipped.
+ * Q: m x l; B: l x n; W: m x k (in/out); Wt: l x k (in/out, the compressed
+ * factor W~, normally Q^T W); H: k x n (in/out).  If opts->tol > 0 the sweeps
+ * stop once ||grad^P f||^2 on Q B falls below tol times its value at entry
+ * (Sec. 3.3).  dev_stats (device, optional): 4 doubles = {sweeps done,
+ * ||grad^P||^2 at entry, at exit, status word}.  Requires k <= 64 and
+ * l <= 128.  Asynchronous. */
+rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
+                           int32_t l, int32_t k, void* W, void* Wt, void* H,
+                           int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Relative error ||X - W H||_F / ||X||_F (reading of the "error" of Sec. 4),
+ * with FP64 accumulation.  W: m x k, H: k x n in the factor dtype.  out
+ * (device): 2 doubles = {||X - W H||_F^2, ||X||_F^2}.  Asynchronous. */
+rnmf_status rnmf_rel_error(const void* X, int xt, int64_t m, int64_t n, int64_t ldx,
+                           const void* W, const void* H, int32_t k, const rnmf_opts* opts,
+                           double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Algorithm 1 end to end: sketch, compression, W~ = Q^T W0, sweeps until the
+ * stop test or max_iter, then the relative error.  Omega (n x l), W0 (m x k),
+ * H0 (k x n) are optional device inputs in the factor dtype; NULL draws them
+ * from opts->seed (W0, H0 uniform on [0, 1)).  W (out, m x k), H (out, k x n).
+ * report (host, may be NULL) is filled after the stream is synchronised.
+ * Returns the run's status (RNMF_NOT_CONVERGED only when tol > 0). */
+rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t ldx,
+                           const rnmf_opts* opts, const void* Omega, const void* W0,
+                           const void* H0, void* W, void* H, rnmf_report* report,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Cast an m x n FP32 matrix (ldx) to packed bfloat16 (round to nearest even),
+ * for callers that keep a BF16 copy of X for RNMF_PREC_BF16.  Asynchronous. */
+rnmf_status rnmf_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx,
+                           void* Xb, void* stream);
+
+/* Synchronises `stream` and returns the device status word recorded in `ws`
+ * by the most recent asynchronous call that used `ws` (each entry point clears
+ * the word when it starts), then clears it. */
+rnmf_status rnmf_read_status(void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RNMF_H */

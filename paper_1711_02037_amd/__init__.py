@@ -1,0 +1,326 @@
+"""Randomized HALS for nonnegative matrix factorisation on AMD MI355X.
+
+Python binding of ``librnmf.so`` (C ABI in ``include/rnmf.h``).  This module
+only marshals arguments: it allocates device memory through PyTorch, passes
+raw device pointers and the current HIP stream to the library, and turns
+status codes into exceptions.  Every step of the method runs in the library's
+HIP kernels; if the library is missing this module raises instead of falling
+back to anything else.
+
+Method: Erichson, Mendible, Wihlborn, Kutz, "Randomized Nonnegative Matrix
+Factorization", arXiv:1711.02037 (Sec. 2.3 randomized QB; Sec. 3.2 and
+Algorithm 1 randomized HALS; Sec. 3.3 projected-gradient stop).
+"""
+
+import ctypes
+import os
+
+__all__ = [
+    "RnmfError", "lib", "available", "make_opts", "sketch_width", "workspace_bytes",
+    "sketch", "compress", "hals_step", "rel_error", "factorize", "cast_bf16",
+    "status_string", "read_status",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librnmf.so")
+
+# status codes (include/rnmf.h)
+OK, ERR_ARG, ERR_SHAPE, ERR_DTYPE, ERR_WORKSPACE, ERR_NONFINITE, ERR_NEGATIVE_INPUT, \
+    ERR_NOT_SPD, ERR_HIP, ERR_DEVICE_TIMEOUT, NOT_CONVERGED = range(11)
+F64, F32, BF16 = 0, 1, 2
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+GRAM = {"full": 0, "lowdim": 1, "mixed": 2}
+ORDER = {"h_first": 0, "w_first": 1}
+OMEGA = {"gaussian": 0, "uniform": 1}
+FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q = 0x1, 0x2, 0x4
+OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR = range(5)
+
+EXPORTS = [
+    "rnmf_default_opts", "rnmf_workspace_bytes", "rnmf_status_string", "rnmf_last_error",
+    "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
+    "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status",
+]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("prec", ctypes.c_int32), ("omega_dist", ctypes.c_int32), ("gram_mode", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("l_eff", ctypes.c_int32), ("q_eff", ctypes.c_int32),
+                ("qr_path", ctypes.c_int32), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rel_err", ctypes.c_double), ("pg_ratio", ctypes.c_double), ("ms_qb", ctypes.c_double),
+                ("ms_sweeps", ctypes.c_double), ("ms_error", ctypes.c_double)]
+
+
+class RnmfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"rnmf status {status} ({status_string(status)}): {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librnmf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1711_02037_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.rnmf_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.rnmf_default_opts.restype = None
+        L.rnmf_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, ctypes.POINTER(Opts)]
+        L.rnmf_workspace_bytes.restype = sz
+        L.rnmf_status_string.argtypes = [ctypes.c_int]
+        L.rnmf_status_string.restype = ctypes.c_char_p
+        L.rnmf_last_error.argtypes = []
+        L.rnmf_last_error.restype = ctypes.c_char_p
+        L.rnmf_sketch_width.argtypes = [i32, i32, i64, i64]
+        L.rnmf_sketch_width.restype = i32
+        L.rnmf_sketch.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, ctypes.POINTER(Opts), vp,
+                                  ctypes.POINTER(i32), vp, sz, vp]
+        L.rnmf_sketch.restype = ctypes.c_int
+        L.rnmf_compress.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i32, ctypes.POINTER(Opts), vp,
+                                    vp, sz, vp]
+        L.rnmf_compress.restype = ctypes.c_int
+        L.rnmf_hals_step.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, ctypes.POINTER(Opts),
+                                     vp, vp, sz, vp]
+        L.rnmf_hals_step.restype = ctypes.c_int
+        L.rnmf_rel_error.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, vp, i32, ctypes.POINTER(Opts),
+                                     vp, vp, sz, vp]
+        L.rnmf_rel_error.restype = ctypes.c_int
+        L.rnmf_factorize.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Opts), vp, vp, vp,
+                                     vp, vp, ctypes.POINTER(Report), vp, sz, vp]
+        L.rnmf_factorize.restype = ctypes.c_int
+        L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
+        L.rnmf_cast_bf16.restype = ctypes.c_int
+        L.rnmf_read_status.argtypes = [vp, sz, vp]
+        L.rnmf_read_status.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def available():
+    try:
+        lib()
+        return True
+    except (RuntimeError, OSError):
+        return False
+
+
+def status_string(s):
+    return lib().rnmf_status_string(int(s)).decode()
+
+
+def _check(status, allow=()):
+    if status != OK and status not in allow:
+        raise RnmfError(status, lib().rnmf_last_error().decode())
+    return status
+
+
+def make_opts(k, p=20, q=2, max_iter=200, tol=0.0, seed=0, precision="fp32", omega="gaussian",
+              gram="full", order="h_first", check_input=True, shift=True, exact_q=False):
+    o = Opts()
+    lib().rnmf_default_opts(ctypes.byref(o))
+    o.k, o.p, o.q, o.max_iter = int(k), int(p), int(q), int(max_iter)
+    o.tol, o.seed = float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.prec, o.omega_dist = PREC[precision], OMEGA[omega]
+    o.gram_mode, o.order = GRAM[gram], ORDER[order]
+    o.flags = (FLAG_CHECK_INPUT if check_input else 0) | (0 if shift else FLAG_NO_SHIFT) | \
+        (FLAG_EXACT_Q if exact_q else 0)
+    return o
+
+
+def sketch_width(k, p, m, n):
+    return int(lib().rnmf_sketch_width(int(k), int(p), int(m), int(n)))
+
+
+def workspace_bytes(op, m, n, opts):
+    b = lib().rnmf_workspace_bytes(int(op), int(m), int(n), ctypes.byref(opts))
+    if b == 0:
+        raise RnmfError(ERR_ARG, lib().rnmf_last_error().decode())
+    return int(b)
+
+
+# ---------------------------------------------------------------------------
+# torch marshalling
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _xt(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _fdtype(precision):
+    torch = _torch()
+    return torch.float64 if precision == "fp64" else torch.float32
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need_dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+
+
+def _rowmajor(t, name):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
+    return t
+
+
+def _packed(t, name):
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:off + nbytes]
+
+
+def sketch(X, k, p=20, q=2, omega=None, precision="fp32", seed=0, omega_dist="gaussian", ws=None, **kw):
+    """Orthonormal basis Q (m x l) of the range of X (rnmf_sketch)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X")
+    m, n = X.shape
+    o = make_opts(k, p, q, seed=seed, precision=precision, omega=omega_dist, **kw)
+    l = sketch_width(k, p, m, n)
+    dt = _fdtype(precision)
+    if omega is not None:
+        _packed(omega, "omega")
+        if omega.shape != (n, l) or omega.dtype != dt:
+            raise ValueError(f"omega must be {n} x {l} of {dt}")
+    Q = torch.empty((m, l), dtype=dt, device=X.device)
+    nb = workspace_bytes(OP_SKETCH, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, X.device)
+    lo = ctypes.c_int32(0)
+    _check(lib().rnmf_sketch(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(omega), ctypes.byref(o), _ptr(Q),
+                             ctypes.byref(lo), _ptr(w), w.numel(), _stream(X.device)))
+    return Q
+
+
+def compress(X, Q, precision="fp32", ws=None):
+    """B = Q^T X (rnmf_compress)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X"); _packed(Q, "Q")
+    m, n = X.shape
+    l = Q.shape[1]
+    if Q.shape[0] != m:
+        raise ValueError("Q must have as many rows as X")
+    o = make_opts(1, l - 1, 0, precision=precision)
+    B = torch.empty((l, n), dtype=Q.dtype, device=X.device)
+    nb = workspace_bytes(OP_COMPRESS, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, X.device)
+    _check(lib().rnmf_compress(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(Q), l, ctypes.byref(o), _ptr(B),
+                               _ptr(w), w.numel(), _stream(X.device)))
+    return B
+
+
+def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, ws=None):
+    """nsweeps compressed HALS sweeps in place on W, Wt, H (rnmf_hals_step).
+    Returns (sweeps done, pg^2 at entry, pg^2 at exit)."""
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B"), (W, "W"), (Wt, "Wt"), (H, "H")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    k, n = H.shape
+    prec = precision or ("fp64" if Q.dtype == torch.float64 else "fp32")
+    o = make_opts(k, l - k, 0, tol=tol, precision=prec, gram=gram, order=order)
+    nb = workspace_bytes(OP_HALS_STEP, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, Q.device)
+    stats = torch.zeros(4, dtype=torch.float64, device=Q.device)
+    _check(lib().rnmf_hals_step(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W), _ptr(Wt), _ptr(H), int(nsweeps),
+                                ctypes.byref(o), _ptr(stats), _ptr(w), w.numel(), _stream(Q.device)))
+    s = stats.cpu().tolist()
+    _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(Q.device)))
+    return int(s[0]), s[1], s[2]
+
+
+def rel_error(X, W, H, ws=None):
+    """||X - W H||_F / ||X||_F with FP64 accumulation (rnmf_rel_error)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X")
+    m, n = X.shape
+    k = W.shape[1]
+    prec = "fp64" if W.dtype == torch.float64 else ("bf16" if X.dtype == torch.bfloat16 else "fp32")
+    o = make_opts(1, 0, 0, precision=prec)
+    nb = workspace_bytes(OP_REL_ERROR, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, X.device)
+    out = torch.zeros(2, dtype=torch.float64, device=X.device)
+    _check(lib().rnmf_rel_error(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(W), _ptr(H), k, ctypes.byref(o),
+                                _ptr(out), _ptr(w), w.numel(), _stream(X.device)))
+    se, sx = out.cpu().tolist()
+    return (se / sx) ** 0.5 if sx > 0 else 0.0
+
+
+def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, omega=None, W0=None,
+              H0=None, gram="full", order="h_first", omega_dist="gaussian", check_input=True, shift=True,
+              exact_q=False, ws=None):
+    """Algorithm 1 end to end (rnmf_factorize).  Returns (W, H, report dict)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X")
+    m, n = X.shape
+    o = make_opts(k, p, q, max_iter, tol, seed, precision, omega_dist, gram, order, check_input, shift,
+                  exact_q)
+    dt = _fdtype(precision)
+    for t, nm in ((omega, "omega"), (W0, "W0"), (H0, "H0")):
+        if t is not None:
+            _need_dev(t, nm); _packed(t, nm)
+            if t.dtype != dt:
+                raise ValueError(f"{nm} must be {dt}")
+    W = torch.empty((m, k), dtype=dt, device=X.device)
+    H = torch.empty((k, n), dtype=dt, device=X.device)
+    nb = workspace_bytes(OP_FACTORIZE, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, X.device)
+    rep = Report()
+    st = lib().rnmf_factorize(_ptr(X), _xt(X), m, n, X.stride(0), ctypes.byref(o), _ptr(omega), _ptr(W0),
+                              _ptr(H0), _ptr(W), _ptr(H), ctypes.byref(rep), _ptr(w), w.numel(),
+                              _stream(X.device))
+    _check(st, allow=(NOT_CONVERGED,))
+    info = dict(iters=rep.iters, l=rep.l_eff, q=rep.q_eff, shifted_qr=bool(rep.qr_path & 1),
+                status=rep.status, rel_err=rep.rel_err, pg_ratio=rep.pg_ratio, ms_qb=rep.ms_qb,
+                ms_sweeps=rep.ms_sweeps, ms_error=rep.ms_error)
+    return W, H, info
+
+
+def cast_bf16(X):
+    """Packed bfloat16 copy of an FP32 matrix, round to nearest even (rnmf_cast_bf16)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X")
+    m, n = X.shape
+    Xb = torch.empty((m, n), dtype=torch.bfloat16, device=X.device)
+    _check(lib().rnmf_cast_bf16(_ptr(X), m, n, X.stride(0), _ptr(Xb), _stream(X.device)))
+    return Xb
+
+
+def read_status(ws):
+    return _check(lib().rnmf_read_status(_ptr(ws), ws.numel(), None))

@@ -1,0 +1,694 @@
+// Host side of librnmf: argument checks, workspace planning and the order of
+// kernel launches for each entry point of include/rnmf.h.
+//
+// The workspace is carved by one bump allocator (Arena); the size query runs
+// the same planning code with a null base, so the two always agree.
+#include "rnmf.h"
+#include "rnmf_common.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+using namespace rnmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+rnmf_status fail(rnmf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(RNMF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t HDR_BYTES = 4096;
+// header layout (bytes): 0 status u32, 4 QR control u32, 64 stats (8 doubles),
+// 128 relative-error sums (2 doubles)
+struct Hdr {
+  unsigned* status;
+  unsigned* ctl;
+  double* stats;
+  double* rel;
+};
+Hdr header(void* ws) {
+  char* b = (char*)ws;
+  return Hdr{(unsigned*)b, (unsigned*)(b + 4), (double*)(b + 64), (double*)(b + 128)};
+}
+
+bool get_dev(Dev& d, hipStream_t s) {
+  int id = 0;
+  if (hipGetDevice(&id) != hipSuccess) return false;
+  static std::mutex mu;
+  static int cache_cus[64] = {0}, cache_lds[64] = {0};
+  std::lock_guard<std::mutex> lk(mu);
+  if (id < 0 || id >= 64) return false;
+  if (cache_cus[id] == 0) {
+    int cus = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, id) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, id) != hipSuccess) return false;
+    cache_cus[id] = cus;
+    cache_lds[id] = lds;
+  }
+  d.stream = s;
+  d.cus = cache_cus[id];
+  d.max_lds = cache_lds[id];
+  return true;
+}
+
+// Device properties for sizing when no device is usable (size queries on a
+// host without a GPU): MI355X values.
+Dev default_dev() { return Dev{nullptr, 256, 160 * 1024}; }
+
+struct Mode {
+  int dt;    // factor dtype: 0 f64, 1 f32
+  int cdt;   // X-pass compute: 0 f64, 1 f32, 2 bf16
+  int gdt;   // GEMM dtype of the orthonormalisation: 0 f64, 1 f32
+  size_t es; // bytes per factor element
+};
+
+Mode mode_of(const rnmf_opts* o) {
+  Mode md;
+  if (o->prec == RNMF_PREC_F64) { md.dt = 0; md.cdt = 0; md.gdt = 0; md.es = 8; }
+  else if (o->prec == RNMF_PREC_F32) { md.dt = 1; md.cdt = 1; md.gdt = 1; md.es = 4; }
+  else { md.dt = 1; md.cdt = 2; md.gdt = 1; md.es = 4; }
+  return md;
+}
+
+int q_effective(const rnmf_opts* o) {
+  int q = o->q;
+  if (o->prec == RNMF_PREC_BF16 && !(o->flags & RNMF_FLAG_EXACT_Q)) q += 1;
+  return q;
+}
+
+int lwidth(const rnmf_opts* o, int64_t m, int64_t n) {
+  int64_t l = (int64_t)o->k + o->p;
+  if (l > m) l = m;
+  if (l > n) l = n;
+  return (int)l;
+}
+
+rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax) {
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (o->reserved != 0) return fail(RNMF_ERR_ARG, "opts.reserved must be 0");
+  if (m < 1 || n < 1) return fail(RNMF_ERR_SHAPE, "empty matrix (m=%lld, n=%lld)", (long long)m, (long long)n);
+  if (m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "m and n must be below 2^31");
+  if (o->k < 1 || (int64_t)o->k >= (m < n ? m : n))
+    return fail(RNMF_ERR_ARG, "need 1 <= k < min(m, n) (k=%d, m=%lld, n=%lld)", o->k, (long long)m, (long long)n);
+  if (o->p < 0) return fail(RNMF_ERR_ARG, "p must be >= 0");
+  if (o->q < 0 || o->q > 32) return fail(RNMF_ERR_ARG, "q must be in [0, 32]");
+  if (o->max_iter < 0) return fail(RNMF_ERR_ARG, "max_iter must be >= 0");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode %d", o->prec);
+  if (o->omega_dist < 0 || o->omega_dist > 1) return fail(RNMF_ERR_ARG, "unknown omega_dist %d", o->omega_dist);
+  if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode %d", o->gram_mode);
+  if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order %d", o->order);
+  if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q))
+    return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
+  if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
+  int l = lwidth(o, m, n);
+  if (l > LMAX) return fail(RNMF_ERR_ARG, "sketch width l = min(k + p, m, n) = %d exceeds %d", l, LMAX);
+  if (need_kmax && o->k > KMAX) return fail(RNMF_ERR_ARG, "k = %d exceeds the supported %d", o->k, KMAX);
+  return RNMF_OK;
+}
+
+rnmf_status check_xt(const rnmf_opts* o, int xt) {
+  if (o->prec == RNMF_PREC_F64 && xt != RNMF_F64) return fail(RNMF_ERR_DTYPE, "RNMF_PREC_F64 needs X in RNMF_F64");
+  if (o->prec == RNMF_PREC_F32 && xt != RNMF_F32) return fail(RNMF_ERR_DTYPE, "RNMF_PREC_F32 needs X in RNMF_F32");
+  if (o->prec == RNMF_PREC_BF16 && xt != RNMF_F32 && xt != RNMF_BF16)
+    return fail(RNMF_ERR_DTYPE, "RNMF_PREC_BF16 needs X in RNMF_F32 or RNMF_BF16");
+  return RNMF_OK;
+}
+
+rnmf_status check_ws(void* ws, size_t have, size_t need) {
+  if (!ws) return fail(RNMF_ERR_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(RNMF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (have < need) return fail(RNMF_ERR_WORKSPACE, "workspace too small: %zu bytes given, %zu needed", have, need);
+  return RNMF_OK;
+}
+
+int64_t bf16_ld(int64_t n) { return (int64_t)round_up((size_t)n, 8); }
+
+// ---------------------------------------------------------------------------
+// Plans: pointer sets carved from an arena
+// ---------------------------------------------------------------------------
+struct QrBufs {
+  double* gpart;
+  double* G;
+  void* rinv;
+  int gsplits;
+};
+QrBufs plan_qr(Arena& a, int64_t rows, int l, const Mode& md, const Dev& d) {
+  QrBufs b;
+  b.gsplits = gram_splits(rows, d.cus);
+  b.gpart = a.take<double>((size_t)b.gsplits * LMAX * LMAX);
+  b.G = a.take<double>((size_t)l * l);
+  int lp = ceil_div(l, 16) * 16;
+  b.rinv = a.take<char>((size_t)lp * lp * (md.gdt == 0 ? 8 : 4));
+  return b;
+}
+
+struct SketchBufs {
+  void* om;
+  void* at;
+  int64_t ldp;
+  void* y;
+  void* y2;
+  void* z;
+  void* z2;
+  void* z3;
+  void* part;
+  QrBufs qy, qz;
+  XPlan nn, tn, nnq;
+};
+SketchBufs plan_sketch(Arena& a, int64_t m, int64_t n, int l, const Mode& md, const Dev& d) {
+  SketchBufs b;
+  const int lp = ceil_div(l, 16) * 16;
+  b.ldp = (int64_t)round_up((size_t)(m > n ? m : n), 16);
+  b.om = a.take<char>((size_t)n * l * md.es);
+  b.at = a.take<char>((size_t)lp * b.ldp * (md.cdt == 0 ? 8 : 4));  // bf16: two planes of 2 bytes
+  b.y = a.take<char>((size_t)m * l * md.es);
+  b.y2 = a.take<char>((size_t)m * l * md.es);
+  b.z = a.take<char>((size_t)n * l * md.es);
+  b.z2 = a.take<char>((size_t)n * l * md.es);
+  b.z3 = a.take<char>((size_t)n * l * md.es);
+  b.nn = plan_nn(m, n, l, md.cdt, d.cus);
+  b.tn = plan_tn(m, n, l, md.cdt, d.cus);
+  size_t pe = b.nn.part_elems > b.tn.part_elems ? b.nn.part_elems : b.tn.part_elems;
+  b.part = a.take<char>(pe * (md.cdt == 0 ? 8 : 4));
+  b.qy = plan_qr(a, m, l, md, d);
+  b.qz = plan_qr(a, n, l, md, d);
+  return b;
+}
+
+struct CompressBufs {
+  void* at;
+  int64_t ldp;
+  void* part;
+  XPlan tn;
+};
+CompressBufs plan_compress(Arena& a, int64_t m, int64_t n, int l, const Mode& md, const Dev& d) {
+  CompressBufs b;
+  const int lp = ceil_div(l, 16) * 16;
+  b.ldp = (int64_t)round_up((size_t)m, 16);
+  b.at = a.take<char>((size_t)lp * b.ldp * (md.cdt == 0 ? 8 : 4));
+  b.tn = plan_tn(m, n, l, md.cdt, d.cus);
+  b.part = a.take<char>(b.tn.part_elems * (md.cdt == 0 ? 8 : 4));
+  return b;
+}
+
+struct InitBufs {
+  void* at;
+  int64_t ldp;
+  void* part;
+  XPlan tn;
+};
+InitBufs plan_init(Arena& a, int64_t m, int k, int l, const Mode& md, const Dev& d) {
+  InitBufs b;
+  const int lp = ceil_div(l, 16) * 16;
+  b.ldp = (int64_t)round_up((size_t)m, 16);
+  b.at = a.take<char>((size_t)lp * b.ldp * md.es);
+  b.tn = plan_tn(m, k, l, md.dt, d.cus);
+  b.part = a.take<char>(b.tn.part_elems * md.es);
+  return b;
+}
+
+struct SweepBufs {
+  SweepShape sh;
+  u64* xbuf;
+};
+SweepBufs plan_hals(Arena& a, int64_t m, int64_t n, int l, int k, const Mode& md, const Dev& d) {
+  SweepBufs b;
+  b.sh = plan_sweep(m, n, l, k, md.dt, d);
+  b.xbuf = a.take<u64>(sweep_ws_words(b.sh, l));
+  return b;
+}
+
+struct RelBufs {
+  double* part;
+  int np;
+};
+RelBufs plan_rel(Arena& a, int64_t m, int64_t n) {
+  RelBufs b;
+  b.np = relerr_parts(m, n);
+  b.part = a.take<double>((size_t)2 * b.np);
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Orchestration
+// ---------------------------------------------------------------------------
+
+// One Cholesky QR pass: out = in * L^{-T} where L = chol(in^T in).
+rnmf_status qr_pass(const void* in, int64_t rows, int l, void* out, const QrBufs& qb, const Mode& md, int extra,
+                    unsigned* ctl, int allow_shift, unsigned* status, const Dev& d) {
+  hipStream_t s = d.stream;
+  const int lp = ceil_div(l, 16) * 16;
+  HIPCHK(launch_gram(in, md.dt, rows, l, qb.gpart, qb.gsplits, qb.G, s));
+  HIPCHK(launch_chol(qb.G, l, rows, qb.rinv, lp, md.gdt, ctl, extra ? 2 : 0, allow_shift, status, s));
+  XPlan pl = plan_nn(rows, l, l, md.gdt, d.cus);
+  pl.splits = 1;
+  HIPCHK(launch_nn(in, md.gdt, rows, l, l, qb.rinv, lp, l, out, nullptr, pl, status, 0, s));
+  return RNMF_OK;
+}
+
+// Thin QR by Cholesky QR2 (plus a leading shifted pass if needed).  `in` is
+// overwritten.  Result in `out`.
+rnmf_status cholqr(void* in, int64_t rows, int l, void* out, void* tmp, const QrBufs& qb, const Mode& md,
+                   unsigned* ctl, int allow_shift, unsigned* status, const Dev& d) {
+  HIPCHK(launch_fill_u32(ctl, 1, 0u, d.stream));
+  rnmf_status r;
+  if ((r = qr_pass(in, rows, l, tmp, qb, md, 0, ctl, allow_shift, status, d)) != RNMF_OK) return r;
+  if ((r = qr_pass(tmp, rows, l, in, qb, md, 0, ctl, allow_shift, status, d)) != RNMF_OK) return r;
+  // third pass: a real pass after a shifted one, an exact copy otherwise
+  return qr_pass(in, rows, l, out, qb, md, 1, ctl, allow_shift, status, d);
+}
+
+rnmf_status run_sketch(const void* Xc, int64_t m, int64_t n, int64_t ldx, const void* Omega, const rnmf_opts* o,
+                       void* Q, const SketchBufs& b, const Mode& md, const Hdr& h, int check, const Dev& d) {
+  hipStream_t s = d.stream;
+  const int l = lwidth(o, m, n);
+  const int lp = ceil_div(l, 16) * 16;
+  const int allow_shift = !(o->flags & RNMF_FLAG_NO_SHIFT);
+  const void* om = Omega;
+  if (!om) {
+    HIPCHK(launch_philox(b.om, md.dt, n, l, o->seed, 3u, o->omega_dist, s));
+    om = b.om;
+  }
+  rnmf_status r;
+  // Y = X Omega
+  HIPCHK(launch_pack_t(om, md.dt, n, l, lp, b.ldp, b.at, md.cdt, s));
+  HIPCHK(launch_nn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.y, b.part, b.nn, h.status, check, s));
+  const int q = q_effective(o);
+  for (int it = 0; it < q; ++it) {
+    // Q = qr(Y); Z = X^T Q; Q = qr(Z); Y = X Q
+    if ((r = cholqr(b.y, m, l, b.y2, Q, b.qy, md, h.ctl, allow_shift, h.status, d)) != RNMF_OK) return r;
+    HIPCHK(launch_pack_t(b.y2, md.dt, m, l, lp, b.ldp, b.at, md.cdt, s));
+    HIPCHK(launch_tn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.z, 0, b.part, b.tn, s));
+    if ((r = cholqr(b.z, n, l, b.z2, b.z3, b.qz, md, h.ctl, allow_shift, h.status, d)) != RNMF_OK) return r;
+    HIPCHK(launch_pack_t(b.z2, md.dt, n, l, lp, b.ldp, b.at, md.cdt, s));
+    HIPCHK(launch_nn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.y, b.part, b.nn, h.status, 0, s));
+  }
+  return cholqr(b.y, m, l, Q, b.y2, b.qy, md, h.ctl, allow_shift, h.status, d);
+}
+
+rnmf_status run_compress(const void* Xc, int64_t m, int64_t n, int64_t ldx, const void* Q, int l, void* B,
+                         const CompressBufs& b, const Mode& md, const Dev& d) {
+  const int lp = ceil_div(l, 16) * 16;
+  HIPCHK(launch_pack_t(Q, md.dt, m, l, lp, b.ldp, b.at, md.cdt, d.stream));
+  HIPCHK(launch_tn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, B, 1, b.part, b.tn, d.stream));
+  return RNMF_OK;
+}
+
+// W~ = Q^T W
+rnmf_status run_init_wt(const void* Q, const void* W, int64_t m, int k, int l, void* Wt, const InitBufs& b,
+                        const Mode& md, const Dev& d) {
+  const int lp = ceil_div(l, 16) * 16;
+  HIPCHK(launch_pack_t(Q, md.dt, m, l, lp, b.ldp, b.at, md.dt, d.stream));
+  HIPCHK(launch_tn(W, md.dt, m, k, k, b.at, b.ldp, l, Wt, 1, b.part, b.tn, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status status_from_bits(unsigned bits) {
+  if (bits & ST_TIMEOUT) return fail(RNMF_ERR_DEVICE_TIMEOUT, "a device-wide wait hit its spin limit");
+  if (bits & ST_NONFINITE) return fail(RNMF_ERR_NONFINITE, "X contains NaN or Inf");
+  if (bits & ST_NEGATIVE) return fail(RNMF_ERR_NEGATIVE_INPUT, "X contains a negative entry");
+  if (bits & ST_NOT_SPD) return fail(RNMF_ERR_NOT_SPD, "Cholesky QR broke down");
+  if (bits & ST_NONFINITE_SWEEP) return fail(RNMF_ERR_NONFINITE, "a sweep produced NaN or Inf");
+  return RNMF_OK;
+}
+
+size_t factorize_bytes(int64_t m, int64_t n, const rnmf_opts* o, int xt, const Dev& d, void* base,
+                       void** pQ, void** pB, void** pWt, void** pXb, SketchBufs* sb, CompressBufs* cb, InitBufs* ib,
+                       SweepBufs* wb, RelBufs* rb) {
+  const Mode md = mode_of(o);
+  const int l = lwidth(o, m, n);
+  Arena a(base);
+  a.take<char>(HDR_BYTES);
+  void* Q = a.take<char>((size_t)m * l * md.es);
+  void* B = a.take<char>((size_t)l * n * md.es);
+  void* Wt = a.take<char>((size_t)l * o->k * md.es);
+  void* Xb = nullptr;
+  if (md.cdt == 2 && xt == RNMF_F32) Xb = a.take<bf16_t>((size_t)m * bf16_ld(n));
+  const size_t start = round_up(a.used, 256);
+  size_t mx = 0;
+  char* sub = base ? (char*)base + start : nullptr;
+  { Arena s(sub); SketchBufs t = plan_sketch(s, m, n, l, md, d); if (sb) *sb = t; mx = s.used > mx ? s.used : mx; }
+  { Arena s(sub); CompressBufs t = plan_compress(s, m, n, l, md, d); if (cb) *cb = t; mx = s.used > mx ? s.used : mx; }
+  { Arena s(sub); InitBufs t = plan_init(s, m, o->k, l, md, d); if (ib) *ib = t; mx = s.used > mx ? s.used : mx; }
+  { Arena s(sub); SweepBufs t = plan_hals(s, m, n, l, o->k, md, d); if (wb) *wb = t; mx = s.used > mx ? s.used : mx; }
+  { Arena s(sub); RelBufs t = plan_rel(s, m, n); if (rb) *rb = t; mx = s.used > mx ? s.used : mx; }
+  if (pQ) *pQ = Q;
+  if (pB) *pB = B;
+  if (pWt) *pWt = Wt;
+  if (pXb) *pXb = Xb;
+  return start + mx;
+}
+
+size_t op_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o, int xt, const Dev& d) {
+  const Mode md = mode_of(o);
+  const int l = lwidth(o, m, n);
+  Arena a(nullptr);
+  a.take<char>(HDR_BYTES);
+  switch (op) {
+    case RNMF_OP_SKETCH:
+      if (md.cdt == 2 && xt == RNMF_F32) a.take<bf16_t>((size_t)m * bf16_ld(n));
+      plan_sketch(a, m, n, l, md, d);
+      return a.used;
+    case RNMF_OP_COMPRESS: {
+      int64_t lc = (int64_t)o->k + o->p;
+      if (lc > m) lc = m;
+      if (md.cdt == 2 && xt == RNMF_F32) a.take<bf16_t>((size_t)m * bf16_ld(n));
+      plan_compress(a, m, n, (int)lc, md, d);
+      return a.used;
+    }
+    case RNMF_OP_HALS_STEP:
+      plan_hals(a, m, n, l, o->k, md, d);
+      return a.used;
+    case RNMF_OP_REL_ERROR:
+      plan_rel(a, m, n);
+      return a.used;
+    case RNMF_OP_FACTORIZE:
+      return factorize_bytes(m, n, o, xt, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, nullptr);
+    default:
+      return 0;
+  }
+}
+
+// Resolves the X operand actually streamed (casting to BF16 into ws if needed).
+rnmf_status prepare_x(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const rnmf_opts* o, const Mode& md,
+                      void* xb_slot, const Hdr& h, const Dev& d, const void** Xc, int64_t* ldc, int* check_in_pass) {
+  const int check = (o->flags & RNMF_FLAG_CHECK_INPUT) ? 1 : 0;
+  *check_in_pass = 0;
+  if (md.cdt == 2 && xt == RNMF_F32) {
+    int64_t ldb = bf16_ld(n);
+    HIPCHK(launch_cast_bf16((const float*)X, m, n, ldx, (bf16_t*)xb_slot, ldb, h.status, check, d.stream));
+    *Xc = xb_slot;
+    *ldc = ldb;
+  } else {
+    *Xc = X;
+    *ldc = ldx;
+    *check_in_pass = (md.cdt != 2) ? check : 0;
+  }
+  return RNMF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void rnmf_default_opts(rnmf_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->k = 0;
+  o->p = 20;
+  o->q = 2;
+  o->max_iter = 200;
+  o->tol = 0.0;
+  o->seed = 0;
+  o->prec = RNMF_PREC_F32;
+  o->omega_dist = RNMF_OMEGA_GAUSSIAN;
+  o->gram_mode = RNMF_GRAM_FULL;
+  o->order = RNMF_ORDER_H_FIRST;
+  o->flags = RNMF_FLAG_CHECK_INPUT;
+}
+
+const char* rnmf_status_string(int s) {
+  switch (s) {
+    case RNMF_OK: return "ok";
+    case RNMF_ERR_ARG: return "invalid argument";
+    case RNMF_ERR_SHAPE: return "invalid or unsupported shape";
+    case RNMF_ERR_DTYPE: return "dtype not valid for the precision mode";
+    case RNMF_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case RNMF_ERR_NONFINITE: return "non-finite value";
+    case RNMF_ERR_NEGATIVE_INPUT: return "negative entry in X";
+    case RNMF_ERR_NOT_SPD: return "Cholesky QR breakdown";
+    case RNMF_ERR_HIP: return "HIP runtime error";
+    case RNMF_ERR_DEVICE_TIMEOUT: return "device-wide wait timed out";
+    case RNMF_NOT_CONVERGED: return "iteration cap reached before the tolerance";
+    default: return "unknown status";
+  }
+}
+
+const char* rnmf_last_error(void) { return g_err.c_str(); }
+
+int32_t rnmf_sketch_width(int32_t k, int32_t p, int64_t m, int64_t n) {
+  int64_t l = (int64_t)k + p;
+  if (l > m) l = m;
+  if (l > n) l = n;
+  return (int32_t)l;
+}
+
+size_t rnmf_workspace_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o) {
+  g_err.clear();
+  if (op == RNMF_OP_HALS_STEP) {
+    if (!o) { fail(RNMF_ERR_ARG, "opts is NULL"); return 0; }
+    if (m < 1 || n < 1 || o->k < 1 || o->k > KMAX) { fail(RNMF_ERR_ARG, "bad shape or k for the sweep"); return 0; }
+  } else if (op == RNMF_OP_REL_ERROR) {
+    if (m < 1 || n < 1) { fail(RNMF_ERR_SHAPE, "empty matrix"); return 0; }
+  } else {
+    if (check_opts(o, m, n, op == RNMF_OP_FACTORIZE) != RNMF_OK) return 0;
+  }
+  if (op < RNMF_OP_SKETCH || op > RNMF_OP_REL_ERROR) { fail(RNMF_ERR_ARG, "unknown op %d", op); return 0; }
+  Dev d = default_dev();
+  Dev q;
+  if (get_dev(q, nullptr)) d = q;
+  rnmf_opts tmp;
+  if (!o) { rnmf_default_opts(&tmp); tmp.k = 1; o = &tmp; }
+  // the F32 cast slot is sized whenever the BF16 mode might receive FP32 X
+  return op_bytes(op, m, n, o, RNMF_F32, d);
+}
+
+rnmf_status rnmf_sketch(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const void* Omega,
+                        const rnmf_opts* o, void* Q, int32_t* l_out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rnmf_status r;
+  if ((r = check_opts(o, m, n, false)) != RNMF_OK) return r;
+  if ((r = check_xt(o, xt)) != RNMF_OK) return r;
+  if (!X || !Q) return fail(RNMF_ERR_ARG, "X and Q must be non-NULL");
+  if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  if ((r = check_ws(ws, ws_bytes, op_bytes(RNMF_OP_SKETCH, m, n, o, xt, d))) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  void* xb = (md.cdt == 2 && xt == RNMF_F32) ? (void*)a.take<bf16_t>((size_t)m * bf16_ld(n)) : nullptr;
+  SketchBufs b = plan_sketch(a, m, n, lwidth(o, m, n), md, d);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
+  const void* Xc;
+  int64_t ldc;
+  int check;
+  if ((r = prepare_x(X, xt, m, n, ldx, o, md, xb, h, d, &Xc, &ldc, &check)) != RNMF_OK) return r;
+  if ((r = run_sketch(Xc, m, n, ldc, Omega, o, Q, b, md, h, check, d)) != RNMF_OK) return r;
+  if (l_out) *l_out = lwidth(o, m, n);
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const void* Q, int32_t l,
+                          const rnmf_opts* o, void* B, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rnmf_status r;
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  // only the precision of opts matters here (B = Q^T X for any m x n X,
+  // including n < l); the plan is sized with l itself
+  if (l < 1 || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need 1 <= l <= min(m, %d)", LMAX);
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode %d", o->prec);
+  if ((r = check_xt(o, xt)) != RNMF_OK) return r;
+  if (!X || !Q || !B) return fail(RNMF_ERR_ARG, "X, Q and B must be non-NULL");
+  if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  void* xb = (md.cdt == 2 && xt == RNMF_F32) ? (void*)a.take<bf16_t>((size_t)m * bf16_ld(n)) : nullptr;
+  CompressBufs b = plan_compress(a, m, n, l, md, d);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
+  const void* Xc;
+  int64_t ldc;
+  int check;
+  if ((r = prepare_x(X, xt, m, n, ldx, o, md, xb, h, d, &Xc, &ldc, &check)) != RNMF_OK) return r;
+  (void)check;  // the input scan belongs to the first pass over X (sketch)
+  return run_compress(Xc, m, n, ldc, Q, l, B, b, md, d);
+}
+
+rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
+                           void* Wt, void* H, int32_t nsweeps, const rnmf_opts* o, double* dev_stats, void* ws,
+                           size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!Q || !B || !W || !Wt || !H) return fail(RNMF_ERR_ARG, "Q, B, W, Wt and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (nsweeps < 0) return fail(RNMF_ERR_ARG, "nsweeps < 0");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode");
+  if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  rnmf_opts o2 = *o;
+  o2.k = k;
+  rnmf_status r;
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  SweepBufs b = plan_hals(a, m, n, l, k, md, d);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
+  double* stats = dev_stats ? dev_stats : h.stats;
+  HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, b.xbuf,
+                      stats, h.status, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_rel_error(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const void* W, const void* H,
+                           int32_t k, const rnmf_opts* o, double* out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!X || !W || !H || !out) return fail(RNMF_ERR_ARG, "X, W, H and out must be non-NULL");
+  if (m < 1 || n < 1) return fail(RNMF_ERR_SHAPE, "empty matrix");
+  if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  if (k < 1) return fail(RNMF_ERR_ARG, "k < 1");
+  rnmf_status r;
+  if ((r = check_xt(o, xt)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  RelBufs b = plan_rel(a, m, n);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  HIPCHK(launch_relerr(X, xt, md.dt, m, n, ldx, W, H, k, b.part, b.np, out, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const rnmf_opts* o,
+                           const void* Omega, const void* W0, const void* H0, void* W, void* H, rnmf_report* rep,
+                           void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rnmf_status r;
+  if ((r = check_opts(o, m, n, true)) != RNMF_OK) return r;
+  if ((r = check_xt(o, xt)) != RNMF_OK) return r;
+  if (!X || !W || !H) return fail(RNMF_ERR_ARG, "X, W and H must be non-NULL");
+  if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  const int l = lwidth(o, m, n);
+  const int k = o->k;
+  void *Q, *B, *Wt, *Xb;
+  SketchBufs sb;
+  CompressBufs cb;
+  InitBufs ib;
+  SweepBufs wb;
+  RelBufs rb;
+  size_t need = factorize_bytes(m, n, o, xt, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, nullptr);
+  if ((r = check_ws(ws, ws_bytes, need)) != RNMF_OK) return r;
+  factorize_bytes(m, n, o, xt, d, ws, &Q, &B, &Wt, &Xb, &sb, &cb, &ib, &wb, &rb);
+  Hdr h = header(ws);
+  hipStream_t s = d.stream;
+  HIPCHK(launch_fill_u32((unsigned*)ws, HDR_BYTES / 4, 0u, s));
+  const void* Xc;
+  int64_t ldc;
+  int check;
+  // stage timing with events on the caller's stream
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 4; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+  } guard{ev};
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  HIPCHK(hipEventRecord(ev[0], s));
+  if ((r = prepare_x(X, xt, m, n, ldx, o, md, Xb, h, d, &Xc, &ldc, &check)) != RNMF_OK) return r;
+  if ((r = run_sketch(Xc, m, n, ldc, Omega, o, Q, sb, md, h, check, d)) != RNMF_OK) return r;
+  if ((r = run_compress(Xc, m, n, ldc, Q, l, B, cb, md, d)) != RNMF_OK) return r;
+  if (W0) HIPCHK(hipMemcpyAsync(W, W0, (size_t)m * k * md.es, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(launch_philox(W, md.dt, m, k, o->seed, 4u, 1, s));
+  if (H0) HIPCHK(hipMemcpyAsync(H, H0, (size_t)k * n * md.es, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, 1, s));
+  if ((r = run_init_wt(Q, W, m, k, l, Wt, ib, md, d)) != RNMF_OK) return r;
+  HIPCHK(hipEventRecord(ev[1], s));
+  HIPCHK(launch_sweep(wb.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, o->max_iter, o->tol, o->gram_mode, o->order,
+                      wb.xbuf, h.stats, h.status, s));
+  HIPCHK(hipEventRecord(ev[2], s));
+  HIPCHK(launch_relerr(X, xt, md.dt, m, n, ldx, W, H, k, rb.part, rb.np, h.rel, s));
+  HIPCHK(hipEventRecord(ev[3], s));
+  unsigned char host[256];
+  HIPCHK(hipMemcpyAsync(host, ws, sizeof(host), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  unsigned bits;
+  double stats[3], rel[2];
+  std::memcpy(&bits, host, 4);
+  std::memcpy(stats, host + 64, sizeof(stats));
+  std::memcpy(rel, host + 128, sizeof(rel));
+  rnmf_status st = status_from_bits(bits);
+  const int iters = (int)stats[0];
+  const double ratio = stats[1] > 0 ? stats[2] / stats[1] : 0.0;
+  if (st == RNMF_OK && o->tol > 0.0 && iters >= o->max_iter && !(ratio < o->tol)) st = RNMF_NOT_CONVERGED;
+  if (rep) {
+    rep->iters = iters;
+    rep->l_eff = l;
+    rep->q_eff = q_effective(o);
+    rep->qr_path = (bits & ST_SHIFTED) ? 1 : 0;
+    rep->status = st;
+    rep->reserved = 0;
+    rep->rel_err = rel[1] > 0 ? std::sqrt(rel[0] / rel[1]) : 0.0;
+    rep->pg_ratio = ratio;
+    float ms[3] = {0.f, 0.f, 0.f};
+    for (int i = 0; i < 3; ++i)
+      if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) ms[i] = -1.f;
+    rep->ms_qb = ms[0];
+    rep->ms_sweeps = ms[1];
+    rep->ms_error = ms[2];
+  }
+  return st;
+}
+
+rnmf_status rnmf_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, void* Xb, void* stream) {
+  g_err.clear();
+  if (!X || !Xb) return fail(RNMF_ERR_ARG, "X and Xb must be non-NULL");
+  if (m < 1 || n < 1 || ldx < n) return fail(RNMF_ERR_SHAPE, "bad shape");
+  if ((uintptr_t)Xb % 8) return fail(RNMF_ERR_ARG, "Xb must be 8-byte aligned");
+  // packed output (ld = n); the kernel writes 4-element groups, so an odd
+  // tail is handled element by element
+  HIPCHK(launch_cast_bf16(X, m, n, ldx, (bf16_t*)Xb, n, nullptr, 0, (hipStream_t)stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_read_status(void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!ws || ws_bytes < HDR_BYTES) return fail(RNMF_ERR_WORKSPACE, "workspace missing or too small");
+  unsigned bits = 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(&bits, ws, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(launch_fill_u32((unsigned*)ws, 1, 0u, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return status_from_bits(bits);
+}
+
+}  // extern "C"

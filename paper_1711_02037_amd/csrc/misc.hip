@@ -1,0 +1,312 @@
+// Small kernels: fills, the Philox test-matrix generator, the BF16 cast and
+// input scan, and the relative reconstruction error.
+#include "rnmf_common.h"
+
+namespace rnmf {
+
+// ---------------------------------------------------------------------------
+// Fill (used instead of hipMemsetAsync so that captured graphs replay safely)
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(unsigned* p, size_t count, unsigned v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC 2011): counter = (index lo, index hi, stream id, tag),
+// key = seed.  Uniform [0,1) from 53 bits; normal by Box-Muller (one normal
+// per counter, the cosine branch).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
+  const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const unsigned W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    unsigned hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    unsigned hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+constexpr unsigned PHILOX_TAG = 0x524E4D46u;
+
+__device__ __forceinline__ double u53(unsigned lo, unsigned hi) {
+  u64 v = ((u64)hi << 21) ^ (u64)(lo >> 11);
+  return (double)v * (1.0 / 9007199254740992.0);
+}
+
+template <typename T>
+__global__ void philox_kernel(T* out, int64_t count, unsigned k0, unsigned k1, unsigned sid, int dist) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) {
+    unsigned c[4] = {(unsigned)(uint64_t)i, (unsigned)((uint64_t)i >> 32), sid, PHILOX_TAG};
+    philox4x32_10(c, k0, k1);
+    double v;
+    if (dist == 0) {
+      double u1 = u53(c[0], c[1]) + (1.0 / 9007199254740992.0);  // (0, 1]
+      double u2 = u53(c[2], c[3]);
+      v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+    } else {
+      v = u53(c[0], c[1]);
+    }
+    out[i] = (T)v;
+  }
+}
+
+hipError_t launch_philox(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed,
+                         unsigned sid, int dist, hipStream_t s) {
+  int64_t count = rows * cols;
+  if (count == 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  unsigned k0 = (unsigned)seed, k1 = (unsigned)(seed >> 32);
+  if (dt == 0)
+    hipLaunchKernelGGL(philox_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (double*)out, count, k0, k1, sid, dist);
+  else
+    hipLaunchKernelGGL(philox_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (float*)out, count, k0, k1, sid, dist);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP32 -> BF16 cast (round to nearest even), with the NaN/Inf/negative scan.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bf16_t f32_to_bf16_rne(float f) {
+  unsigned b = __float_as_uint(f);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (bf16_t)((b >> 16) | 0x40u);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (bf16_t)(b >> 16);
+}
+
+__device__ __forceinline__ unsigned scan_bits(float v) {
+  unsigned f = 0;
+  if (!(v == v) || fabsf(v) == INFINITY) f |= ST_NONFINITE;
+  else if (v < 0.0f) f |= ST_NEGATIVE;
+  return f;
+}
+__device__ __forceinline__ unsigned scan_bits(double v) {
+  unsigned f = 0;
+  if (!(v == v) || fabs(v) == INFINITY) f |= ST_NONFINITE;
+  else if (v < 0.0) f |= ST_NEGATIVE;
+  return f;
+}
+
+__device__ __forceinline__ void or_status(unsigned* status, unsigned f) {
+  // reduce over the wavefront first so that at most one atomic per wave is issued
+  unsigned long long any = __ballot(f != 0);
+  if (any) {
+    unsigned acc = f;
+    for (int o = 32; o > 0; o >>= 1) acc |= __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) atomicOr(status, acc);
+  }
+}
+
+__global__ void cast_bf16_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                 bf16_t* __restrict__ Xb, int64_t ldb, unsigned* status, int check) {
+  // one row-chunk of 4 elements per thread; pad columns [n, ldb) are zeroed
+  const int64_t qpr = (ldb + 3) / 4;  // quads per row of the destination
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned flag = 0;
+  for (; i < m * qpr; i += stride) {
+    int64_t r = i / qpr, c0 = (i - r * qpr) * 4;
+    const float* src = X + r * ldx;
+    bf16_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int64_t c = c0 + e;
+      float v = c < n ? src[c] : 0.0f;
+      if (check) flag |= scan_bits(v);
+      o[e] = f32_to_bf16_rne(v);
+    }
+    bf16_t* dst = Xb + r * ldb + c0;
+    if (c0 + 4 <= ldb && ((uintptr_t)dst & 7u) == 0) {
+      uint2 w;
+      w.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+      w.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+      *(uint2*)dst = w;
+    } else {
+      for (int e = 0; c0 + e < ldb; ++e) dst[e] = o[e];
+    }
+  }
+  if (check) or_status(status, flag);
+}
+
+hipError_t launch_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, bf16_t* Xb,
+                            int64_t ldb, unsigned* status, int check, hipStream_t s) {
+  int64_t work = m * ((ldb + 3) / 4);
+  if (work == 0) return hipSuccess;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(cast_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, m, n, ldx, Xb,
+                     ldb, status, check);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void check_kernel(const T* __restrict__ X, int64_t m, int64_t n, int64_t ldx, unsigned* status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned flag = 0;
+  for (; i < m * n; i += stride) {
+    int64_t r = i / n, c = i - r * n;
+    flag |= scan_bits(X[r * ldx + c]);
+  }
+  or_status(status, flag);
+}
+
+hipError_t launch_check_input(const void* X, int dt, int64_t m, int64_t n, int64_t ldx,
+                              unsigned* status, hipStream_t s) {
+  int64_t work = m * n;
+  if (work == 0) return hipSuccess;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (dt == 0)
+    hipLaunchKernelGGL(check_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double*)X, m, n, ldx, status);
+  else
+    hipLaunchKernelGGL(check_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)X, m, n, ldx, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Relative error: per 64 x 64 tile of X, D = W H by register-blocked FMA
+// (each thread a 4 x 4 block), E = X - D, and sums of E^2 and X^2 in FP64.
+// One pair of partial sums per workgroup; a single workgroup then adds the
+// partials in index order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+template <typename XT> __device__ __forceinline__ double ld_x(const XT* p) { return (double)*p; }
+template <> __device__ __forceinline__ double ld_x<bf16_t>(const bf16_t* p) {
+  return (double)__uint_as_float(((unsigned)*p) << 16);
+}
+
+template <typename T, typename XT>
+__global__ __launch_bounds__(256) void relerr_kernel(const XT* __restrict__ X, int64_t m, int64_t n,
+                                                     int64_t ldx, const T* __restrict__ W,
+                                                     const T* __restrict__ H, int k,
+                                                     double* __restrict__ part) {
+  constexpr int KC = 16;
+  __shared__ T Ws[KC][64 + 1];
+  __shared__ T Hs[KC][64 + 1];
+  __shared__ double red[2][256];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+  for (int k0 = 0; k0 < k; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * 64; e += 256) {
+      int kk = e / 64, rr = e % 64;
+      int64_t r = r0 + rr;
+      Ws[kk][rr] = (r < m && k0 + kk < k) ? W[r * k + k0 + kk] : (T)0;
+      int64_t c = c0 + rr;
+      Hs[kk][rr] = (c < n && k0 + kk < k) ? H[(int64_t)(k0 + kk) * n + c] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      T wa[4], hb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) wa[a] = Ws[kk][ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) hb[b] = Hs[kk][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(wa[a], hb[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double se = 0.0, sx = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int64_t r = r0 + ty + 16 * a;
+    if (r >= m) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t c = c0 + tx + 16 * b;
+      if (c >= n) continue;
+      double x = ld_x<XT>(X + r * ldx + c);
+      T xt = (T)x;
+      T e = xt - acc[a][b];
+      se += (double)e * (double)e;
+      sx += x * x;
+    }
+  }
+  red[0][threadIdx.x] = se;
+  red[1][threadIdx.x] = sx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = red[0][0];
+    part[2 * b + 1] = red[1][0];
+  }
+}
+
+__global__ __launch_bounds__(1024) void sum_pairs_kernel(const double* __restrict__ part, int np,
+                                                         double* __restrict__ out) {
+  __shared__ double red[2][1024];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < np; i += 1024) { a += part[2 * i]; b += part[2 * i + 1]; }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
+}
+
+int relerr_parts(int64_t m, int64_t n) { return ceil_div(m, 64) * ceil_div(n, 64); }
+
+hipError_t launch_relerr(const void* X, int xt, int dt, int64_t m, int64_t n, int64_t ldx,
+                         const void* W, const void* H, int k, double* part, int nparts_max,
+                         double* out, hipStream_t s) {
+  int gx = ceil_div(n, 64), gy = ceil_div(m, 64);
+  if ((int64_t)gx * gy > nparts_max || gy > 65535) return hipErrorInvalidValue;
+  dim3 grid(gx, gy);
+  if (dt == 0) {
+    hipLaunchKernelGGL((relerr_kernel<double, double>), grid, dim3(256), 0, s, (const double*)X, m,
+                       n, ldx, (const double*)W, (const double*)H, k, part);
+  } else if (xt == 2) {
+    hipLaunchKernelGGL((relerr_kernel<float, bf16_t>), grid, dim3(256), 0, s, (const bf16_t*)X, m,
+                       n, ldx, (const float*)W, (const float*)H, k, part);
+  } else {
+    hipLaunchKernelGGL((relerr_kernel<float, float>), grid, dim3(256), 0, s, (const float*)X, m, n,
+                       ldx, (const float*)W, (const float*)H, k, part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, part, gx * gy, out);
+  return hipGetLastError();
+}
+
+}  // namespace rnmf

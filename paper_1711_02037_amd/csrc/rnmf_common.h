@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP translation units of librnmf.
+// Every kernel is launched through a host wrapper defined in the same file as
+// the kernel, so the library needs no relocatable device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace rnmf {
+
+typedef unsigned long long u64;
+typedef uint16_t bf16_t;  // raw bfloat16 bits
+
+// Device status word bits (first 4 bytes of every workspace).
+enum : unsigned {
+  ST_NONFINITE = 1u << 0,
+  ST_NEGATIVE = 1u << 1,
+  ST_NOT_SPD = 1u << 2,
+  ST_SHIFTED = 1u << 3,      // informational: a shifted Cholesky QR pass ran
+  ST_TIMEOUT = 1u << 4,
+  ST_NONFINITE_SWEEP = 1u << 5,
+};
+
+constexpr int LMAX = 128;  // largest sketch width the kernels support
+constexpr int KMAX = 64;   // largest rank the sweep kernel supports
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// counts bytes, so the same planning code sizes and carves the workspace.
+struct Arena {
+  char* base;
+  size_t used;
+  explicit Arena(void* b) : base((char*)b), used(0) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = round_up(used, 256);
+    used = off + round_up(count * sizeof(T), 256);
+    return base ? (T*)(base + off) : (T*)nullptr;
+  }
+};
+
+struct Dev {
+  hipStream_t stream;
+  int cus;        // compute units
+  int max_lds;    // bytes of LDS per workgroup
+};
+
+// ---------------------------------------------------------------------------
+// Host launch wrappers (each returns hipSuccess or the launch error)
+// ---------------------------------------------------------------------------
+
+// misc.hip
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s);
+hipError_t launch_philox(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed,
+                         unsigned stream_id, int dist, hipStream_t s);
+hipError_t launch_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, bf16_t* Xb,
+                            int64_t ldb, unsigned* status, int check, hipStream_t s);
+hipError_t launch_check_input(const void* X, int dt, int64_t m, int64_t n, int64_t ldx,
+                              unsigned* status, hipStream_t s);
+// relerr partial sums; `part` holds 2 doubles per workgroup; `out` 2 doubles
+hipError_t launch_relerr(const void* X, int xt, int dt, int64_t m, int64_t n, int64_t ldx,
+                         const void* W, const void* H, int k, double* part, int nparts_max,
+                         double* out, hipStream_t s);
+int relerr_parts(int64_t m, int64_t n);
+
+// xpass.hip: passes over X.
+// Small operand packing: src (rows x cols, ld = cols, dtype dt) -> dst, the
+// transpose (lp x ldp, ldp >= rows) in the compute dtype; rows i >= cols are
+// zero.  For bf16 the destination holds hi then lo planes.
+hipError_t launch_pack_t(const void* src, int dt, int64_t rows, int cols, int lp, int64_t ldp,
+                         void* dst, int cdt, hipStream_t s);
+// Y (m x l) = X (m x n) * A, with At = A^T packed (lp x ldat).  Output in dt
+// (float or double).  Split-K partials in `part` (float or double) if needed.
+struct XPlan {
+  int splits;
+  size_t part_elems;
+};
+XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus);
+XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus);
+hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* At,
+                     int64_t ldat, int l, void* Y, void* part, const XPlan& pl,
+                     unsigned* status, int check, hipStream_t s);
+// Z = X^T Q: writes Z (n x l) if !transposed, else Z^T (l x n).
+hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt,
+                     int64_t ldqt, int l, void* Z, int transposed, void* part,
+                     const XPlan& pl, hipStream_t s);
+
+// qr.hip: Cholesky QR pass pieces.
+int gram_splits(int64_t rows, int cus);
+hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart, int splits,
+                       double* G, hipStream_t s);
+// One workgroup: Cholesky of G (l x l, FP64) with optional shift; writes the
+// transposed inverse factor packed for the GEMM (lp x lp, dtype cdt) and
+// updates flags.  `pass_ctl`: 0 first pass of a pair, 1 second pass, 2 extra.
+hipError_t launch_chol(double* G, int l, int64_t rows, void* RinvT, int lp, int cdt,
+                       unsigned* ctl, int pass, int allow_shift, unsigned* status,
+                       hipStream_t s);
+
+// sweep.hip
+struct SweepShape {
+  int G, GR, GC, rows_per, cols_per, rows_lds, cb, nt, red2_elems;
+  size_t lds_bytes;
+};
+SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d);
+size_t sweep_ws_words(const SweepShape& sh, int l);
+hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void* B, void* W,
+                        void* Wt, void* H, int64_t m, int64_t n, int l, int k, int nsweeps,
+                        double tol, int gram_mode, int order, u64* xbuf, double* stats,
+                        unsigned* status, hipStream_t s);
+
+}  // namespace rnmf

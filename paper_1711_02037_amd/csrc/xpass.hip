@@ -1,0 +1,841 @@
+// Passes over the data matrix X (m x n, row-major, leading dimension ldx):
+//   NN:  Y = X A        (sketch X Omega and power half-step X Q; Sec. 2.3)
+//   TN:  Z = X^T Q      (power half-step X^T Q and, transposed, B = Q^T X)
+// The small operand (A or Q, at most 128 columns) is pre-packed transposed so
+// that every MFMA operand fragment is a contiguous run along the reduction
+// index.  Each workgroup streams a disjoint block of X exactly once; split
+// reductions write partials that a second kernel adds in fixed order, so
+// results are deterministic.
+//
+// Matrix-core forms (gfx950):
+//   FP32: v_mfma_f32_16x16x4_f32, lane (i, g) = (lane % 16, lane / 16) holds
+//         A[i][g] and B[g][i]; D[4g + e][i] in element e.
+//   BF16: v_mfma_f32_16x16x32_bf16, lane (i, g) holds A[i][8g..8g+7] and
+//         B[8g..8g+7][i]; same D layout.  X is bfloat16 and the small operand
+//         is split into hi + lo bfloat16 planes (two MFMAs per tile), so only
+//         X is rounded.
+//   FP64: vector FMA, register-blocked through LDS.
+#include "rnmf_common.h"
+
+namespace rnmf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma_bf(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned scan_f32(float v) {
+  unsigned f = 0;
+  if (!(v == v) || fabsf(v) == INFINITY) f |= ST_NONFINITE;
+  else if (v < 0.0f) f |= ST_NEGATIVE;
+  return f;
+}
+
+template <int VW> struct fvec;
+template <> struct fvec<1> { typedef float t; };
+template <> struct fvec<2> { typedef floatx2 t; };
+template <> struct fvec<4> { typedef floatx4 t; };
+
+template <int VW>
+__device__ __forceinline__ typename fvec<VW>::t ldv(const float* p) {
+  return *(const typename fvec<VW>::t*)p;
+}
+template <int VW>
+__device__ __forceinline__ float el(const typename fvec<VW>::t& v, int s) {
+  if constexpr (VW == 1) return v;
+  else return v[s];
+}
+template <int VW>
+__device__ __forceinline__ typename fvec<VW>::t ldv_guard(const float* p, int64_t idx, int64_t end) {
+  typename fvec<VW>::t r;
+  if constexpr (VW == 1) {
+    r = idx < end ? p[0] : 0.0f;
+  } else {
+#pragma unroll
+    for (int s = 0; s < VW; ++s) r[s] = (idx + s < end) ? p[s] : 0.0f;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Packing of the small operand: dst[i][r] = src[r][i] (i < cols), 0 for
+// cols <= i < lp or rows <= r < ldp.  For bf16 the hi plane is followed by the
+// lo plane: hi = bf16(x), lo = bf16(x - hi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (unsigned short)(b >> 16);
+}
+
+template <typename ST, typename DT>
+__global__ __launch_bounds__(256) void pack_t_kernel(const ST* __restrict__ src, int64_t rows, int cols,
+                                                     int lp, int64_t ldp, DT* __restrict__ dst) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    int64_t r = r0 + yy;
+    int i = i0 + tx;
+    tile[yy][tx] = (r < rows && i < cols) ? (double)src[r * cols + i] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int i = i0 + yy;
+    int64_t r = r0 + tx;
+    if (i < lp && r < ldp) dst[(int64_t)i * ldp + r] = (DT)tile[tx][yy];
+  }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void pack_t_bf16_kernel(const ST* __restrict__ src, int64_t rows, int cols,
+                                                          int lp, int64_t ldp, unsigned short* __restrict__ dst) {
+  __shared__ float tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    int64_t r = r0 + yy;
+    int i = i0 + tx;
+    tile[yy][tx] = (r < rows && i < cols) ? (float)src[r * cols + i] : 0.0f;
+  }
+  __syncthreads();
+  unsigned short* lo = dst + (int64_t)lp * ldp;
+  for (int yy = ty; yy < 32; yy += 8) {
+    int i = i0 + yy;
+    int64_t r = r0 + tx;
+    if (i < lp && r < ldp) {
+      float x = tile[tx][yy];
+      unsigned short h = bf16_rne(x);
+      float hf = __uint_as_float(((unsigned)h) << 16);
+      dst[(int64_t)i * ldp + r] = h;
+      lo[(int64_t)i * ldp + r] = bf16_rne(x - hf);
+    }
+  }
+}
+
+hipError_t launch_pack_t(const void* src, int dt, int64_t rows, int cols, int lp, int64_t ldp,
+                         void* dst, int cdt, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(ldp, 32), (unsigned)ceil_div(lp, 32));
+  if (cdt == 2) {
+    if (dt == 0)
+      hipLaunchKernelGGL(pack_t_bf16_kernel<double>, grid, dim3(256), 0, s, (const double*)src, rows,
+                         cols, lp, ldp, (unsigned short*)dst);
+    else
+      hipLaunchKernelGGL(pack_t_bf16_kernel<float>, grid, dim3(256), 0, s, (const float*)src, rows,
+                         cols, lp, ldp, (unsigned short*)dst);
+  } else if (cdt == 1) {
+    if (dt == 0)
+      hipLaunchKernelGGL((pack_t_kernel<double, float>), grid, dim3(256), 0, s, (const double*)src,
+                         rows, cols, lp, ldp, (float*)dst);
+    else
+      hipLaunchKernelGGL((pack_t_kernel<float, float>), grid, dim3(256), 0, s, (const float*)src,
+                         rows, cols, lp, ldp, (float*)dst);
+  } else {
+    if (dt == 0)
+      hipLaunchKernelGGL((pack_t_kernel<double, double>), grid, dim3(256), 0, s, (const double*)src,
+                         rows, cols, lp, ldp, (double*)dst);
+    else
+      hipLaunchKernelGGL((pack_t_kernel<float, double>), grid, dim3(256), 0, s, (const float*)src,
+                         rows, cols, lp, ldp, (double*)dst);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// NN, FP32 matrix cores.  Workgroup: 4 waves x (16 * RW) rows, all lp = 16 NT
+// columns; grid.y splits the reduction over n.
+// ---------------------------------------------------------------------------
+template <int NT, int VW, int RW>
+__global__ __launch_bounds__(256) void nn_f32_kernel(const float* __restrict__ X, int64_t m, int64_t n,
+                                                     int64_t ldx, const float* __restrict__ At, int64_t ldat,
+                                                     int l, float* __restrict__ Y, float* __restrict__ part,
+                                                     int64_t klen, unsigned* status, int check) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t row_base = (int64_t)blockIdx.x * (64 * RW) + wave * (16 * RW);
+  const int64_t kb = (int64_t)blockIdx.y * klen;
+  const int64_t ke = (kb + klen < n) ? kb + klen : n;
+  constexpr int KS = 4 * VW;
+  floatx4 acc[RW][NT];
+#pragma unroll
+  for (int a = 0; a < RW; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float* xr[RW];
+  bool rv[RW];
+#pragma unroll
+  for (int rt = 0; rt < RW; ++rt) {
+    int64_t r = row_base + rt * 16 + i;
+    rv[rt] = r < m;
+    xr[rt] = X + (rv[rt] ? r : (m - 1)) * ldx + VW * g;
+  }
+  const float* ar[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) ar[ct] = At + (int64_t)(ct * 16 + i) * ldat + VW * g;
+  unsigned flag = 0;
+  int64_t k0 = kb;
+  for (; k0 + KS <= ke; k0 += KS) {
+    typename fvec<VW>::t xa[RW], av[NT];
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt) xa[rt] = ldv<VW>(xr[rt] + k0);
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) av[ct] = ldv<VW>(ar[ct] + k0);
+    if (check) {
+#pragma unroll
+      for (int rt = 0; rt < RW; ++rt)
+        if (rv[rt])
+#pragma unroll
+          for (int s = 0; s < VW; ++s) flag |= scan_f32(el<VW>(xa[rt], s));
+    }
+#pragma unroll
+    for (int s = 0; s < VW; ++s)
+#pragma unroll
+      for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = mfma4(el<VW>(xa[rt], s), el<VW>(av[ct], s), acc[rt][ct]);
+  }
+  if (k0 < ke) {
+    const int64_t kk = k0 + VW * g;
+    typename fvec<VW>::t xa[RW], av[NT];
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt) xa[rt] = ldv_guard<VW>(xr[rt] + k0, kk, ke);
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) av[ct] = ldv_guard<VW>(ar[ct] + k0, kk, ke);
+    if (check) {
+#pragma unroll
+      for (int rt = 0; rt < RW; ++rt)
+        if (rv[rt])
+#pragma unroll
+          for (int s = 0; s < VW; ++s) flag |= scan_f32(el<VW>(xa[rt], s));
+    }
+#pragma unroll
+    for (int s = 0; s < VW; ++s)
+#pragma unroll
+      for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = mfma4(el<VW>(xa[rt], s), el<VW>(av[ct], s), acc[rt][ct]);
+  }
+  if (check && __ballot(flag != 0)) {
+    for (int o = 32; o > 0; o >>= 1) flag |= __shfl_xor(flag, o);
+    if (lane == 0 && flag) atomicOr(status, flag);
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t r = row_base + rt * 16 + 4 * g + e;
+        int c = ct * 16 + i;
+        if (r < m && c < l) {
+          if (part) part[((int64_t)blockIdx.y * m + r) * lp + c] = acc[rt][ct][e];
+          else Y[r * l + c] = acc[rt][ct][e];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// NN, BF16 matrix cores (X bfloat16 with ldx % 8 == 0; At hi and lo planes).
+// ---------------------------------------------------------------------------
+template <int NT, int RW>
+__global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__ X, int64_t m, int64_t n,
+                                                      int64_t ldx, const bf16_t* __restrict__ At, int64_t ldat,
+                                                      int lp_all, int l, float* __restrict__ Y,
+                                                      float* __restrict__ part, int64_t klen) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t row_base = (int64_t)blockIdx.x * (64 * RW) + wave * (16 * RW);
+  const int64_t kb = (int64_t)blockIdx.y * klen;
+  const int64_t ke = (kb + klen < n) ? kb + klen : n;
+  floatx4 acc[RW][NT];
+#pragma unroll
+  for (int a = 0; a < RW; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16_t* xr[RW];
+#pragma unroll
+  for (int rt = 0; rt < RW; ++rt) {
+    int64_t r = row_base + rt * 16 + i;
+    xr[rt] = X + (r < m ? r : (m - 1)) * ldx + 8 * g;
+  }
+  const bf16_t* ah[NT];
+  const int64_t plane = (int64_t)lp_all * ldat;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) ah[ct] = At + (int64_t)(ct * 16 + i) * ldat + 8 * g;
+  int64_t k0 = kb;
+  for (; k0 + 32 <= ke; k0 += 32) {
+    bf16x8 xa[RW], hv[NT], lv[NT];
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt) xa[rt] = *(const bf16x8*)(xr[rt] + k0);
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      hv[ct] = *(const bf16x8*)(ah[ct] + k0);
+      lv[ct] = *(const bf16x8*)(ah[ct] + plane + k0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
+        acc[rt][ct] = mfma_bf(xa[rt], lv[ct], acc[rt][ct]);
+      }
+  }
+  if (k0 < ke) {
+    const int64_t kk = k0 + 8 * g;
+    bf16x8 xa[RW], hv[NT], lv[NT];
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        unsigned short v = (kk + s < ke) ? xr[rt][k0 + s] : (unsigned short)0;
+        xa[rt][s] = __builtin_bit_cast(__bf16, v);
+      }
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        unsigned short h = (kk + s < ke) ? ah[ct][k0 + s] : (unsigned short)0;
+        unsigned short lo = (kk + s < ke) ? ah[ct][plane + k0 + s] : (unsigned short)0;
+        hv[ct][s] = __builtin_bit_cast(__bf16, h);
+        lv[ct][s] = __builtin_bit_cast(__bf16, lo);
+      }
+#pragma unroll
+    for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
+        acc[rt][ct] = mfma_bf(xa[rt], lv[ct], acc[rt][ct]);
+      }
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int rt = 0; rt < RW; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t r = row_base + rt * 16 + 4 * g + e;
+        int c = ct * 16 + i;
+        if (r < m && c < l) {
+          if (part) part[((int64_t)blockIdx.y * m + r) * lp + c] = acc[rt][ct][e];
+          else Y[r * l + c] = acc[rt][ct][e];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// TN, FP32 matrix cores.  Each wave owns 16 * VW columns of X; lane (i, g)
+// loads rows m0 + 4g + s (s < 4) x VW columns; MFMA (s, c) uses row 4g + s
+// and column VW * i + c, paired with Qt rows t * 16 + i at m0 + 4g + s.
+// ---------------------------------------------------------------------------
+template <int NT, int VW>
+__global__ __launch_bounds__(256) void tn_f32_kernel(const float* __restrict__ X, int64_t m, int64_t n,
+                                                     int64_t ldx, const float* __restrict__ Qt, int64_t ldqt,
+                                                     float* __restrict__ part, int64_t mlen) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t col0 = (int64_t)blockIdx.x * (64 * VW) + wave * (16 * VW) + VW * i;
+  const int64_t mb = (int64_t)blockIdx.y * mlen;
+  const int64_t me = (mb + mlen < m) ? mb + mlen : m;
+  floatx4 acc[NT][VW];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < VW; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bool cfull = col0 + VW <= n;
+  const bool cany = col0 < n;
+  const float* xc = X + (cany ? col0 : 0);
+  const float* qr[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) qr[t] = Qt + (int64_t)(t * 16 + i) * ldqt + 4 * g;
+  int64_t m0 = mb;
+  for (; m0 + 16 <= me; m0 += 16) {
+    typename fvec<VW>::t xv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float* p = xc + (m0 + 4 * g + s) * ldx;
+      xv[s] = cfull ? ldv<VW>(p) : ldv_guard<VW>(p, col0, cany ? n : col0);
+    }
+    floatx4 qa[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) qa[t] = *(const floatx4*)(qr[t] + m0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) acc[t][c] = mfma4(qa[t][s], el<VW>(xv[s], c), acc[t][c]);
+  }
+  if (m0 < me) {
+    typename fvec<VW>::t xv[4];
+    floatx4 qa[NT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int64_t r = m0 + 4 * g + s;
+      if (r < me) {
+        const float* p = xc + r * ldx;
+        xv[s] = cfull ? ldv<VW>(p) : ldv_guard<VW>(p, col0, cany ? n : col0);
+      } else {
+        xv[s] = ldv_guard<VW>(xc, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) qa[t][s] = (r < me) ? qr[t][m0 + s] : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) acc[t][c] = mfma4(qa[t][s], el<VW>(xv[s], c), acc[t][c]);
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) {
+      int64_t col = col0 + c;
+      if (col < n) {
+        float* dst = part + ((int64_t)blockIdx.y * n + col) * lp + t * 16 + 4 * g;
+        *(floatx4*)dst = acc[t][c];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TN, BF16 matrix cores (X bfloat16 with ldx % 4 == 0).  Lane (i, g) loads
+// rows m0 + 8g + s (s < 8) x 4 columns (8 bytes each) and regroups them in
+// registers into four B fragments (8 consecutive rows of one column each).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(256) void tn_bf16_kernel(const bf16_t* __restrict__ X, int64_t m, int64_t n,
+                                                      int64_t ldx, const bf16_t* __restrict__ Qt, int64_t ldqt,
+                                                      int lp_all, float* __restrict__ part, int64_t mlen) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + wave * 64 + 4 * i;
+  const int64_t mb = (int64_t)blockIdx.y * mlen;
+  const int64_t me = (mb + mlen < m) ? mb + mlen : m;
+  floatx4 acc[NT][4];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bool cfull = col0 + 4 <= n;
+  const bf16_t* xc = X + (col0 < n ? col0 : 0);
+  const int64_t plane = (int64_t)lp_all * ldqt;
+  const bf16_t* qr[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) qr[t] = Qt + (int64_t)(t * 16 + i) * ldqt + 8 * g;
+  for (int64_t m0 = mb; m0 < me; m0 += 32) {
+    const bool full = (m0 + 32 <= me) && cfull;
+    ushort4_t xv[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      int64_t r = m0 + 8 * g + s;
+      if (full) {
+        xv[s] = *(const ushort4_t*)(xc + r * ldx);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          xv[s][c] = (r < me && col0 + c < n) ? xc[r * ldx + c] : (unsigned short)0;
+      }
+    }
+    bf16x8 b[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) b[c][s] = __builtin_bit_cast(__bf16, (unsigned short)xv[s][c]);
+    bf16x8 hv[NT], lv[NT];
+    if (m0 + 32 <= me) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        hv[t] = *(const bf16x8*)(qr[t] + m0);
+        lv[t] = *(const bf16x8*)(qr[t] + plane + m0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          bool ok = m0 + 8 * g + s < me;
+          hv[t][s] = __builtin_bit_cast(__bf16, ok ? qr[t][m0 + s] : (unsigned short)0);
+          lv[t][s] = __builtin_bit_cast(__bf16, ok ? qr[t][plane + m0 + s] : (unsigned short)0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[t][c] = mfma_bf(hv[t], b[c], acc[t][c]);
+        acc[t][c] = mfma_bf(lv[t], b[c], acc[t][c]);
+      }
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int64_t col = col0 + c;
+      if (col < n) {
+        float* dst = part + ((int64_t)blockIdx.y * n + col) * lp + t * 16 + 4 * g;
+        *(floatx4*)dst = acc[t][c];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector-FMA forms (FP64, and bfloat16 X without 16-byte row alignment).
+// NN: workgroup = 64 rows x lp columns, 16-wide reduction chunks in LDS.
+// ---------------------------------------------------------------------------
+template <typename XT> __device__ __forceinline__ float to_f(XT v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f<bf16_t>(bf16_t v) { return __uint_as_float(((unsigned)v) << 16); }
+
+template <typename XT, typename CT, typename AT, int NT>
+__global__ __launch_bounds__(256) void nn_valu_kernel(const XT* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                      const AT* __restrict__ At, int64_t ldat, int lp_all, int l,
+                                                      CT* __restrict__ Y, CT* __restrict__ part, int64_t klen,
+                                                      unsigned* status, int check) {
+  constexpr int KC = 16;
+  __shared__ CT Xs[64][KC + 1];
+  __shared__ CT As[KC][NT * 16 + 1];
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t kb = (int64_t)blockIdx.y * klen;
+  const int64_t ke = (kb + klen < n) ? kb + klen : n;
+  CT acc[4][NT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = (CT)0;
+  unsigned flag = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+    for (int e = threadIdx.x; e < 64 * KC; e += 256) {
+      int rr = e / KC, kk = e % KC;
+      int64_t r = r0 + rr, k = k0 + kk;
+      CT v = (CT)0;
+      if (r < m && k < ke) {
+        if constexpr (sizeof(XT) == 2) v = (CT)to_f<XT>(X[r * ldx + k]);
+        else v = (CT)X[r * ldx + k];
+        if (check) {
+          double d = (double)v;
+          if (!(d == d) || fabs(d) == INFINITY) flag |= ST_NONFINITE;
+          else if (d < 0.0) flag |= ST_NEGATIVE;
+        }
+      }
+      Xs[rr][kk] = v;
+    }
+    for (int e = threadIdx.x; e < KC * NT * 16; e += 256) {
+      int kk = e / (NT * 16), c = e % (NT * 16);
+      int64_t k = k0 + kk;
+      CT v = (CT)0;
+      if (k < ke) {
+        if constexpr (sizeof(AT) == 2) {
+          const bf16_t* ah = (const bf16_t*)At;
+          v = (CT)to_f<bf16_t>(ah[(int64_t)c * ldat + k]) +
+              (CT)to_f<bf16_t>(ah[(int64_t)lp_all * ldat + (int64_t)c * ldat + k]);
+        } else {
+          v = (CT)At[(int64_t)c * ldat + k];
+        }
+      }
+      As[kk][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KC; ++kk) {
+      CT xa[4], av[NT];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xa[a] = Xs[tr * 4 + a][kk];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) av[b] = As[kk][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = fma(xa[a], av[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  if (check && flag) atomicOr(status, flag);
+  const int lp = NT * 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int64_t r = r0 + tr * 4 + a;
+    if (r >= m) continue;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      int c = tc + 16 * b;
+      if (c >= l) continue;
+      if (part) part[((int64_t)blockIdx.y * m + r) * lp + c] = acc[a][b];
+      else Y[r * l + c] = acc[a][b];
+    }
+  }
+}
+
+// TN: workgroup = 64 columns of X x lp, over a split of the rows.
+template <typename XT, typename CT, typename AT, int NT>
+__global__ __launch_bounds__(256) void tn_valu_kernel(const XT* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                      const AT* __restrict__ Qt, int64_t ldqt, int lp_all,
+                                                      CT* __restrict__ part, int64_t mlen) {
+  constexpr int KC = 16;
+  __shared__ CT Xs[KC][64 + 1];
+  __shared__ CT Qs[KC][NT * 16 + 1];
+  const int tcol = threadIdx.x >> 4, ta = threadIdx.x & 15;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int64_t mb = (int64_t)blockIdx.y * mlen;
+  const int64_t me = (mb + mlen < m) ? mb + mlen : m;
+  CT acc[4][NT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = (CT)0;
+  for (int64_t m0 = mb; m0 < me; m0 += KC) {
+    for (int e = threadIdx.x; e < KC * 64; e += 256) {
+      int rr = e / 64, cc = e % 64;
+      int64_t r = m0 + rr, c = c0 + cc;
+      CT v = (CT)0;
+      if (r < me && c < n) {
+        if constexpr (sizeof(XT) == 2) v = (CT)to_f<XT>(X[r * ldx + c]);
+        else v = (CT)X[r * ldx + c];
+      }
+      Xs[rr][cc] = v;
+    }
+    for (int e = threadIdx.x; e < KC * NT * 16; e += 256) {
+      int rr = e / (NT * 16), a = e % (NT * 16);
+      int64_t r = m0 + rr;
+      CT v = (CT)0;
+      if (r < me) {
+        if constexpr (sizeof(AT) == 2) {
+          const bf16_t* qh = (const bf16_t*)Qt;
+          v = (CT)to_f<bf16_t>(qh[(int64_t)a * ldqt + r]) +
+              (CT)to_f<bf16_t>(qh[(int64_t)lp_all * ldqt + (int64_t)a * ldqt + r]);
+        } else {
+          v = (CT)Qt[(int64_t)a * ldqt + r];
+        }
+      }
+      Qs[rr][a] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < KC; ++rr) {
+      CT xa[4], qv[NT];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xa[a] = Xs[rr][tcol * 4 + a];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) qv[b] = Qs[rr][ta + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = fma(xa[a], qv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int64_t c = c0 + tcol * 4 + a;
+    if (c >= n) continue;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) part[((int64_t)blockIdx.y * n + c) * lp + ta + 16 * b] = acc[a][b];
+  }
+}
+
+// Fixed-order sum of split partials: out = sum_s part[s] (rows x l), written
+// row-major (rows x l) or transposed (l x rows).
+template <typename CT, typename OT>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const CT* __restrict__ part, int splits, int64_t rows,
+                                                           int l, int lp, OT* __restrict__ out, int transposed) {
+  const int64_t total = rows * l;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r, c;
+    if (transposed) { c = e / rows; r = e - c * rows; }   // coalesced stores along rows
+    else { r = e / l; c = e - r * l; }
+    CT s = (CT)0;
+    for (int p = 0; p < splits; ++p) s += part[((int64_t)p * rows + r) * lp + c];
+    if (transposed) out[c * rows + r] = (OT)s;
+    else out[r * l + c] = (OT)s;
+  }
+}
+
+template <typename CT, typename OT>
+static hipError_t launch_reduce(const CT* part, int splits, int64_t rows, int l, int lp, OT* out, int tr,
+                                hipStream_t s) {
+  int64_t total = rows * l;
+  if (total == 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((reduce_parts_kernel<CT, OT>), dim3((unsigned)blocks), dim3(256), 0, s, part, splits,
+                     rows, l, lp, out, tr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Planning and dispatch
+// ---------------------------------------------------------------------------
+static int vec_width(const void* X, int64_t ldx, int esize) {
+  uintptr_t a = (uintptr_t)X;
+  if (ldx % 4 == 0 && a % (4 * esize) == 0) return 4;
+  if (ldx % 2 == 0 && a % (2 * esize) == 0) return 2;
+  return 1;
+}
+
+XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus) {
+  XPlan p;
+  const int lp = ceil_div(l, 16) * 16;
+  const int rows_wg = (cdt == 0) ? 64 : 128;
+  const int wg_m = ceil_div(m, rows_wg);
+  int target = 2 * cus;
+  int splits = wg_m >= target ? 1 : ceil_div(target, wg_m);
+  int maxs = (int)(n / 256);
+  if (maxs < 1) maxs = 1;
+  if (splits > maxs) splits = maxs;
+  if (splits > 64) splits = 64;
+  p.splits = splits;
+  p.part_elems = splits > 1 ? (size_t)splits * (size_t)m * (size_t)lp : 0;
+  return p;
+}
+
+XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus) {
+  XPlan p;
+  const int lp = ceil_div(l, 16) * 16;
+  const int wg_n = ceil_div(n, 256);
+  int target = 2 * cus;
+  int splits = ceil_div(target, wg_n);
+  int maxs = (int)(m / 64);
+  if (maxs < 1) maxs = 1;
+  if (splits > maxs) splits = maxs;
+  if (splits > 512) splits = 512;
+  if (splits < 1) splits = 1;
+  p.splits = splits;
+  p.part_elems = (size_t)splits * (size_t)n * (size_t)lp;
+  return p;
+}
+
+#define NT_SWITCH(NTV, CALL)        \
+  switch (NTV) {                    \
+    case 1: { constexpr int NT = 1; CALL; } break; \
+    case 2: { constexpr int NT = 2; CALL; } break; \
+    case 3: { constexpr int NT = 3; CALL; } break; \
+    case 4: { constexpr int NT = 4; CALL; } break; \
+    case 5: { constexpr int NT = 5; CALL; } break; \
+    case 6: { constexpr int NT = 6; CALL; } break; \
+    case 7: { constexpr int NT = 7; CALL; } break; \
+    default: { constexpr int NT = 8; CALL; } break; \
+  }
+
+hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* At, int64_t ldat,
+                     int l, void* Y, void* part, const XPlan& pl, unsigned* status, int check, hipStream_t s) {
+  const int ntile = ceil_div(l, 16);
+  const int lp = ntile * 16;
+  const int splits = pl.splits;
+  if (cdt == 1) {
+    const int64_t klen = round_up((size_t)ceil_div(n, splits), 16);
+    const int rs = ceil_div(n, klen);
+    dim3 grid((unsigned)ceil_div(m, 128), (unsigned)rs);
+    float* pp = rs > 1 ? (float*)part : nullptr;
+    int vw = vec_width(X, ldx, 4);
+    if (vw == 4) {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 4, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+    } else if (vw == 2) {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 2, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+    } else {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 1, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || rs == 1) return e;
+    return launch_reduce<float, float>((const float*)part, rs, m, l, lp, (float*)Y, 0, s);
+  }
+  if (cdt == 2) {
+    const int64_t klen = round_up((size_t)ceil_div(n, splits), 32);
+    const int rs = ceil_div(n, klen);
+    dim3 grid((unsigned)ceil_div(m, 128), (unsigned)rs);
+    float* pp = rs > 1 ? (float*)part : nullptr;
+    if (ldx % 8 == 0 && ((uintptr_t)X % 16) == 0) {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((nn_bf16_kernel<NT, 2>), grid, dim3(256), 0, s, (const bf16_t*)X, m, n,
+                                          ldx, (const bf16_t*)At, ldat, lp, l, (float*)Y, pp, klen));
+    } else {
+      dim3 g2((unsigned)ceil_div(m, 64), (unsigned)rs);
+      NT_SWITCH(ntile, hipLaunchKernelGGL((nn_valu_kernel<bf16_t, float, bf16_t, NT>), g2, dim3(256), 0, s,
+                                          (const bf16_t*)X, m, n, ldx, (const bf16_t*)At, ldat, lp, l, (float*)Y,
+                                          pp, klen, status, 0));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || rs == 1) return e;
+    return launch_reduce<float, float>((const float*)part, rs, m, l, lp, (float*)Y, 0, s);
+  }
+  // FP64
+  const int64_t klen = round_up((size_t)ceil_div(n, splits), 16);
+  const int rs = ceil_div(n, klen);
+  dim3 grid((unsigned)ceil_div(m, 64), (unsigned)rs);
+  double* pp = rs > 1 ? (double*)part : nullptr;
+  NT_SWITCH(ntile, hipLaunchKernelGGL((nn_valu_kernel<double, double, double, NT>), grid, dim3(256), 0, s,
+                                      (const double*)X, m, n, ldx, (const double*)At, ldat, lp, l, (double*)Y,
+                                      pp, klen, status, check));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || rs == 1) return e;
+  return launch_reduce<double, double>((const double*)part, rs, m, l, lp, (double*)Y, 0, s);
+}
+
+hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt, int64_t ldqt,
+                     int l, void* Z, int transposed, void* part, const XPlan& pl, hipStream_t s) {
+  const int ntile = ceil_div(l, 16);
+  const int lp = ntile * 16;
+  const int splits = pl.splits;
+  if (cdt == 1) {
+    const int64_t mlen = round_up((size_t)ceil_div(m, splits), 16);
+    const int rs = ceil_div(m, mlen);
+    int vw = vec_width(X, ldx, 4);
+    dim3 grid((unsigned)ceil_div(n, 64 * vw), (unsigned)rs);
+    if (vw == 4) {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((tn_f32_kernel<NT, 4>), grid, dim3(256), 0, s, (const float*)X, m, n, ldx,
+                                          (const float*)Qt, ldqt, (float*)part, mlen));
+    } else if (vw == 2) {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((tn_f32_kernel<NT, 2>), grid, dim3(256), 0, s, (const float*)X, m, n, ldx,
+                                          (const float*)Qt, ldqt, (float*)part, mlen));
+    } else {
+      NT_SWITCH(ntile, hipLaunchKernelGGL((tn_f32_kernel<NT, 1>), grid, dim3(256), 0, s, (const float*)X, m, n, ldx,
+                                          (const float*)Qt, ldqt, (float*)part, mlen));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce<float, float>((const float*)part, rs, n, l, lp, (float*)Z, transposed, s);
+  }
+  if (cdt == 2) {
+    const int64_t mlen = round_up((size_t)ceil_div(m, splits), 32);
+    const int rs = ceil_div(m, mlen);
+    if (ldx % 4 == 0 && ((uintptr_t)X % 8) == 0) {
+      dim3 grid((unsigned)ceil_div(n, 256), (unsigned)rs);
+      NT_SWITCH(ntile, hipLaunchKernelGGL((tn_bf16_kernel<NT>), grid, dim3(256), 0, s, (const bf16_t*)X, m, n, ldx,
+                                          (const bf16_t*)Qt, ldqt, lp, (float*)part, mlen));
+    } else {
+      dim3 grid((unsigned)ceil_div(n, 64), (unsigned)rs);
+      NT_SWITCH(ntile, hipLaunchKernelGGL((tn_valu_kernel<bf16_t, float, bf16_t, NT>), grid, dim3(256), 0, s,
+                                          (const bf16_t*)X, m, n, ldx, (const bf16_t*)Qt, ldqt, lp, (float*)part,
+                                          mlen));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce<float, float>((const float*)part, rs, n, l, lp, (float*)Z, transposed, s);
+  }
+  const int64_t mlen = round_up((size_t)ceil_div(m, splits), 16);
+  const int rs = ceil_div(m, mlen);
+  dim3 grid((unsigned)ceil_div(n, 64), (unsigned)rs);
+  NT_SWITCH(ntile, hipLaunchKernelGGL((tn_valu_kernel<double, double, double, NT>), grid, dim3(256), 0, s,
+                                      (const double*)X, m, n, ldx, (const double*)Qt, ldqt, lp, (double*)part, mlen));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce<double, double>((const double*)part, rs, n, l, lp, (double*)Z, transposed, s);
+}
+
+}  // namespace rnmf

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/rnmf.h declares, sizes workspaces, validates arguments
+before touching a device, and maps a missing device to RNMF_ERR_HIP."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1711_02037_amd as rn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rnmf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rnmf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rn.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert sorted(rn.EXPORTS) == names
+
+
+def test_status_strings_and_defaults():
+    for s in range(11):
+        assert rn.status_string(s)
+    assert rn.status_string(99) == "unknown status"
+    o = rn.Opts()
+    rn.lib().rnmf_default_opts(ctypes.byref(o))
+    assert (o.p, o.q, o.max_iter, o.prec, o.gram_mode, o.order) == (20, 2, 200, 1, 0, 0)
+    assert o.flags & rn.FLAG_CHECK_INPUT
+
+
+def test_sketch_width_clamps():
+    assert rn.sketch_width(50, 20, 100000, 5000) == 70
+    assert rn.sketch_width(10, 20, 500, 25) == 25
+    assert rn.sketch_width(10, 20, 18, 400) == 18
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16"])
+def test_workspace_sizes_grow_with_the_problem(prec):
+    o = rn.make_opts(16, 20, 2, precision=prec)
+    small = rn.workspace_bytes(rn.OP_FACTORIZE, 2000, 500, o)
+    big = rn.workspace_bytes(rn.OP_FACTORIZE, 32256, 2410, o)
+    assert 0 < small < big
+    for op in (rn.OP_SKETCH, rn.OP_COMPRESS, rn.OP_HALS_STEP, rn.OP_REL_ERROR):
+        assert 0 < rn.workspace_bytes(op, 32256, 2410, o) <= big
+    assert big % 1 == 0
+
+
+def test_workspace_query_rejects_bad_arguments():
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_FACTORIZE, 100, 50, rn.make_opts(50, 20, 2))      # k >= min(m, n)
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_FACTORIZE, 100000, 5000, rn.make_opts(100, 50, 2))  # l > 128
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_FACTORIZE, 1000, 500, rn.make_opts(80, 20, 2))    # k > 64
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(9, 100, 50, rn.make_opts(5, 5, 2))
+
+
+def _call_factorize(o, m=100, n=80, ldx=80, xt=rn.F32, ws=ctypes.c_void_p(256), wsb=1 << 40):
+    L = rn.lib()
+    rep = rn.Report()
+    p = ctypes.c_void_p(4096)
+    return L.rnmf_factorize(p, xt, m, n, ldx, ctypes.byref(o), None, None, None, p, p, ctypes.byref(rep),
+                            ws, wsb, None)
+
+
+def test_arguments_are_checked_before_any_device_work():
+    L = rn.lib()
+    o = rn.make_opts(10, 5, 1)
+    assert _call_factorize(o, ldx=79) == rn.ERR_SHAPE
+    assert _call_factorize(o, xt=rn.F64) == rn.ERR_DTYPE
+    assert _call_factorize(rn.make_opts(10, 5, 1, precision="fp64"), xt=rn.F32) == rn.ERR_DTYPE
+    assert _call_factorize(rn.make_opts(100, 5, 1)) == rn.ERR_ARG
+    assert _call_factorize(o, m=0) == rn.ERR_SHAPE
+    bad = rn.make_opts(10, 5, 1)
+    bad.reserved = 1
+    assert _call_factorize(bad) == rn.ERR_ARG
+    bad = rn.make_opts(10, 5, 1)
+    bad.flags = 0x80
+    assert _call_factorize(bad) == rn.ERR_ARG
+    assert b"flag" in L.rnmf_last_error()
+    bad = rn.make_opts(10, 5, 1)
+    bad.tol = float("nan")
+    assert _call_factorize(bad) == rn.ERR_ARG
+    assert L.rnmf_factorize(None, rn.F32, 100, 80, 80, ctypes.byref(o), None, None, None, None, None, None,
+                            None, 0, None) == rn.ERR_ARG
+
+
+def test_missing_device_is_a_hip_error_not_a_crash():
+    # On a host without a GPU the library must fail cleanly.
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    o = rn.make_opts(10, 5, 1)
+    assert _call_factorize(o) == rn.ERR_HIP
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    assert L.rnmf_hals_step(p, p, 100, 80, 15, 10, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_HIP
+    assert L.rnmf_cast_bf16(p, 10, 10, 10, p, None) in (rn.ERR_HIP, rn.OK)
+
+
+def test_hals_step_validation():
+    L = rn.lib()
+    o = rn.make_opts(10, 5, 1)
+    p = ctypes.c_void_p(4096)
+    assert L.rnmf_hals_step(p, p, 100, 80, 15, 65, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_ARG
+    assert L.rnmf_hals_step(p, p, 100, 80, 200, 10, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_SHAPE
+    assert L.rnmf_hals_step(p, p, 100, 80, 15, 10, p, p, p, -1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_ARG
+    assert L.rnmf_hals_step(None, p, 100, 80, 15, 10, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_ARG
