@@ -87,6 +87,7 @@ enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
 #define RNMF_FLAG_CHECK_INPUT 0x1u      /* scan X for NaN/Inf/negative values  */
 #define RNMF_FLAG_NO_SHIFT 0x2u         /* no shifted Cholesky QR fallback     */
 #define RNMF_FLAG_EXACT_Q 0x4u          /* BF16: do not add one power iteration */
+#define RNMF_FLAG_TRACE 0x8u            /* rnmf_hals_step: record phase timestamps */
 
 typedef struct rnmf_opts {
   int32_t k;          /* target rank, 1 <= k < min(m, n)                        */
@@ -173,7 +174,11 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
  * stop once ||grad^P f||^2 on Q B falls below tol times its value at entry
  * (Sec. 3.3).  dev_stats (device, optional): 4 doubles = {sweeps done,
  * ||grad^P||^2 at entry, at exit, status word}.  Requires k <= 64 and
- * l <= 128.  Asynchronous. */
+ * l <= 128.  With RNMF_FLAG_TRACE, workgroup 0 writes 10 + 2k timestamps of
+ * the device's 100 MHz real-time counter for the first sweep (entry, Q slab
+ * loaded, prologue, H phase, T/V exchange, each W column before and after its
+ * exchange, W phase, local S, S exchange, sweep end, kernel end) as uint64 at
+ * byte offset 1024 of ws.  Asynchronous. */
 rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
                            int32_t l, int32_t k, void* W, void* Wt, void* H,
                            int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,

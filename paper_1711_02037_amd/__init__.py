@@ -32,7 +32,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 GRAM = {"full": 0, "lowdim": 1, "mixed": 2}
 ORDER = {"h_first": 0, "w_first": 1}
 OMEGA = {"gaussian": 0, "uniform": 1}
-FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q = 0x1, 0x2, 0x4
+FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE = 0x1, 0x2, 0x4, 0x8
 OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR = range(5)
 
 EXPORTS = [
@@ -245,9 +245,11 @@ def compress(X, Q, precision="fp32", ws=None):
     return B
 
 
-def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, ws=None):
+def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, ws=None,
+              trace=False):
     """nsweeps compressed HALS sweeps in place on W, Wt, H (rnmf_hals_step).
-    Returns (sweeps done, pg^2 at entry, pg^2 at exit)."""
+    Returns (sweeps done, pg^2 at entry, pg^2 at exit), plus the list of phase
+    timestamps in microseconds when trace is set."""
     torch = _torch()
     for t, nm in ((Q, "Q"), (B, "B"), (W, "W"), (Wt, "Wt"), (H, "H")):
         _need_dev(t, nm); _packed(t, nm)
@@ -255,6 +257,8 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
     k, n = H.shape
     prec = precision or ("fp64" if Q.dtype == torch.float64 else "fp32")
     o = make_opts(k, l - k, 0, tol=tol, precision=prec, gram=gram, order=order)
+    if trace:
+        o.flags |= FLAG_TRACE
     nb = workspace_bytes(OP_HALS_STEP, m, n, o)
     keep, w = ws if ws is not None else _workspace(nb, Q.device)
     stats = torch.zeros(4, dtype=torch.float64, device=Q.device)
@@ -262,6 +266,10 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
                                 ctypes.byref(o), _ptr(stats), _ptr(w), w.numel(), _stream(Q.device)))
     s = stats.cpu().tolist()
     _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(Q.device)))
+    if trace:
+        ts = w[1024:1024 + 8 * (13 + 2 * k)].cpu().view(torch.int64).tolist()
+        t0 = ts[0]
+        return int(s[0]), s[1], s[2], [(x - t0) / 100.0 if x else None for x in ts]
     return int(s[0]), s[1], s[2]
 
 

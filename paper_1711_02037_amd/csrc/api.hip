@@ -36,6 +36,7 @@ rnmf_status fail(rnmf_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t HDR_BYTES = 4096;
+constexpr size_t TRACE_OFFSET = 1024;  // phase timestamps of a traced sweep
 // header layout (bytes): 0 status u32, 4 QR control u32, 64 stats (8 doubles),
 // 128 relative-error sums (2 doubles)
 struct Hdr {
@@ -115,7 +116,7 @@ rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax)
   if (o->omega_dist < 0 || o->omega_dist > 1) return fail(RNMF_ERR_ARG, "unknown omega_dist %d", o->omega_dist);
   if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode %d", o->gram_mode);
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order %d", o->order);
-  if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q))
+  if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q | RNMF_FLAG_TRACE))
     return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
   if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
   int l = lwidth(o, m, n);
@@ -229,9 +230,9 @@ struct SweepBufs {
   SweepShape sh;
   u64* xbuf;
 };
-SweepBufs plan_hals(Arena& a, int64_t m, int64_t n, int l, int k, const Mode& md, const Dev& d) {
+SweepBufs plan_hals(Arena& a, int64_t m, int64_t n, int l, int k, const Mode& md, const Dev& d, bool need_pg) {
   SweepBufs b;
-  b.sh = plan_sweep(m, n, l, k, md.dt, d);
+  b.sh = plan_sweep(m, n, l, k, md.dt, d, need_pg);
   b.xbuf = a.take<u64>(sweep_ws_words(b.sh, l));
   return b;
 }
@@ -348,7 +349,7 @@ size_t factorize_bytes(int64_t m, int64_t n, const rnmf_opts* o, int xt, const D
   { Arena s(sub); SketchBufs t = plan_sketch(s, m, n, l, md, d); if (sb) *sb = t; mx = s.used > mx ? s.used : mx; }
   { Arena s(sub); CompressBufs t = plan_compress(s, m, n, l, md, d); if (cb) *cb = t; mx = s.used > mx ? s.used : mx; }
   { Arena s(sub); InitBufs t = plan_init(s, m, o->k, l, md, d); if (ib) *ib = t; mx = s.used > mx ? s.used : mx; }
-  { Arena s(sub); SweepBufs t = plan_hals(s, m, n, l, o->k, md, d); if (wb) *wb = t; mx = s.used > mx ? s.used : mx; }
+  { Arena s(sub); SweepBufs t = plan_hals(s, m, n, l, o->k, md, d, o->tol > 0.0); if (wb) *wb = t; mx = s.used > mx ? s.used : mx; }
   { Arena s(sub); RelBufs t = plan_rel(s, m, n); if (rb) *rb = t; mx = s.used > mx ? s.used : mx; }
   if (pQ) *pQ = Q;
   if (pB) *pB = B;
@@ -375,7 +376,7 @@ size_t op_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o, int xt, const 
       return a.used;
     }
     case RNMF_OP_HALS_STEP:
-      plan_hals(a, m, n, l, o->k, md, d);
+      plan_hals(a, m, n, l, o->k, md, d, o->tol > 0.0);
       return a.used;
     case RNMF_OP_REL_ERROR:
       plan_rel(a, m, n);
@@ -554,13 +555,18 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   rnmf_status r;
   Arena a(ws);
   a.take<char>(HDR_BYTES);
-  SweepBufs b = plan_hals(a, m, n, l, k, md, d);
+  SweepBufs b = plan_hals(a, m, n, l, k, md, d, o->tol > 0.0);
   if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
   Hdr h = header(ws);
   HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
   double* stats = dev_stats ? dev_stats : h.stats;
+  u64* trace = nullptr;
+  if (o->flags & RNMF_FLAG_TRACE) {
+    trace = (u64*)((char*)ws + TRACE_OFFSET);
+    HIPCHK(launch_fill_u32((unsigned*)trace, (HDR_BYTES - TRACE_OFFSET) / 4, 0u, d.stream));
+  }
   HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, b.xbuf,
-                      stats, h.status, d.stream));
+                      stats, h.status, trace, d.stream));
   return RNMF_OK;
 }
 
@@ -633,7 +639,7 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   if ((r = run_init_wt(Q, W, m, k, l, Wt, ib, md, d)) != RNMF_OK) return r;
   HIPCHK(hipEventRecord(ev[1], s));
   HIPCHK(launch_sweep(wb.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, o->max_iter, o->tol, o->gram_mode, o->order,
-                      wb.xbuf, h.stats, h.status, s));
+                      wb.xbuf, h.stats, h.status, nullptr, s));
   HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_relerr(X, xt, md.dt, m, n, ldx, W, H, k, rb.part, rb.np, h.rel, s));
   HIPCHK(hipEventRecord(ev[3], s));

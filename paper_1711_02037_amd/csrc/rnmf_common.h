@@ -102,14 +102,14 @@ hipError_t launch_chol(double* G, int l, int64_t rows, void* RinvT, int lp, int 
 
 // sweep.hip
 struct SweepShape {
-  int G, GR, GC, rows_per, cols_per, rows_lds, cb, nt, red2_elems;
+  int G, GR, GC, rows_per, cols_per, rows_lds, cb, nt, red2_elems, alias_sv, regq;
   size_t lds_bytes;
 };
-SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d);
+SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, bool need_pg);
 size_t sweep_ws_words(const SweepShape& sh, int l);
 hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void* B, void* W,
                         void* Wt, void* H, int64_t m, int64_t n, int l, int k, int nsweeps,
                         double tol, int gram_mode, int order, u64* xbuf, double* stats,
-                        unsigned* status, hipStream_t s);
+                        unsigned* status, u64* trace, hipStream_t s);
 
 }  // namespace rnmf

@@ -65,7 +65,9 @@ __device__ __forceinline__ void put(u64* base, int elem, V v, unsigned e) {
 }
 
 // Fixed-order sum over nsrc slots (slot s at base + s * stride) of element
-// `elem`, waiting for epoch e on every word.  All loads are issued first.
+// `elem`, waiting for epoch e on every word.  All loads are issued first, then
+// each source is polled in turn (polling every stale word each round loads the
+// memory system enough to slow the whole device down).
 template <typename V>
 __device__ __forceinline__ V gather_sum(const u64* base, size_t stride, int nsrc, int elem, unsigned e,
                                         bool& ok) {
@@ -94,6 +96,18 @@ __device__ __forceinline__ V gather_sum(const u64* base, size_t stride, int nsrc
   return sum;
 }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// (lgkmcnt) but not for its outstanding global stores, which a full
+// __syncthreads() would drain (vmcnt also counts stores on this architecture).
+// Use __syncthreads() where a thread reads global data another thread of the
+// workgroup wrote.
+__device__ __forceinline__ void lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = 63, expcnt = 7, lgkmcnt = 0
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <typename T>
 struct SweepArgs {
   const T* Q; const T* B; T* W; T* Wt; T* H;
@@ -101,6 +115,8 @@ struct SweepArgs {
   int nsweeps; double tol; int gram_mode, order;
   int G, GR, GC, rows_per, cols_per, rows_lds, lq, cb;
   int red2_elems;
+  int alias_sv;          // S shares V's LDS slot (no projected gradient needed)
+  u64* trace;            // optional phase timestamps (workgroup 0, first sweep)
   u64 *xs_part, *xs_row, *xb_part, *xb_row, *xb_fin;
   size_t lpw, cbw, csw;  // words per slot
   double* stats; unsigned* status;
@@ -114,8 +130,7 @@ struct Xch {
 
 // All-reduce of c <= LPS values of type V held in LDS `vals` (in/out).
 template <typename T, typename V>
-__device__ bool allreduce_small(const SweepArgs<T>& a, Xch& x, V* vals, int c, int* abort_flag) {
-  constexpr int W = Words<V>::n;
+__device__ __forceinline__ bool allreduce_small(const SweepArgs<T>& a, Xch& x, V* vals, int c, int* abort_flag) {
   const int t = threadIdx.x;
   const unsigned e = ++x.seq;
   const unsigned par = (x.small_use++) & 1u;
@@ -132,17 +147,16 @@ __device__ bool allreduce_small(const SweepArgs<T>& a, Xch& x, V* vals, int c, i
       r = gather_sum<V>(RS + (size_t)x.j * slot, (size_t)a.GC * slot, a.GR, t, e, ok);
     }
   }
-  (void)W;
   if (!ok) *abort_flag = 1;
-  __syncthreads();
+  lds_sync();
   if (t < c) vals[t] = r;
-  __syncthreads();
+  lds_sync();
   return *abort_flag == 0;
 }
 
 // All-reduce of c <= cb values of type T held in LDS `vals` (in/out).
 template <typename T>
-__device__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, int* abort_flag) {
+__device__ __forceinline__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, int* abort_flag) {
   const int t = threadIdx.x;
   const unsigned e = ++x.seq;
   const unsigned par = (x.big_use++) & 1u;
@@ -154,7 +168,7 @@ __device__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, int
   u64* FN = a.xb_fin + (size_t)par * a.G * a.csw;
   bool ok = true;
   for (int v = t; v < c; v += NTH) put<T>(P + (size_t)x.g * a.cbw, v, vals[v], e);
-  __syncthreads();
+  lds_sync();
   for (int v = s0 + t; v < s1; v += NTH) {
     T r = gather_sum<T>(P + (size_t)x.i * a.GC * a.cbw, a.cbw, a.GC, v, e, ok);
     if (a.GR > 1) put<T>(RS + (size_t)x.g * a.csw, v - s0, r, e);
@@ -166,12 +180,40 @@ __device__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, int
       put<T>(FN + (size_t)x.g * a.csw, v - s0, r, e);
     }
   }
-  for (int v = t; v < c; v += NTH) {
-    int jj = v / cs;
-    vals[v] = gather_sum<T>(FN + ((size_t)x.i * a.GC + jj) * a.csw, 0, 1, v - jj * cs, e, ok);
+  // all-gather of the slices from the row: PB elements per thread in flight
+  constexpr int W = Words<T>::n;
+  constexpr int PB = 8;
+  for (int v0 = t; v0 < c; v0 += NTH * PB) {
+    u64 w[PB][W];
+    const u64* ad[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int v = v0 + b * NTH;
+      if (v < c) {
+        const int jj = v / cs;
+        ad[b] = FN + ((size_t)x.i * a.GC + jj) * a.csw + (size_t)(v - jj * cs) * W;
+#pragma unroll
+        for (int h = 0; h < W; ++h) w[b][h] = ld_ll(ad[b] + h);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int v = v0 + b * NTH;
+      if (v < c) {
+#pragma unroll
+        for (int h = 0; h < W; ++h) {
+          long spins = 0;
+          while ((unsigned)(w[b][h] >> 32) != e) {
+            if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
+            w[b][h] = ld_ll(ad[b] + h);
+          }
+        }
+        vals[v] = value_of<T>(w[b]);
+      }
+    }
   }
   if (!ok) *abort_flag = 1;
-  __syncthreads();
+  lds_sync();
   return *abort_flag == 0;
 }
 
@@ -189,78 +231,27 @@ __device__ __forceinline__ T readlane(T v, int lane) {
 
 template <typename T> __device__ __forceinline__ T clip0(T x) { return x > (T)0 ? x : (T)0; }
 
-template <typename T>
-__device__ __forceinline__ const T* qrow(const SweepArgs<T>& a, const T* Qs, int r0, int rr) {
-  return rr < a.rows_lds ? Qs + (size_t)rr * a.lq : a.Q + (size_t)(r0 + rr) * a.l;
+// Maps a linear block index to (row block, column block) of the upper block
+// triangle of an nb x nb block matrix, in row-major order.
+__device__ __forceinline__ void upper_block(int b, int nb, int& r, int& c) {
+  int q = 0, rem = b;
+  while (rem >= nb - q) { rem -= nb - q; ++q; }
+  r = q;
+  c = q + rem;
 }
 
-// Local Gram of the workgroup's rows of W (k x k, full), into dst (LDS).
-// Rows are staged in LDS chunks; each thread owns 4 x 4 blocks of the upper
-// block triangle, mirrored on the way out.
-template <typename T>
-__device__ void local_wgram(const SweepArgs<T>& a, int r0, int nr, T* stage, T* dst) {
-  const int k = a.k, t = threadIdx.x;
-  const int kb = (k + 3) / 4;
-  const int nblk = kb * (kb + 1) / 2;  // <= 136 for k <= 64
-  int ba = -1, bb = -1;
-  if (t < nblk) {
-    int q = 0, rem = t;
-    while (rem >= kb - q) { rem -= kb - q; ++q; }
-    ba = q;
-    bb = q + rem;
-  }
-  double acc[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-  constexpr int RC = 32;
-  const int kp = 4 * kb;
-  for (int c0 = 0; c0 < nr; c0 += RC) {
-    __syncthreads();
-    for (int e = t; e < RC * kp; e += NTH) {
-      int rr = e / kp, cc = e % kp;
-      stage[e] = (c0 + rr < nr && cc < k) ? a.W[(size_t)(r0 + c0 + rr) * k + cc] : (T)0;
-    }
-    __syncthreads();
-    if (ba >= 0) {
-      const int rmax = (nr - c0 < RC) ? nr - c0 : RC;
-      for (int rr = 0; rr < rmax; ++rr) {
-        double u[4], w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          u[q] = (double)stage[rr * kp + 4 * ba + q];
-          w[q] = (double)stage[rr * kp + 4 * bb + q];
-        }
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[p * 4 + q] = fma(u[p], w[q], acc[p * 4 + q]);
-      }
-    }
-  }
-  __syncthreads();
-  if (ba >= 0) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int r = 4 * ba + p, c = 4 * bb + q;
-        if (r < k && c < k) {
-          dst[r * k + c] = (T)acc[p * 4 + q];
-          if (ba != bb) dst[c * k + r] = (T)acc[p * 4 + q];
-        }
-      }
-  }
-  __syncthreads();
-}
+// Register-resident Q slab (REGQ): thread (wave w, lane L) owns rows
+// {8w + L/8 + 64 i : i < RQ} and columns {9 (L % 8) + s : s < CQ} of the slab.
+constexpr int RQ = 7, CQ = 9;  // at most 448 rows x 72 columns per workgroup
 
-template <typename T>
+template <typename T, bool REGQ>
 __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
   __shared__ int abort_flag;
   __shared__ double pg_buf[2];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int l = a.l, k = a.k;
+  const int l = a.l, k = a.k, n = a.n;
   const int g = blockIdx.x;
   Xch x;
   x.g = g; x.i = g / a.GC; x.j = g % a.GC; x.seq = 0; x.small_use = 0; x.big_use = 0;
@@ -269,153 +260,529 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   int nr = a.m - r0; if (nr > a.rows_per) nr = a.rows_per; if (nr < 0) nr = 0;
   const int c0 = g * a.cols_per;
   int nc = a.n - c0; if (nc > a.cols_per) nc = a.cols_per; if (nc < 0) nc = 0;
-  const int rows_in_lds = nr < a.rows_lds ? nr : a.rows_lds;
+  const int nrl = nr < a.rows_lds ? nr : a.rows_lds;  // rows whose Q lives in LDS
+  const int lq = a.lq;
 
   // LDS carve-up (red2 first so that it is 8-byte aligned for the FP64 sums)
-  T* red2 = smem;                                 // scratch: backward partials, W staging, pg sums
+  T* red2 = smem;                                 // scratch: backward partials, staging, pg sums
   T* Wts = red2 + a.red2_elems;                   // l x k
   T* U = Wts + (size_t)l * k;                     // [T: l x k | V: k x k | S: k x k]
   T* Tm = U;
   T* Vm = U + (size_t)l * k;
-  T* Sm = Vm + (size_t)k * k;
-  T* vec = Sm + (size_t)k * k;                    // LPS
+  T* Sm = a.alias_sv ? Vm : Vm + (size_t)k * k;   // S and V are never live together without pg
+  T* vec = Vm + (size_t)k * k * (a.alias_sv ? 1 : 2);  // LPS
   T* wcol = vec + LPS;                            // rows_per
   T* Qs = wcol + a.rows_per;                      // rows_lds x lq
 
+  const bool tracer = a.trace && g == 0 && t == 0;
+#define TRACE(idx) \
+  if (tracer) a.trace[(idx)] = __builtin_amdgcn_s_memrealtime();
+  TRACE(0);
   if (t == 0) abort_flag = 0;
-  for (size_t e = t; e < (size_t)rows_in_lds * l; e += NTH) {
-    int rr = (int)(e / l), c = (int)(e % l);
-    Qs[(size_t)rr * a.lq + c] = a.Q[(size_t)(r0 + rr) * l + c];
+  const int ga = wave * 8 + (lane >> 3), gc = lane & 7;  // REGQ row group, column group
+  T qreg[REGQ ? RQ : 1][REGQ ? CQ : 1];
+  if constexpr (REGQ) {
+#pragma unroll
+    for (int i = 0; i < RQ; ++i)
+#pragma unroll
+      for (int s = 0; s < CQ; ++s) {
+        const int rr = ga + 64 * i, aa = gc * CQ + s;
+        qreg[i][s] = (rr < nr && aa < l) ? a.Q[(size_t)(r0 + rr) * l + aa] : (T)0;
+      }
+  } else {
+    for (int e = t; e < nrl * l; e += NTH) {
+      int rr = e / l, c = e - rr * l;
+      Qs[rr * lq + c] = a.Q[(size_t)(r0 + rr) * l + c];
+    }
   }
   for (int e = t; e < l * k; e += NTH) Wts[e] = a.Wt[e];
   __syncthreads();
+  TRACE(1);
+  bool tr_sweep = false;
 
   const bool need_S = (a.gram_mode != 1) || (a.tol > 0.0);
   const bool need_pg = a.tol > 0.0;
   const int RG = (NTH / l < 16) ? NTH / l : 16;
+  const int kb = (k + 3) / 4, lb = (l + 3) / 4;
 
-  // --- building blocks ------------------------------------------------------
-  auto s_exchange = [&]() -> bool {
-    local_wgram<T>(a, r0, nr, red2, Sm);
+  // --- S = W^T W over this workgroup's rows (4 x 4 register blocks) --------
+  // Rows are staged through LDS 32 at a time; the next chunk is loaded into
+  // registers while the current one is used.
+  auto local_wgram = [&]() __attribute__((always_inline)) {
+    __syncthreads();  // W rows written by other threads of this workgroup
+    constexpr int RC = 32, PF = (RC * KMAX + NTH - 1) / NTH;  // staged values per thread
+    const int kp = 4 * kb;
+    const int nblk = kb * (kb + 1) / 2;
+    // NG groups of threads share the rows of a chunk (rows rg, rg + NG, ...)
+    const int NG = (NTH / nblk < 8) ? NTH / nblk : 8;
+    const int tb = t % nblk, rgi = t / nblk;
+    int ba = -1, bb = -1;
+    if (rgi < NG) upper_block(tb, kb, ba, bb);
+    double acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    T pf[PF];
+    auto fetch = [&](int cstart) __attribute__((always_inline)) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = t + q * NTH;
+        const int rr = e / kp, cc = e - (e / kp) * kp;
+        pf[q] = (e < RC * kp && cstart + rr < nr && cc < k) ? a.W[(size_t)(r0 + cstart + rr) * k + cc] : (T)0;
+      }
+    };
+    fetch(0);
+    for (int cs = 0; cs < nr; cs += RC) {
+      lds_sync();
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = t + q * NTH;
+        if (e < RC * kp) red2[e] = pf[q];
+      }
+      lds_sync();
+      if (cs + RC < nr) fetch(cs + RC);
+      if (ba >= 0) {
+        const int rmax = (nr - cs < RC) ? nr - cs : RC;
+        for (int rr = rgi; rr < rmax; rr += NG) {
+          double u[4], w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            u[q] = (double)red2[rr * kp + 4 * ba + q];
+            w[q] = (double)red2[rr * kp + 4 * bb + q];
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p * 4 + q] = fma(u[p], w[q], acc[p * 4 + q]);
+        }
+      }
+    }
+    // fixed-order sum of the NG group partials through LDS (as doubles), in
+    // passes of `cap` blocks so that the staging area bounds the LDS use
+    lds_sync();
+    double* gsum = (double*)red2;
+    const int cap = (int)((size_t)a.red2_elems * sizeof(T) / 8 / 16);
+    for (int b0 = 0; b0 < nblk; b0 += cap) {
+      const bool mine = ba >= 0 && tb >= b0 && tb < b0 + cap;
+      for (int gi = 0; gi < NG; ++gi) {
+        if (rgi == gi && mine) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            if (gi == 0) gsum[(tb - b0) * 16 + e] = acc[e];
+            else gsum[(tb - b0) * 16 + e] += acc[e];
+          }
+        }
+        lds_sync();
+      }
+      if (t >= b0 && t < nblk && t < b0 + cap) {
+        int pa, pb;
+        upper_block(t, kb, pa, pb);
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = 4 * pa + p, c = 4 * pb + q;
+            if (r < k && c < k) {
+              const T v = (T)gsum[(t - b0) * 16 + p * 4 + q];
+              Sm[r * k + c] = v;
+              if (pa != pb) Sm[c * k + r] = v;
+            }
+          }
+      }
+      lds_sync();
+    }
+  };
+
+  auto s_exchange = [&]() __attribute__((always_inline)) -> bool {
+    local_wgram();
+    if (tr_sweep) { TRACE(6 + 2 * k); }
     return allreduce_big<T>(a, x, Sm, k * k, &abort_flag);
   };
 
-  auto tv_exchange = [&]() -> bool {
-    // T = B H^T (l x k) and V = H H^T (k x k) over this workgroup's columns
-    for (int e = t; e < l * k + k * k; e += NTH) {
-      double s = 0.0;
-      if (e < l * k) {
-        int aa = e / k, jj = e % k;
-        const T* brow = a.B + (size_t)aa * a.n + c0;
-        const T* hrow = a.H + (size_t)jj * a.n + c0;
-        for (int c = 0; c < nc; ++c) s = fma((double)brow[c], (double)hrow[c], s);
-      } else {
-        int f = e - l * k, ii = f / k, jj = f % k;
-        const T* h1 = a.H + (size_t)ii * a.n + c0;
-        const T* h2 = a.H + (size_t)jj * a.n + c0;
-        for (int c = 0; c < nc; ++c) s = fma((double)h1[c], (double)h2[c], s);
-      }
-      U[e] = (T)s;
+  // --- T = B H^T and V = H H^T over this workgroup's columns ---------------
+  // 4 x 4 register blocks (FP64 accumulation); B and H columns are staged
+  // through LDS 8 columns at a time.
+  auto tv_exchange = [&]() __attribute__((always_inline)) -> bool {
+    __syncthreads();  // H columns written by other threads of this workgroup
+    constexpr int CW = 8;
+    const int nbt = lb * kb;                 // blocks of T
+    const int nbv = kb * (kb + 1) / 2;       // upper blocks of V
+    T* Bs = red2;                            // l x CW
+    T* Hs = red2 + LMAX * CW;                // k x CW
+    double acc[2][16];
+    int br[2], bc[2], isv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int b = t + q * NTH;
+      isv[q] = -1;
+      if (b < nbt) { br[q] = b / kb; bc[q] = b - (b / kb) * kb; isv[q] = 0; }
+      else if (b < nbt + nbv) { upper_block(b - nbt, kb, br[q], bc[q]); isv[q] = 1; }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[q][e] = 0.0;
     }
-    __syncthreads();
+    for (int cs = 0; cs < nc; cs += CW) {
+      const int w = (nc - cs < CW) ? nc - cs : CW;
+      lds_sync();
+      for (int e = t; e < (l + k) * CW; e += NTH) {
+        const int row = e / CW, cc = e - (e / CW) * CW;
+        if (row < l) Bs[row * CW + cc] = cc < w ? a.B[(size_t)row * n + c0 + cs + cc] : (T)0;
+        else Hs[(row - l) * CW + cc] = cc < w ? a.H[(size_t)(row - l) * n + c0 + cs + cc] : (T)0;
+      }
+      lds_sync();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (isv[q] < 0) continue;
+        const T* left = isv[q] ? Hs : Bs;
+        const int rl = isv[q] ? k : l;
+        for (int cc = 0; cc < w; ++cc) {
+          double u[4], v[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const int r = 4 * br[q] + p, c = 4 * bc[q] + p;
+            u[p] = r < rl ? (double)left[r * CW + cc] : 0.0;
+            v[p] = c < k ? (double)Hs[c * CW + cc] : 0.0;
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[q][p * 4 + s] = fma(u[p], v[s], acc[q][p * 4 + s]);
+        }
+      }
+    }
+    lds_sync();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (isv[q] < 0) continue;
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = 4 * br[q] + p, c = 4 * bc[q] + s;
+          if (c >= k) continue;
+          if (!isv[q]) {
+            if (r < l) Tm[r * k + c] = (T)acc[q][p * 4 + s];
+          } else if (r < k) {
+            Vm[r * k + c] = (T)acc[q][p * 4 + s];
+            if (br[q] != bc[q]) Vm[c * k + r] = (T)acc[q][p * 4 + s];
+          }
+        }
+    }
+    // blocks beyond 2 * NTH (l = 128 and k = 64 need at most 648)
+    for (int b = t + 2 * NTH; b < nbt + nbv; b += NTH) {
+      int rb, cb2, vv = b >= nbt;
+      if (!vv) { rb = b / kb; cb2 = b - (b / kb) * kb; } else upper_block(b - nbt, kb, rb, cb2);
+      for (int p = 0; p < 4; ++p)
+        for (int s = 0; s < 4; ++s) {
+          const int r = 4 * rb + p, c = 4 * cb2 + s;
+          if (c >= k || r >= (vv ? k : l)) continue;
+          double sum = 0.0;
+          for (int cc = 0; cc < nc; ++cc) {
+            const double lv = vv ? (double)a.H[(size_t)r * n + c0 + cc] : (double)a.B[(size_t)r * n + c0 + cc];
+            sum = fma(lv, (double)a.H[(size_t)c * n + c0 + cc], sum);
+          }
+          if (!vv) Tm[r * k + c] = (T)sum;
+          else { Vm[r * k + c] = (T)sum; Vm[c * k + r] = (T)sum; }
+        }
+    }
+    lds_sync();
     return allreduce_big<T>(a, x, U, l * k + k * k, &abort_flag);
   };
 
-  auto h_phase = [&]() {
-    // numerator Gram and scale
+  // --- H phase: this workgroup's columns of H, one wavefront per column -----
+  auto h_phase = [&]() __attribute__((always_inline)) {
     const T* Snum = Sm;
     const T* Ssc = Sm;
     if (a.gram_mode != 0) {
       // W~^T W~ into the T region (T is recomputed after the H phase)
       for (int e = t; e < k * k; e += NTH) {
         int ii = e / k, jj = e % k;
-        T s = (T)0;
-        for (int aa = 0; aa < l; ++aa) s = fma(Wts[aa * k + ii], Wts[aa * k + jj], s);
-        Tm[e] = s;
+        double s = 0.0;
+        for (int aa = 0; aa < l; ++aa) s = fma((double)Wts[aa * k + ii], (double)Wts[aa * k + jj], s);
+        Tm[e] = (T)s;
       }
-      __syncthreads();
+      lds_sync();
       Snum = Tm;
       if (a.gram_mode == 1) Ssc = Tm;
     }
+    // reciprocal scales, computed once per phase (0 marks a skipped row)
+    double* rinv = (double*)red2;
+    if (t < k) {
+      const double d = (double)Ssc[t * k + t];
+      rinv[t] = d > 0.0 ? 1.0 / d : 0.0;
+    }
+    lds_sync();
     // FP64 arithmetic: the update cancels R against H^T S, and S is the Gram
     // of a nonnegative factor, so its rounding is amplified.
     for (int cc = wave; cc < nc; cc += NTH / 64) {
       const int c = c0 + cc;
       const int jj = lane < k ? lane : 0;
-      double R = 0.0;
-      for (int aa = 0; aa < l; ++aa) R = fma((double)a.B[(size_t)aa * a.n + c], (double)Wts[aa * k + jj], R);
-      double h = (double)a.H[(size_t)jj * a.n + c];
-      double gsum = R;
-      for (int ii = 0; ii < k; ++ii) gsum = fma(-(double)Snum[ii * k + jj], readlane<double>(h, ii), gsum);
-      for (int ii = 0; ii < k; ++ii) {
-        const double d = (double)Ssc[ii * k + ii];
-        if (d > 0.0) {
+      // lane holds B(lane, c) and B(lane + 64, c); H(lane, c)
+      const T b0 = lane < l ? a.B[(size_t)lane * n + c] : (T)0;
+      const T b1 = lane + 64 < l ? a.B[(size_t)(lane + 64) * n + c] : (T)0;
+      double h = lane < k ? (double)a.H[(size_t)lane * n + c] : 0.0;
+      double R0 = 0.0, R1 = 0.0;
+      const int l0 = l < 64 ? l : 64;
+      int aa = 0;
+      for (; aa + 2 <= l0; aa += 2) {
+        R0 = fma((double)readlane<T>(b0, aa), (double)Wts[aa * k + jj], R0);
+        R1 = fma((double)readlane<T>(b0, aa + 1), (double)Wts[(aa + 1) * k + jj], R1);
+      }
+      for (; aa < l0; ++aa) R0 = fma((double)readlane<T>(b0, aa), (double)Wts[aa * k + jj], R0);
+      for (aa = 64; aa < l; ++aa) R1 = fma((double)readlane<T>(b1, aa - 64), (double)Wts[aa * k + jj], R1);
+      double g0 = R0 + R1, g1 = 0.0;
+      int ii = 0;
+      for (; ii + 2 <= k; ii += 2) {
+        g0 = fma(-(double)Snum[ii * k + jj], readlane<double>(h, ii), g0);
+        g1 = fma(-(double)Snum[(ii + 1) * k + jj], readlane<double>(h, ii + 1), g1);
+      }
+      for (; ii < k; ++ii) g0 = fma(-(double)Snum[ii * k + jj], readlane<double>(h, ii), g0);
+      double gsum = g0 + g1;
+      for (ii = 0; ii < k; ++ii) {
+        const double rd = rinv[ii];
+        if (rd > 0.0) {
           const double hi = readlane<double>(h, ii);
           const double gi = readlane<double>(gsum, ii);
           // the new row is rounded to the storage type before it is used
-          const double hn = (double)clip0<T>((T)(hi + gi / d));
+          const double hn = (double)clip0<T>((T)fma(gi, rd, hi));
           const double delta = hn - hi;
           if (lane == ii) h = hn;
           gsum = fma(-(double)Snum[ii * k + jj], delta, gsum);
         }
       }
-      if (lane < k) a.H[(size_t)lane * a.n + c] = (T)h;
+      if (lane < k) a.H[(size_t)lane * n + c] = (T)h;
     }
     __syncthreads();
   };
 
-  auto w_phase = [&]() -> bool {
+  // --- W phase: columns of W in order, one device-wide exchange each --------
+  // W phase with the Q slab in registers.  Per column: lift and clip (a
+  // register GEMV reduced over the 8 column-group lanes), the local map-back
+  // (reduced over the 64 row groups: lanes, then waves through LDS), one
+  // device-wide exchange by threads t < l; while it is in flight, threads
+  // t >= 128 prepare the next column's update vector without the column being
+  // exchanged, whose term is added once its value arrives.
+  auto w_phase_reg = [&]() __attribute__((always_inline)) -> bool {
+    T* part = red2;                    // 8 x 72: per-wave map-back partials
+    T* cpart = red2 + 8 * 72;          // 5 x LPS: partial sums for the next update vector
+    auto next_col = [&](int j) __attribute__((always_inline)) -> int {
+      int q = j + 1;
+      while (q < k && !(Vm[q * k + q] > (T)0)) ++q;
+      return q;
+    };
+    int jj = next_col(-1);
+    if (jj >= k) return true;
+    // update vector of the first column: v = W~(:,j) + (T(:,j) - W~ V(:,j)) / V_jj
+    if (t < l) {
+      const T* wr = Wts + t * k;
+      T s0 = Tm[t * k + jj], s1 = (T)0;
+      int ii = 0;
+      for (; ii + 2 <= k; ii += 2) {
+        s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
+        s1 = fma(-wr[ii + 1], Vm[(ii + 1) * k + jj], s1);
+      }
+      for (; ii < k; ++ii) s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
+      vec[t] = Wts[t * k + jj] + (s0 + s1) / Vm[jj * k + jj];
+    }
+    lds_sync();
+    while (jj < k) {
+      // lift and clip: W(r, j) = max(0, Q(r, :) v)
+      T vs[CQ];
+#pragma unroll
+      for (int s = 0; s < CQ; ++s) vs[s] = (gc * CQ + s < l) ? vec[gc * CQ + s] : (T)0;
+      T w[RQ];
+#pragma unroll
+      for (int i = 0; i < RQ; ++i) {
+        T u0 = (T)0, u1 = (T)0;
+#pragma unroll
+        for (int s = 0; s + 1 < CQ; s += 2) {
+          u0 = fma(qreg[i][s], vs[s], u0);
+          u1 = fma(qreg[i][s + 1], vs[s + 1], u1);
+        }
+        if (CQ & 1) u0 = fma(qreg[i][CQ - 1], vs[CQ - 1], u0);
+        T u = u0 + u1;
+        u += __shfl_xor(u, 1);
+        u += __shfl_xor(u, 2);
+        u += __shfl_xor(u, 4);
+        w[i] = clip0<T>(u);
+      }
+      if (gc == 0) {
+#pragma unroll
+        for (int i = 0; i < RQ; ++i) {
+          const int rr = ga + 64 * i;
+          if (rr < nr) a.W[(size_t)(r0 + rr) * k + jj] = w[i];
+        }
+      }
+      // local map-back partials: sum_i Q(r_i, a) w_i over this thread's rows
+      T pv[CQ];
+#pragma unroll
+      for (int s = 0; s < CQ; ++s) {
+        T p0 = (T)0, p1 = (T)0;
+#pragma unroll
+        for (int i = 0; i + 1 < RQ; i += 2) {
+          p0 = fma(qreg[i][s], w[i], p0);
+          p1 = fma(qreg[i + 1][s], w[i + 1], p1);
+        }
+        if (RQ & 1) p0 = fma(qreg[RQ - 1][s], w[RQ - 1], p0);
+        T p = p0 + p1;
+        p += __shfl_xor(p, 8);
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        pv[s] = p;
+      }
+      if (lane < 8) {
+#pragma unroll
+        for (int s = 0; s < CQ; ++s) part[wave * 72 + gc * CQ + s] = pv[s];
+      }
+      const int nj = next_col(jj);
+      lds_sync();
+      if (tr_sweep) { TRACE(5 + 2 * jj); }
+      // exchange (t < l) and, meanwhile, the next update vector's partials
+      const unsigned e = ++x.seq;
+      const unsigned par = (x.small_use++) & 1u;
+      T wt = (T)0;
+      bool ok = true;
+      if (t < l) {
+        T s = part[t];
+#pragma unroll
+        for (int wv = 1; wv < 8; ++wv) s += part[wv * 72 + t];
+        const size_t slot = (size_t)LPS * 2;
+        u64* P = a.xs_part + ((size_t)par * a.G) * slot;
+        u64* RS = a.xs_row + ((size_t)par * a.G) * slot;
+        put<T>(P + (size_t)x.g * slot, t, s, e);
+        s = gather_sum<T>(P + (size_t)x.i * a.GC * slot, slot, a.GC, t, e, ok);
+        if (a.GR > 1) {
+          put<T>(RS + (size_t)x.g * slot, t, s, e);
+          s = gather_sum<T>(RS + (size_t)x.j * slot, (size_t)a.GC * slot, a.GR, t, e, ok);
+        }
+        wt = s;
+      } else if (t >= 128 && nj < k) {
+        // sum over i != jj of W~(a, i) V(i, nj), in 5 parts of the index range
+        const int h = t - 128, aa = h % l, pt = h / l;
+        if (pt < 5) {
+          const int i0 = (k * pt) / 5, i1 = (k * (pt + 1)) / 5;
+          T s = (T)0;
+          for (int ii = i0; ii < i1; ++ii)
+            if (ii != jj) s = fma(Wts[aa * k + ii], Vm[ii * k + nj], s);
+          cpart[pt * LPS + aa] = s;
+        }
+      }
+      if (!ok) abort_flag = 1;
+      lds_sync();
+      if (abort_flag) return false;
+      if (t < l) {
+        Wts[t * k + jj] = wt;
+        if (g == 0 && !(wt == wt)) atomicOr(a.status, ST_NONFINITE_SWEEP);
+        if (nj < k) {
+          T s = cpart[t];
+#pragma unroll
+          for (int pt = 1; pt < 5; ++pt) s += cpart[pt * LPS + t];
+          s = fma(wt, Vm[jj * k + nj], s);
+          vec[t] = Wts[t * k + nj] + (Tm[t * k + nj] - s) / Vm[nj * k + nj];
+        }
+      }
+      if (tr_sweep) { TRACE(6 + 2 * jj); }
+      lds_sync();
+      jj = nj;
+    }
+    return true;
+  };
+
+  auto w_phase = [&]() __attribute__((always_inline)) -> bool {
     for (int jj = 0; jj < k; ++jj) {
       const T d = Vm[jj * k + jj];
       if (!(d > (T)0)) continue;
       if (t < l) {
-        T s = Tm[t * k + jj];
-        for (int ii = 0; ii < k; ++ii) s = fma(-Wts[t * k + ii], Vm[ii * k + jj], s);
-        vec[t] = Wts[t * k + jj] + s / d;
+        const T* wr = Wts + t * k;
+        T s0 = Tm[t * k + jj], s1 = (T)0, s2 = (T)0, s3 = (T)0;
+        int ii = 0;
+        for (; ii + 4 <= k; ii += 4) {
+          s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
+          s1 = fma(-wr[ii + 1], Vm[(ii + 1) * k + jj], s1);
+          s2 = fma(-wr[ii + 2], Vm[(ii + 2) * k + jj], s2);
+          s3 = fma(-wr[ii + 3], Vm[(ii + 3) * k + jj], s3);
+        }
+        for (; ii < k; ++ii) s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
+        vec[t] = Wts[t * k + jj] + ((s0 + s1) + (s2 + s3)) / d;
       }
-      __syncthreads();
+      lds_sync();
+      if (tr_sweep && jj == 1) { TRACE(10 + 2 * k); }
+      // lift and clip on the local rows: W(r, j) = max(0, Q(r, :) v)
       for (int rr = t; rr < nr; rr += NTH) {
-        const T* q = qrow<T>(a, Qs, r0, rr);
-        T u = (T)0;
-        for (int aa = 0; aa < l; ++aa) u = fma(q[aa], vec[aa], u);
-        const T w = clip0<T>(u);
+        const T* q = rr < nrl ? nullptr : a.Q + (size_t)(r0 + rr) * l;
+        T u0 = (T)0, u1 = (T)0, u2 = (T)0, u3 = (T)0;
+        int aa = 0;
+        if (rr < nrl) {
+          const T* qs = Qs + rr * lq;
+          for (; aa + 4 <= l; aa += 4) {
+            u0 = fma(qs[aa], vec[aa], u0);
+            u1 = fma(qs[aa + 1], vec[aa + 1], u1);
+            u2 = fma(qs[aa + 2], vec[aa + 2], u2);
+            u3 = fma(qs[aa + 3], vec[aa + 3], u3);
+          }
+          for (; aa < l; ++aa) u0 = fma(qs[aa], vec[aa], u0);
+        } else {
+          for (; aa + 4 <= l; aa += 4) {
+            u0 = fma(q[aa], vec[aa], u0);
+            u1 = fma(q[aa + 1], vec[aa + 1], u1);
+            u2 = fma(q[aa + 2], vec[aa + 2], u2);
+            u3 = fma(q[aa + 3], vec[aa + 3], u3);
+          }
+          for (; aa < l; ++aa) u0 = fma(q[aa], vec[aa], u0);
+        }
+        const T w = clip0<T>((u0 + u1) + (u2 + u3));
         wcol[rr] = w;
         a.W[(size_t)(r0 + rr) * k + jj] = w;
       }
-      __syncthreads();
+      lds_sync();
+      if (tr_sweep && jj == 1) { TRACE(11 + 2 * k); }
+      // local part of the map-back Q^T W(:, j)
       if (t < RG * l) {
         const int aa = t % l, rg = t / l;
-        T s = (T)0;
-        for (int rr = rg; rr < nr; rr += RG) s = fma(qrow<T>(a, Qs, r0, rr)[aa], wcol[rr], s);
-        red2[rg * LPS + aa] = s;
+        T s0 = (T)0, s1 = (T)0, s2 = (T)0, s3 = (T)0;
+        int rr = rg;
+        for (; rr + 3 * RG < nrl; rr += 4 * RG) {
+          s0 = fma(Qs[rr * lq + aa], wcol[rr], s0);
+          s1 = fma(Qs[(rr + RG) * lq + aa], wcol[rr + RG], s1);
+          s2 = fma(Qs[(rr + 2 * RG) * lq + aa], wcol[rr + 2 * RG], s2);
+          s3 = fma(Qs[(rr + 3 * RG) * lq + aa], wcol[rr + 3 * RG], s3);
+        }
+        for (; rr < nrl; rr += RG) s0 = fma(Qs[rr * lq + aa], wcol[rr], s0);
+        for (; rr < nr; rr += RG) s0 = fma(a.Q[(size_t)(r0 + rr) * l + aa], wcol[rr], s0);
+        red2[rg * LPS + aa] = (s0 + s1) + (s2 + s3);
       }
-      __syncthreads();
+      lds_sync();
+      if (tr_sweep && jj == 1) { TRACE(12 + 2 * k); }
       if (t < l) {
         T s = (T)0;
         for (int rg = 0; rg < RG; ++rg) s += red2[rg * LPS + t];
         vec[t] = s;
       }
-      __syncthreads();
+      lds_sync();
+      if (tr_sweep) { TRACE(5 + 2 * jj); }
       if (!allreduce_small<T, T>(a, x, vec, l, &abort_flag)) return false;
+      if (tr_sweep) { TRACE(6 + 2 * jj); }
       if (t < l) {
         Wts[t * k + jj] = vec[t];
         if (g == 0 && !(vec[t] == vec[t])) atomicOr(a.status, ST_NONFINITE_SWEEP);
       }
-      __syncthreads();
+      lds_sync();
     }
     return true;
   };
 
   // projected gradient norm^2 on X^ = Q B (factor 2 dropped)
-  auto pgrad = [&](double& out) -> bool {
+  auto pgrad = [&](double& out) __attribute__((always_inline)) -> bool {
+    __syncthreads();  // W and H written by other threads of this workgroup
     double s = 0.0;
     for (int e = t; e < nr * k; e += NTH) {
       int rr = e / k, cc = e % k;
       const T* wr = a.W + (size_t)(r0 + rr) * k;
-      const T* q = qrow<T>(a, Qs, r0, rr);
       T gval = (T)0;
       for (int ii = 0; ii < k; ++ii) gval = fma(wr[ii], Vm[ii * k + cc], gval);
-      for (int aa = 0; aa < l; ++aa) gval = fma(-q[aa], Tm[aa * k + cc], gval);
+      if (rr < nrl) {
+        for (int aa = 0; aa < l; ++aa) gval = fma(-Qs[rr * lq + aa], Tm[aa * k + cc], gval);
+      } else {
+        for (int aa = 0; aa < l; ++aa) gval = fma(-a.Q[(size_t)(r0 + rr) * l + aa], Tm[aa * k + cc], gval);
+      }
       T p = wr[cc] > (T)0 ? gval : (gval < (T)0 ? gval : (T)0);
       s += (double)p * (double)p;
     }
@@ -423,9 +790,9 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       int cc = e / k, jj = e % k;
       const int c = c0 + cc;
       T gval = (T)0;
-      for (int ii = 0; ii < k; ++ii) gval = fma(Sm[jj * k + ii], a.H[(size_t)ii * a.n + c], gval);
-      for (int aa = 0; aa < l; ++aa) gval = fma(-Wts[aa * k + jj], a.B[(size_t)aa * a.n + c], gval);
-      T hv = a.H[(size_t)jj * a.n + c];
+      for (int ii = 0; ii < k; ++ii) gval = fma(Sm[jj * k + ii], a.H[(size_t)ii * n + c], gval);
+      for (int aa = 0; aa < l; ++aa) gval = fma(-Wts[aa * k + jj], a.B[(size_t)aa * n + c], gval);
+      T hv = a.H[(size_t)jj * n + c];
       T p = hv > (T)0 ? gval : (gval < (T)0 ? gval : (T)0);
       s += (double)p * (double)p;
     }
@@ -445,35 +812,75 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     return true;
   };
 
-  // --- prologue -------------------------------------------------------------
+  // --- schedule: every phase is instantiated once (keeps the kernel small
+  // enough for the instruction cache); the order of phases is data ---------
+  enum { PH_S = 0, PH_TV = 1, PH_H = 2, PH_W = 3, PH_PG = 4 };
+  int pro[3], npro = 0, seq[5], nseq = 0;
+  if (need_S) pro[npro++] = PH_S;
+  if (need_pg || a.order == 1) pro[npro++] = PH_TV;
+  if (need_pg) pro[npro++] = PH_PG;
+  if (a.order == 0) {
+    seq[nseq++] = PH_H; seq[nseq++] = PH_TV; seq[nseq++] = PH_W;
+    if (need_S) seq[nseq++] = PH_S;
+  } else {
+    seq[nseq++] = PH_W;
+    if (need_S) seq[nseq++] = PH_S;
+    seq[nseq++] = PH_H; seq[nseq++] = PH_TV;
+  }
+  if (need_pg) seq[nseq++] = PH_PG;
+
   bool alive = true;
   double pg0 = 0.0, pg = 0.0;
   int done = 0;
-  if (need_S) alive = s_exchange();
-  if (alive && (need_pg || a.order == 1)) alive = tv_exchange();
-  if (alive && need_pg) { alive = pgrad(pg0); pg = pg0; }
-
-  // --- sweeps ---------------------------------------------------------------
-  for (int sw = 0; alive && sw < a.nsweeps; ++sw) {
-    if (a.order == 0) {
-      h_phase();
-      alive = tv_exchange();
-      if (alive) alive = w_phase();
-      if (alive && need_S) alive = s_exchange();
-    } else {
-      alive = w_phase();
-      if (alive && need_S) alive = s_exchange();
-      if (alive) { h_phase(); alive = tv_exchange(); }
+  int pos = -npro;  // negative: prologue
+  if (a.nsweeps <= 0 && npro == 0) pos = 0;
+  while (alive && (pos < 0 || done < a.nsweeps)) {
+    const int ph = pos < 0 ? pro[pos + npro] : seq[pos];
+    const bool in_sweep = pos >= 0;
+    tr_sweep = in_sweep && done == 0;
+    switch (ph) {
+      case PH_S:
+        alive = s_exchange();
+        if (tr_sweep) { TRACE(7 + 2 * k); }
+        break;
+      case PH_TV:
+        alive = tv_exchange();
+        if (tr_sweep) { TRACE(4); }
+        break;
+      case PH_H:
+        h_phase();
+        if (tr_sweep) { TRACE(3); }
+        break;
+      case PH_W:
+        if constexpr (REGQ) alive = w_phase_reg();
+        else alive = w_phase();
+        if (tr_sweep) { TRACE(5 + 2 * k); }
+        break;
+      default: {
+        double v = 0.0;
+        alive = pgrad(v);
+        if (in_sweep) pg = v;
+        else { pg0 = v; pg = v; }
+        break;
+      }
     }
     if (!alive) break;
-    ++done;
-    if (need_pg) {
-      alive = pgrad(pg);
-      if (!alive) break;
-      if (pg < a.tol * pg0) break;
+    ++pos;
+    if (pos == 0 && !in_sweep) {
+      TRACE(2);
+      if (a.nsweeps <= 0) break;
+    }
+    if (in_sweep && pos == nseq) {
+      if (tr_sweep) { TRACE(8 + 2 * k); }
+      pos = 0;
+      ++done;
+      if (need_pg && pg < a.tol * pg0) break;
     }
   }
+  tr_sweep = false;
 
+  TRACE(9 + 2 * k);
+#undef TRACE
   if (!alive) {
     if (t == 0) atomicOr(a.status, ST_TIMEOUT);
     return;
@@ -490,7 +897,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 
 }  // namespace
 
-SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d) {
+SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, bool need_pg) {
   SweepShape sh;
   int gmax = d.cus < 256 ? d.cus : 256;
   int G = 1;
@@ -503,18 +910,22 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d) 
   sh.cb = l * k + k * k;
   sh.nt = NTH;
   const size_t es = dt == 0 ? 8 : 4;
-  const int lq = l | 1;
+  const int lq = l | 1;  // odd row stride: row-per-thread LDS reads hit distinct banks
   // Wts + U + vec + wcol + red2 (also the W staging area: 32 x 4*ceil(k/4))
   size_t red2 = 16 * (size_t)LPS;
   size_t stage = 32 * (size_t)(4 * ((k + 3) / 4));
   if (stage > red2) red2 = stage;
+  if ((size_t)(LMAX + KMAX) * 8 > red2) red2 = (size_t)(LMAX + KMAX) * 8;  // T/V column staging
+
   if ((size_t)NTH * 8 / es > red2) red2 = (size_t)NTH * 8 / es;  // pg reduction as doubles
   red2 = round_up(red2, 4);
   sh.red2_elems = (int)red2;
-  size_t fixed = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
+  sh.alias_sv = need_pg ? 0 : 1;
+  size_t fixed = ((size_t)l * k + (size_t)l * k + (size_t)(need_pg ? 2 : 1) * k * k + LPS + sh.rows_per + red2) * es;
   size_t budget = (size_t)d.max_lds - 1024;  // static shared + alignment slack
   size_t qrows = fixed < budget ? (budget - fixed) / ((size_t)lq * es) : 0;
-  sh.rows_lds = (int)((size_t)sh.rows_per < qrows ? sh.rows_per : qrows);
+  sh.regq = (sh.rows_per <= 64 * RQ && l <= 8 * CQ) ? 1 : 0;
+  sh.rows_lds = sh.regq ? 0 : (int)((size_t)sh.rows_per < qrows ? sh.rows_per : qrows);
   sh.lds_bytes = fixed + (size_t)sh.rows_lds * lq * es;
   return sh;
 }
@@ -528,7 +939,7 @@ size_t sweep_ws_words(const SweepShape& sh, int l) {
 
 hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void* B, void* W, void* Wt, void* H,
                         int64_t m, int64_t n, int l, int k, int nsweeps, double tol, int gram_mode, int order,
-                        u64* xbuf, double* stats, unsigned* status, hipStream_t s) {
+                        u64* xbuf, double* stats, unsigned* status, u64* trace, hipStream_t s) {
   size_t words = sweep_ws_words(sh, l);
   hipError_t e = launch_fill_u32((unsigned*)xbuf, words * 2, 0u, s);
   if (e != hipSuccess) return e;
@@ -547,25 +958,24 @@ hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void*
   a.m = (int)m; a.n = (int)n; a.l = l; a.k = k;                                                  \
   a.nsweeps = nsweeps; a.tol = tol; a.gram_mode = gram_mode; a.order = order;                   \
   a.G = sh.G; a.GR = sh.GR; a.GC = sh.GC; a.rows_per = sh.rows_per; a.cols_per = sh.cols_per;  \
-  a.rows_lds = sh.rows_lds; a.lq = l | 1; a.cb = sh.cb; a.red2_elems = sh.red2_elems;             \
+  a.rows_lds = sh.rows_lds; a.lq = l | 1; a.cb = sh.cb; a.red2_elems = sh.red2_elems;               \
+  a.alias_sv = sh.alias_sv; a.trace = trace;                                                     \
   a.xs_part = xs_part; a.xs_row = xs_row; a.xb_part = xb_part; a.xb_row = xb_row;              \
   a.xb_fin = xb_fin; a.lpw = slot; a.cbw = cbw; a.csw = csw; a.stats = stats; a.status = status;
   if (dt == 0) {
     FILL_ARGS(double);
     void* args[] = {&a};
-    e = hipFuncSetAttribute((const void*)sweep_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sh.lds_bytes);
+    const void* fn = sh.regq ? (const void*)sweep_kernel<double, true> : (const void*)sweep_kernel<double, false>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
-    return hipLaunchCooperativeKernel((const void*)sweep_kernel<double>, dim3(sh.G), dim3(NTH), args,
-                                      (unsigned)sh.lds_bytes, s);
+    return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);
   } else {
     FILL_ARGS(float);
     void* args[] = {&a};
-    e = hipFuncSetAttribute((const void*)sweep_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sh.lds_bytes);
+    const void* fn = sh.regq ? (const void*)sweep_kernel<float, true> : (const void*)sweep_kernel<float, false>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
-    return hipLaunchCooperativeKernel((const void*)sweep_kernel<float>, dim3(sh.G), dim3(NTH), args,
-                                      (unsigned)sh.lds_bytes, s);
+    return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);
   }
 #undef FILL_ARGS
 }

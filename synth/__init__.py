@@ -74,7 +74,7 @@ def _noise_sigma(m, n, r, seed, noise_abs, noise_rel, density, Hs):
 
 
 def low_rank_rows(m, n, rank, seed, noise_abs=0.0, noise_rel=0.0, density=1.0,
-                  chunks=None, dtype=np.float64):
+                  chunks=None, dtype=np.float64, threads=1):
     """Rows of X = max(0, W* H* + sigma N), W*, H* ~ U[0,1) (H* optionally
     masked to the given density), N standard normal.  sigma is noise_abs, or
     noise_rel times the RMS of the clean product.  With ``chunks`` (a list of
@@ -88,14 +88,24 @@ def low_rank_rows(m, n, rank, seed, noise_abs=0.0, noise_rel=0.0, density=1.0,
         sel = [all_chunks[int(c)] for c in chunks]
     rows = sum(r1 - r0 for _, r0, r1 in sel)
     X = np.empty((rows, n), dtype=dtype)
-    o = 0
-    for c, r0, r1 in sel:
+    offs = np.cumsum([0] + [r1 - r0 for _, r0, r1 in sel])
+
+    def fill(i):
+        c, r0, r1 = sel[i]
         blk = _chunk_clean(seed, c, r1 - r0, Hs)
         if sigma > 0.0:
             blk += sigma * stream(seed, S_NOISE, c).standard_normal(blk.shape)
         np.maximum(blk, 0.0, out=blk)
-        X[o:o + (r1 - r0)] = blk
-        o += r1 - r0
+        X[offs[i]:offs[i + 1]] = blk
+
+    if len(sel) > 4 and threads > 1:
+        # chunks are independent streams, so threading does not change X
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(fill, range(len(sel))))
+    else:
+        for i in range(len(sel)):
+            fill(i)
     return X
 
 
@@ -133,14 +143,14 @@ def subsample_chunks(m, count, seed):
     return np.sort(idx)
 
 
-def make(name, rows_chunks=None, dtype=None):
+def make(name, rows_chunks=None, dtype=None, threads=1):
     """(X, Omega, W0, H0, params) for a named workload.  X, Omega, W0 and H0
     are produced in float64 and rounded once to the workload's storage type."""
     w = workload(name)
     dt = np.float64 if (dtype or w["dtype"]) == "f64" else np.float32
     X = low_rank_rows(w["m"], w["n"], w["rank"], w["seed"], w["noise_abs"],
                       w["noise_rel"], w["density"], chunks=rows_chunks,
-                      dtype=np.float64).astype(dt)
+                      dtype=dt, threads=threads)
     m = X.shape[0]
     n = w["n"]
     l = sketch_cols(w["k"], w["p"], m, n)
