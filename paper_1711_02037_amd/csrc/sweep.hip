@@ -273,6 +273,18 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   T* vec = Vm + (size_t)k * k * (a.alias_sv ? 1 : 2);  // LPS
   T* wcol = vec + LPS;                            // rows_per
   T* Qs = wcol + a.rows_per;                      // rows_lds x lq
+  // with the Q slab in registers, LDS also holds this workgroup's rows of W
+  // and columns of B and H for the whole launch
+  const int cp = a.cols_per;
+  T* Ws = Qs + (size_t)a.rows_lds * lq;           // rows_per x k   (REGQ)
+  T* Bs = Ws + (size_t)a.rows_per * k;            // l x cols_per   (REGQ)
+  T* Hs = Bs + (size_t)l * cp;                    // k x cols_per   (REGQ)
+  const T* Bp;
+  T* Hp;
+  int ldB;
+  if constexpr (REGQ) { Bp = Bs; Hp = Hs; ldB = cp; }
+  else { Bp = a.B + c0; Hp = a.H + c0; ldB = n; }
+  const int ldH = ldB;
 
   const bool tracer = a.trace && g == 0 && t == 0;
 #define TRACE(idx) \
@@ -289,6 +301,15 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         const int rr = ga + 64 * i, aa = gc * CQ + s;
         qreg[i][s] = (rr < nr && aa < l) ? a.Q[(size_t)(r0 + rr) * l + aa] : (T)0;
       }
+    for (int e = t; e < nr * k; e += NTH) Ws[e] = a.W[(size_t)r0 * k + e];
+    for (int e = t; e < l * cp; e += NTH) {
+      const int r = e / cp, cc = e - (e / cp) * cp;
+      Bs[e] = cc < nc ? a.B[(size_t)r * n + c0 + cc] : (T)0;
+    }
+    for (int e = t; e < k * cp; e += NTH) {
+      const int r = e / cp, cc = e - (e / cp) * cp;
+      Hs[e] = cc < nc ? a.H[(size_t)r * n + c0 + cc] : (T)0;
+    }
   } else {
     for (int e = t; e < nrl * l; e += NTH) {
       int rr = e / l, c = e - rr * l;
@@ -330,24 +351,33 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         pf[q] = (e < RC * kp && cstart + rr < nr && cc < k) ? a.W[(size_t)(r0 + cstart + rr) * k + cc] : (T)0;
       }
     };
-    fetch(0);
+    if constexpr (!REGQ) fetch(0);
+    // REGQ: rows come straight from the LDS copy Ws (leading dimension k)
+    const int lds_ld = REGQ ? k : kp;
     for (int cs = 0; cs < nr; cs += RC) {
-      lds_sync();
+      const T* rows;
+      if constexpr (REGQ) {
+        rows = Ws + (size_t)cs * k;
+      } else {
+        rows = red2;
+        lds_sync();
 #pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        const int e = t + q * NTH;
-        if (e < RC * kp) red2[e] = pf[q];
+        for (int q = 0; q < PF; ++q) {
+          const int e = t + q * NTH;
+          if (e < RC * kp) red2[e] = pf[q];
+        }
+        lds_sync();
+        if (cs + RC < nr) fetch(cs + RC);
       }
-      lds_sync();
-      if (cs + RC < nr) fetch(cs + RC);
       if (ba >= 0) {
         const int rmax = (nr - cs < RC) ? nr - cs : RC;
         for (int rr = rgi; rr < rmax; rr += NG) {
           double u[4], w[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            u[q] = (double)red2[rr * kp + 4 * ba + q];
-            w[q] = (double)red2[rr * kp + 4 * bb + q];
+            const int c1 = 4 * ba + q, c2 = 4 * bb + q;
+            u[q] = (REGQ && c1 >= k) ? 0.0 : (double)rows[rr * lds_ld + c1];
+            w[q] = (REGQ && c2 >= k) ? 0.0 : (double)rows[rr * lds_ld + c2];
           }
 #pragma unroll
           for (int p = 0; p < 4; ++p)
@@ -392,8 +422,18 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     }
   };
 
+  // REGQ: the W phase fills the local S column by column (s_cols marks the
+  // columns done); the rest comes from the LDS copy of the W rows.
+  unsigned long long s_cols = 0ull;
   auto s_exchange = [&]() __attribute__((always_inline)) -> bool {
-    local_wgram();
+    const unsigned long long all_cols = (k == 64) ? ~0ull : ((1ull << k) - 1ull);
+    if constexpr (REGQ) {
+      if ((s_cols & all_cols) != all_cols) local_wgram();
+      s_cols = 0ull;
+      lds_sync();
+    } else {
+      local_wgram();
+    }
     if (tr_sweep) { TRACE(6 + 2 * k); }
     return allreduce_big<T>(a, x, Sm, k * k, &abort_flag);
   };
@@ -402,12 +442,15 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // 4 x 4 register blocks (FP64 accumulation); B and H columns are staged
   // through LDS 8 columns at a time.
   auto tv_exchange = [&]() __attribute__((always_inline)) -> bool {
-    __syncthreads();  // H columns written by other threads of this workgroup
+    if constexpr (REGQ) lds_sync();
+    else __syncthreads();  // H columns written by other threads of this workgroup
     constexpr int CW = 8;
     const int nbt = lb * kb;                 // blocks of T
     const int nbv = kb * (kb + 1) / 2;       // upper blocks of V
-    T* Bs = red2;                            // l x CW
-    T* Hs = red2 + LMAX * CW;                // k x CW
+    T* Bst;
+    T* Hst;
+    if constexpr (REGQ) { Bst = Bs; Hst = Hs; }
+    else { Bst = red2; Hst = red2 + LMAX * CW; }  // l x CW and k x CW staging
     double acc[2][16];
     int br[2], bc[2], isv[2];
 #pragma unroll
@@ -419,27 +462,30 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[q][e] = 0.0;
     }
-    for (int cs = 0; cs < nc; cs += CW) {
-      const int w = (nc - cs < CW) ? nc - cs : CW;
-      lds_sync();
-      for (int e = t; e < (l + k) * CW; e += NTH) {
-        const int row = e / CW, cc = e - (e / CW) * CW;
-        if (row < l) Bs[row * CW + cc] = cc < w ? a.B[(size_t)row * n + c0 + cs + cc] : (T)0;
-        else Hs[(row - l) * CW + cc] = cc < w ? a.H[(size_t)(row - l) * n + c0 + cs + cc] : (T)0;
+    const int CWS = REGQ ? cp : CW;  // column stride of the staged slabs
+    for (int cs = 0; cs < nc; cs += (REGQ ? nc : CW)) {
+      const int w = REGQ ? nc : ((nc - cs < CW) ? nc - cs : CW);
+      if constexpr (!REGQ) {
+        lds_sync();
+        for (int e = t; e < (l + k) * CW; e += NTH) {
+          const int row = e / CW, cc = e - (e / CW) * CW;
+          if (row < l) Bst[row * CW + cc] = cc < w ? a.B[(size_t)row * n + c0 + cs + cc] : (T)0;
+          else Hst[(row - l) * CW + cc] = cc < w ? a.H[(size_t)(row - l) * n + c0 + cs + cc] : (T)0;
+        }
       }
       lds_sync();
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (isv[q] < 0) continue;
-        const T* left = isv[q] ? Hs : Bs;
+        const T* left = isv[q] ? Hst : Bst;
         const int rl = isv[q] ? k : l;
         for (int cc = 0; cc < w; ++cc) {
           double u[4], v[4];
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
             const int r = 4 * br[q] + p, c = 4 * bc[q] + p;
-            u[p] = r < rl ? (double)left[r * CW + cc] : 0.0;
-            v[p] = c < k ? (double)Hs[c * CW + cc] : 0.0;
+            u[p] = r < rl ? (double)left[r * CWS + cc] : 0.0;
+            v[p] = c < k ? (double)Hst[c * CWS + cc] : 0.0;
           }
 #pragma unroll
           for (int p = 0; p < 4; ++p)
@@ -476,8 +522,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           if (c >= k || r >= (vv ? k : l)) continue;
           double sum = 0.0;
           for (int cc = 0; cc < nc; ++cc) {
-            const double lv = vv ? (double)a.H[(size_t)r * n + c0 + cc] : (double)a.B[(size_t)r * n + c0 + cc];
-            sum = fma(lv, (double)a.H[(size_t)c * n + c0 + cc], sum);
+            const double lv = vv ? (double)Hp[(size_t)r * ldH + cc] : (double)Bp[(size_t)r * ldB + cc];
+            sum = fma(lv, (double)Hp[(size_t)c * ldH + cc], sum);
           }
           if (!vv) Tm[r * k + c] = (T)sum;
           else { Vm[r * k + c] = (T)sum; Vm[c * k + r] = (T)sum; }
@@ -513,12 +559,11 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     // FP64 arithmetic: the update cancels R against H^T S, and S is the Gram
     // of a nonnegative factor, so its rounding is amplified.
     for (int cc = wave; cc < nc; cc += NTH / 64) {
-      const int c = c0 + cc;
       const int jj = lane < k ? lane : 0;
       // lane holds B(lane, c) and B(lane + 64, c); H(lane, c)
-      const T b0 = lane < l ? a.B[(size_t)lane * n + c] : (T)0;
-      const T b1 = lane + 64 < l ? a.B[(size_t)(lane + 64) * n + c] : (T)0;
-      double h = lane < k ? (double)a.H[(size_t)lane * n + c] : 0.0;
+      const T b0 = lane < l ? Bp[(size_t)lane * ldB + cc] : (T)0;
+      const T b1 = lane + 64 < l ? Bp[(size_t)(lane + 64) * ldB + cc] : (T)0;
+      double h = lane < k ? (double)Hp[(size_t)lane * ldH + cc] : 0.0;
       double R0 = 0.0, R1 = 0.0;
       const int l0 = l < 64 ? l : 64;
       int aa = 0;
@@ -548,9 +593,10 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           gsum = fma(-(double)Snum[ii * k + jj], delta, gsum);
         }
       }
-      if (lane < k) a.H[(size_t)lane * n + c] = (T)h;
+      if (lane < k) Hp[(size_t)lane * ldH + cc] = (T)h;
     }
-    __syncthreads();
+    if constexpr (REGQ) lds_sync();
+    else __syncthreads();
   };
 
   // --- W phase: columns of W in order, one device-wide exchange each --------
@@ -563,6 +609,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   auto w_phase_reg = [&]() __attribute__((always_inline)) -> bool {
     T* part = red2;                    // 8 x 72: per-wave map-back partials
     T* cpart = red2 + 8 * 72;          // 5 x LPS: partial sums for the next update vector
+    double* spart = (double*)(red2 + 8 * 72 + 5 * LPS);  // 2 x 384: local S partial sums
+    int jprev = -1;  // column whose S partials await their reduction
     auto next_col = [&](int j) __attribute__((always_inline)) -> int {
       int q = j + 1;
       while (q < k && !(Vm[q * k + q] > (T)0)) ++q;
@@ -608,7 +656,10 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < RQ; ++i) {
           const int rr = ga + 64 * i;
-          if (rr < nr) a.W[(size_t)(r0 + rr) * k + jj] = w[i];
+          if (rr < nr) {
+            a.W[(size_t)(r0 + rr) * k + jj] = w[i];
+            Ws[rr * k + jj] = w[i];
+          }
         }
       }
       // local map-back partials: sum_i Q(r_i, a) w_i over this thread's rows
@@ -654,20 +705,51 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           s = gather_sum<T>(RS + (size_t)x.j * slot, (size_t)a.GC * slot, a.GR, t, e, ok);
         }
         wt = s;
-      } else if (t >= 128 && nj < k) {
-        // sum over i != jj of W~(a, i) V(i, nj), in 5 parts of the index range
-        const int h = t - 128, aa = h % l, pt = h / l;
-        if (pt < 5) {
-          const int i0 = (k * pt) / 5, i1 = (k * (pt + 1)) / 5;
-          T s = (T)0;
-          for (int ii = i0; ii < i1; ++ii)
-            if (ii != jj) s = fma(Wts[aa * k + ii], Vm[ii * k + nj], s);
-          cpart[pt * LPS + aa] = s;
+      } else if (t >= 128) {
+        if (nj < k) {
+          // sum over i != jj of W~(a, i) V(i, nj), in 5 parts of the index range
+          const int h = t - 128, aa = h % l, pt = h / l;
+          if (pt < 5) {
+            const int i0 = (k * pt) / 5, i1 = (k * (pt + 1)) / 5;
+            T s = (T)0;
+            for (int ii = i0; ii < i1; ++ii)
+              if (ii != jj) s = fma(Wts[aa * k + ii], Vm[ii * k + nj], s);
+            cpart[pt * LPS + aa] = s;
+          }
+        }
+        if (need_S) {
+          // local S(i, j) = sum_r W(r, i) W(r, j) for i <= j (columns i < j
+          // are final): entry i, rows r = p, p + P, ... in part p
+          const int h = t - 128, np = 384 / (jj + 1);
+          const int i = h / np, p = h - (h / np) * np;
+          // first finish the previous column (its partials are in the other buffer)
+          if (jprev >= 0 && h <= jprev) {
+            const int npp = 384 / (jprev + 1);
+            const double* sp = spart + (jprev & 1) * 384 + h * npp;
+            double s = 0.0;
+            for (int q = 0; q < npp; ++q) s += sp[q];
+            Sm[h * k + jprev] = (T)s;
+            Sm[jprev * k + h] = (T)s;
+          }
+          if (i <= jj) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int r = p;
+            for (; r + 3 * np < nr; r += 4 * np) {
+              s0 = fma((double)Ws[r * k + i], (double)Ws[r * k + jj], s0);
+              s1 = fma((double)Ws[(r + np) * k + i], (double)Ws[(r + np) * k + jj], s1);
+              s2 = fma((double)Ws[(r + 2 * np) * k + i], (double)Ws[(r + 2 * np) * k + jj], s2);
+              s3 = fma((double)Ws[(r + 3 * np) * k + i], (double)Ws[(r + 3 * np) * k + jj], s3);
+            }
+            for (; r < nr; r += np) s0 = fma((double)Ws[r * k + i], (double)Ws[r * k + jj], s0);
+            spart[(jj & 1) * 384 + h] = (s0 + s1) + (s2 + s3);
+          }
         }
       }
+      s_cols |= 1ull << jj;
       if (!ok) abort_flag = 1;
       lds_sync();
       if (abort_flag) return false;
+      jprev = jj;
       if (t < l) {
         Wts[t * k + jj] = wt;
         if (g == 0 && !(wt == wt)) atomicOr(a.status, ST_NONFINITE_SWEEP);
@@ -682,6 +764,18 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       if (tr_sweep) { TRACE(6 + 2 * jj); }
       lds_sync();
       jj = nj;
+    }
+    if (need_S && jprev >= 0) {
+      const int h = t - 128;
+      if (h >= 0 && h <= jprev) {
+        const int npp = 384 / (jprev + 1);
+        const double* sp = spart + (jprev & 1) * 384 + h * npp;
+        double s = 0.0;
+        for (int q = 0; q < npp; ++q) s += sp[q];
+        Sm[h * k + jprev] = (T)s;
+        Sm[jprev * k + h] = (T)s;
+      }
+      lds_sync();
     }
     return true;
   };
@@ -773,9 +867,12 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   auto pgrad = [&](double& out) __attribute__((always_inline)) -> bool {
     __syncthreads();  // W and H written by other threads of this workgroup
     double s = 0.0;
+    const T* Wrows;
+    if constexpr (REGQ) Wrows = Ws;
+    else Wrows = a.W + (size_t)r0 * k;
     for (int e = t; e < nr * k; e += NTH) {
       int rr = e / k, cc = e % k;
-      const T* wr = a.W + (size_t)(r0 + rr) * k;
+      const T* wr = Wrows + (size_t)rr * k;
       T gval = (T)0;
       for (int ii = 0; ii < k; ++ii) gval = fma(wr[ii], Vm[ii * k + cc], gval);
       if (rr < nrl) {
@@ -788,11 +885,10 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     }
     for (int e = t; e < nc * k; e += NTH) {
       int cc = e / k, jj = e % k;
-      const int c = c0 + cc;
       T gval = (T)0;
-      for (int ii = 0; ii < k; ++ii) gval = fma(Sm[jj * k + ii], a.H[(size_t)ii * n + c], gval);
-      for (int aa = 0; aa < l; ++aa) gval = fma(-Wts[aa * k + jj], a.B[(size_t)aa * n + c], gval);
-      T hv = a.H[(size_t)jj * n + c];
+      for (int ii = 0; ii < k; ++ii) gval = fma(Sm[jj * k + ii], Hp[(size_t)ii * ldH + cc], gval);
+      for (int aa = 0; aa < l; ++aa) gval = fma(-Wts[aa * k + jj], Bp[(size_t)aa * ldB + cc], gval);
+      T hv = Hp[(size_t)jj * ldH + cc];
       T p = hv > (T)0 ? gval : (gval < (T)0 ? gval : (T)0);
       s += (double)p * (double)p;
     }
@@ -885,6 +981,12 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     if (t == 0) atomicOr(a.status, ST_TIMEOUT);
     return;
   }
+  if constexpr (REGQ) {
+    for (int e = t; e < k * nc; e += NTH) {
+      const int r = e / nc, cc = e - (e / nc) * nc;
+      a.H[(size_t)r * n + c0 + cc] = Hs[r * cp + cc];
+    }
+  }
   if (g == 0) {
     for (int e = t; e < l * k; e += NTH) a.Wt[e] = Wts[e];
     if (t == 0 && a.stats) {
@@ -916,17 +1018,22 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   size_t stage = 32 * (size_t)(4 * ((k + 3) / 4));
   if (stage > red2) red2 = stage;
   if ((size_t)(LMAX + KMAX) * 8 > red2) red2 = (size_t)(LMAX + KMAX) * 8;  // T/V column staging
+  if ((size_t)(8 * 72 + 5 * LPS) + 768 * 8 / es > red2) red2 = 8 * 72 + 5 * LPS + 768 * 8 / es;  // W phase (REGQ)
 
   if ((size_t)NTH * 8 / es > red2) red2 = (size_t)NTH * 8 / es;  // pg reduction as doubles
   red2 = round_up(red2, 4);
   sh.red2_elems = (int)red2;
-  sh.alias_sv = need_pg ? 0 : 1;
-  size_t fixed = ((size_t)l * k + (size_t)l * k + (size_t)(need_pg ? 2 : 1) * k * k + LPS + sh.rows_per + red2) * es;
+  // REGQ needs the W rows and the B and H columns in LDS besides the fixed part
+  const size_t regq_extra = ((size_t)sh.rows_per * k + (size_t)(l + k) * sh.cols_per) * es;
+  const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
+  const bool regq_fits = sh.rows_per <= 64 * RQ && l <= 8 * CQ && fixed2 + regq_extra + 1024 <= (size_t)d.max_lds;
+  sh.alias_sv = (need_pg || regq_fits) ? 0 : 1;
+  size_t fixed = ((size_t)l * k + (size_t)l * k + (size_t)(sh.alias_sv ? 1 : 2) * k * k + LPS + sh.rows_per + red2) * es;
   size_t budget = (size_t)d.max_lds - 1024;  // static shared + alignment slack
   size_t qrows = fixed < budget ? (budget - fixed) / ((size_t)lq * es) : 0;
-  sh.regq = (sh.rows_per <= 64 * RQ && l <= 8 * CQ) ? 1 : 0;
+  sh.regq = regq_fits ? 1 : 0;
   sh.rows_lds = sh.regq ? 0 : (int)((size_t)sh.rows_per < qrows ? sh.rows_per : qrows);
-  sh.lds_bytes = fixed + (size_t)sh.rows_lds * lq * es;
+  sh.lds_bytes = fixed + (sh.regq ? regq_extra : (size_t)sh.rows_lds * lq * es);
   return sh;
 }
 

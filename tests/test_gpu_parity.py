@@ -146,6 +146,22 @@ def test_hals_step_one_sweep_fp32(gram, order, m, n, k, l):
     assert host(d[2]).min() >= 0 and host(d[4]).min() >= 0
 
 
+@pytest.mark.parametrize("m,n,k,l,tol", [(3000, 900, 20, 100, 0.0),      # l > 72: Q slab in LDS
+                                          (120000, 200, 8, 16, 0.0),     # > 448 rows per workgroup
+                                          (3000, 900, 20, 100, 1e-12)])  # with the stopping test
+def test_hals_step_lds_slab_path(m, n, k, l, tol):
+    Q, B, W, Wt, H = sweep_inputs(m, n, k, l, 27, np.float32)
+    d = [dev(a) for a in (Q, B, W, Wt, H)]
+    done, _, _ = rn.hals_step(*d, nsweeps=2, tol=tol)
+    assert done == 2
+    a = tuple(x.astype(np.float64) for x in (Q, B, W, Wt, H))
+    for _ in range(2):
+        a = a[:2] + o.rhals_sweep(*a)
+    assert relf(host(d[2]), a[2]) <= 2e-5
+    assert relf(host(d[3]), a[3]) <= 2e-5
+    assert relf(host(d[4]), a[4]) <= 2e-5
+
+
 @pytest.mark.parametrize("gram", ["full", "lowdim", "mixed"])
 def test_hals_step_fp64_ten_sweeps(gram):
     Q, B, W, Wt, H = sweep_inputs(500, 400, 10, 30, 22, np.float64)
