@@ -254,7 +254,7 @@ def time_to_target(rn, torch, X, Om, W0, H0, k, p, q, sweeps, ws, step, e32_fina
     return res
 
 
-def cpu_baseline(Xh, Omh, W0h, H0h, k, q, sweeps, nsweeps=3):
+def cpu_baseline(Xh, Omh, W0h, H0h, k, q, sweeps, nsweeps=80):
     """The FP64 oracle on the host's cores, on a bounded sample of the same
     workload: the full QB stage once plus `nsweeps` sweeps, scaled to the
     metric's unit (sweeps per second of a 200-sweep factorisation)."""
