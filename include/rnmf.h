@@ -88,6 +88,8 @@ enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
 #define RNMF_FLAG_NO_SHIFT 0x2u         /* no shifted Cholesky QR fallback     */
 #define RNMF_FLAG_EXACT_Q 0x4u          /* BF16: do not add one power iteration */
 #define RNMF_FLAG_TRACE 0x8u            /* rnmf_hals_step: record phase timestamps */
+#define RNMF_FLAG_SHIFTED_QR3 0x10u     /* every QR: shifted Cholesky QR pass first, then
+                                           two plain passes (shifted CholeskyQR3)   */
 
 typedef struct rnmf_opts {
   int32_t k;          /* target rank, 1 <= k < min(m, n)                        */

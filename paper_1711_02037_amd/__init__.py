@@ -32,7 +32,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 GRAM = {"full": 0, "lowdim": 1, "mixed": 2}
 ORDER = {"h_first": 0, "w_first": 1}
 OMEGA = {"gaussian": 0, "uniform": 1}
-FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE = 0x1, 0x2, 0x4, 0x8
+FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE, FLAG_SHIFTED_QR3 = 0x1, 0x2, 0x4, 0x8, 0x10
 OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR = range(5)
 
 EXPORTS = [
@@ -133,8 +133,10 @@ def make_opts(k, p=20, q=2, max_iter=200, tol=0.0, seed=0, precision="fp32", ome
     o.tol, o.seed = float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF
     o.prec, o.omega_dist = PREC[precision], OMEGA[omega]
     o.gram_mode, o.order = GRAM[gram], ORDER[order]
+    # shift: True = shifted pass only where a Gram is not positive definite,
+    # False = never, "always" = shifted CholeskyQR3 for every QR
     o.flags = (FLAG_CHECK_INPUT if check_input else 0) | (0 if shift else FLAG_NO_SHIFT) | \
-        (FLAG_EXACT_Q if exact_q else 0)
+        (FLAG_SHIFTED_QR3 if shift == "always" else 0) | (FLAG_EXACT_Q if exact_q else 0)
     return o
 
 

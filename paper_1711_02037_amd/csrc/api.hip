@@ -116,7 +116,8 @@ rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax)
   if (o->omega_dist < 0 || o->omega_dist > 1) return fail(RNMF_ERR_ARG, "unknown omega_dist %d", o->omega_dist);
   if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode %d", o->gram_mode);
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order %d", o->order);
-  if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q | RNMF_FLAG_TRACE))
+  if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q | RNMF_FLAG_TRACE |
+                   RNMF_FLAG_SHIFTED_QR3))
     return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
   if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
   int l = lwidth(o, m, n);
@@ -252,29 +253,35 @@ RelBufs plan_rel(Arena& a, int64_t m, int64_t n) {
 // Orchestration
 // ---------------------------------------------------------------------------
 
-// One Cholesky QR pass: out = in * L^{-T} where L = chol(in^T in).
+// One Cholesky QR pass: out = in * L^{-T} where L = chol(in^T in).  With
+// `skip` (the control word), the whole pass is skipped on the device when the
+// word is zero; `out` may then equal `in` (the product is row-local).
 rnmf_status qr_pass(const void* in, int64_t rows, int l, void* out, const QrBufs& qb, const Mode& md, int extra,
-                    unsigned* ctl, int allow_shift, unsigned* status, const Dev& d) {
+                    unsigned* ctl, int allow_shift, unsigned* status, const Dev& d, const unsigned* skip) {
   hipStream_t s = d.stream;
   const int lp = ceil_div(l, 16) * 16;
-  HIPCHK(launch_gram(in, md.dt, rows, l, qb.gpart, qb.gsplits, qb.G, s));
+  HIPCHK(launch_gram(in, md.dt, rows, l, qb.gpart, qb.gsplits, qb.G, s, skip));
   HIPCHK(launch_chol(qb.G, l, rows, qb.rinv, lp, md.gdt, ctl, extra ? 2 : 0, allow_shift, status, s));
   XPlan pl = plan_nn(rows, l, l, md.gdt, d.cus);
   pl.splits = 1;
-  HIPCHK(launch_nn(in, md.gdt, rows, l, l, qb.rinv, lp, l, out, nullptr, pl, status, 0, s));
+  HIPCHK(launch_nn(in, md.gdt, rows, l, l, qb.rinv, lp, l, out, nullptr, pl, status, 0, s, skip));
   return RNMF_OK;
 }
 
-// Thin QR by Cholesky QR2 (plus a leading shifted pass if needed).  `in` is
-// overwritten.  Result in `out`.
+// Thin QR by Cholesky QR2 (plus a third pass when the first needed a shift).
+// `in` is overwritten.  Result in `out`.
 rnmf_status cholqr(void* in, int64_t rows, int l, void* out, void* tmp, const QrBufs& qb, const Mode& md,
                    unsigned* ctl, int allow_shift, unsigned* status, const Dev& d) {
   HIPCHK(launch_fill_u32(ctl, 1, 0u, d.stream));
   rnmf_status r;
-  if ((r = qr_pass(in, rows, l, tmp, qb, md, 0, ctl, allow_shift, status, d)) != RNMF_OK) return r;
-  if ((r = qr_pass(tmp, rows, l, in, qb, md, 0, ctl, allow_shift, status, d)) != RNMF_OK) return r;
-  // third pass: a real pass after a shifted one, an exact copy otherwise
-  return qr_pass(in, rows, l, out, qb, md, 1, ctl, allow_shift, status, d);
+  (void)in;
+  // allow_shift: 0 never shift, 1 shift a pass whose Gram is not numerically
+  // positive definite, 2 also shift the first pass unconditionally
+  const int later = allow_shift ? 1 : 0;
+  if ((r = qr_pass(in, rows, l, tmp, qb, md, 0, ctl, allow_shift, status, d, nullptr)) != RNMF_OK) return r;
+  if ((r = qr_pass(tmp, rows, l, out, qb, md, 0, ctl, later, status, d, nullptr)) != RNMF_OK) return r;
+  // third pass, in place, only after a shifted pass (decided on the device)
+  return qr_pass(out, rows, l, out, qb, md, 1, ctl, later, status, d, ctl);
 }
 
 rnmf_status run_sketch(const void* Xc, int64_t m, int64_t n, int64_t ldx, const void* Omega, const rnmf_opts* o,
@@ -282,7 +289,7 @@ rnmf_status run_sketch(const void* Xc, int64_t m, int64_t n, int64_t ldx, const 
   hipStream_t s = d.stream;
   const int l = lwidth(o, m, n);
   const int lp = ceil_div(l, 16) * 16;
-  const int allow_shift = !(o->flags & RNMF_FLAG_NO_SHIFT);
+  const int allow_shift = (o->flags & RNMF_FLAG_NO_SHIFT) ? 0 : (o->flags & RNMF_FLAG_SHIFTED_QR3) ? 2 : 1;
   const void* om = Omega;
   if (!om) {
     HIPCHK(launch_philox(b.om, md.dt, n, l, o->seed, 3u, o->omega_dist, s));

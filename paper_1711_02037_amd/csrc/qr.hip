@@ -17,7 +17,7 @@
 namespace rnmf {
 
 int gram_splits(int64_t rows, int cus) {
-  int s = 2 * cus;
+  int s = cus;
   int maxs = (int)(rows / 64);
   if (maxs < 1) maxs = 1;
   if (s > maxs) s = maxs;
@@ -28,7 +28,8 @@ int gram_splits(int64_t rows, int cus) {
 // upper block triangle.  Rows are staged through LDS in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int64_t rows, int l, int64_t rlen,
-                                                   double* __restrict__ gpart) {
+                                                   double* __restrict__ gpart, const unsigned* skip) {
+  if (skip && *skip == 0u) return;
   constexpr int RC = 16;
   __shared__ double Ys[RC][LMAX + 4];
   const int lb = (l + 3) / 4;
@@ -91,89 +92,110 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int6
   }
 }
 
-// G[a][c] = sum over splits of the partials (upper part), mirrored; fixed order.
+// G[a][c] = sum over splits of the partials (upper part), mirrored.  A block
+// handles 32 entries; its eight thread groups add every eighth split, then the
+// eight group sums are added in group order (a fixed order).
 __global__ __launch_bounds__(256) void gram_sum_kernel(const double* __restrict__ gpart, int splits, int l,
-                                                       double* __restrict__ G) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < l * l; e += gridDim.x * blockDim.x) {
-    int a = e / l, c = e % l;
-    int lo = a < c ? a : c, hi = a < c ? c : a;
-    // a partial holds block (ba, bb) with ba <= bb: entry (lo, hi) lives in the
-    // upper block triangle unless lo and hi are in the same 4-block, where
-    // both orders were written; read (lo, hi) in either case.
-    double s = 0.0;
-    for (int p = 0; p < splits; ++p) s += gpart[(size_t)p * LMAX * LMAX + lo * LMAX + hi];
-    G[e] = s;
+                                                       double* __restrict__ G, const unsigned* skip) {
+  if (skip && *skip == 0u) return;
+  __shared__ double red[8][32];
+  const int el = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int e = blockIdx.x * 32 + el;
+  double s = 0.0;
+  if (e < l * l) {
+    const int a = e / l, c = e - (e / l) * l;
+    const int lo = a < c ? a : c, hi = a < c ? c : a;
+    // entry (lo, hi) lies in the upper block triangle that every partial holds
+    const double* src = gpart + (size_t)lo * LMAX + hi;
+    for (int p = grp; p < splits; p += 8) s += src[(size_t)p * LMAX * LMAX];
+  }
+  red[grp][el] = s;
+  __syncthreads();
+  if (grp == 0 && e < l * l) {
+    double t = red[0][el];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) t += red[g][el];
+    G[e] = t;
   }
 }
 
 hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart, int splits, double* G,
-                       hipStream_t s) {
+                       hipStream_t s, const unsigned* skip) {
   int64_t rlen = (rows + splits - 1) / splits;
   int rs = ceil_div(rows, rlen);
   if (dt == 0)
-    hipLaunchKernelGGL(gram_kernel<double>, dim3(rs), dim3(256), 0, s, (const double*)Y, rows, l, rlen, gpart);
+    hipLaunchKernelGGL(gram_kernel<double>, dim3(rs), dim3(256), 0, s, (const double*)Y, rows, l, rlen, gpart, skip);
   else
-    hipLaunchKernelGGL(gram_kernel<float>, dim3(rs), dim3(256), 0, s, (const float*)Y, rows, l, rlen, gpart);
+    hipLaunchKernelGGL(gram_kernel<float>, dim3(rs), dim3(256), 0, s, (const float*)Y, rows, l, rlen, gpart, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int blocks = ceil_div(l * l, 256);
-  hipLaunchKernelGGL(gram_sum_kernel, dim3(blocks), dim3(256), 0, s, gpart, rs, l, G);
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(ceil_div(l * l, 32)), dim3(256), 0, s, gpart, rs, l, G, skip);
   return hipGetLastError();
 }
 
-// Cholesky of G and the inverse of its factor, one workgroup.  A (LDS, l x l):
-// lower triangle = L (strict), upper triangle = L^{-1} transposed (strict),
-// with the diagonals of L and L^{-1} in dL and dX.
+// Cholesky of G and the inverse of its factor, one workgroup, FP64 in LDS.
+// Right-looking by columns: at step j the column of L is scaled, then the
+// trailing block of G and the rows of X = L^{-1} below j are updated by rank
+// one (X starts as I; X(j,:) is final once scaled by 1/L(j,j)).  Storage in A:
+// the strict lower triangle holds L, the strict upper triangle holds X
+// transposed (X(i,c) at A[c][i], c < i); dL and dX hold the diagonals.
+// Threads form a 16 x 16 grid for the rank-one updates.
 template <typename OT>
 __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G, int l, int64_t rows,
                                                    OT* __restrict__ At, int lp, unsigned* ctl, int mode,
                                                    int allow_shift, unsigned* status) {
   __shared__ double A[LMAX][LMAX + 1];
   __shared__ double dL[LMAX], dX[LMAX];
-  __shared__ int fail;
   const int t = threadIdx.x;
-  if (mode == 2 && ctl && *ctl == 0u) {
-    // no shifted pass happened: this extra pass is an exact copy
-    for (int e = t; e < lp * lp; e += 256) At[e] = (OT)((e / lp == e % lp && e / lp < l) ? 1.0 : 0.0);
-    return;
-  }
-  double trace = 0.0;
-  for (int i = 0; i < l; ++i) trace += G[i * l + i];
+  const int ti = t >> 4, tp = t & 15;
+  if (mode == 2 && ctl && *ctl == 0u) return;  // no shifted pass happened: nothing to do
+  bool fail = false;
   int shifted = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    __syncthreads();  // every thread has read `fail` of the previous attempt
+  for (int attempt = (allow_shift == 2) ? 1 : 0; attempt < 2; ++attempt) {
     shifted = attempt;
-    double shift = 0.0;
-    if (attempt == 1) {
-      const double u = 1.1102230246251565e-16;
-      shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u * trace;
-    }
     for (int e = t; e < l * l; e += 256) {
-      int i = e / l, j = e % l;
-      A[i][j] = G[e] + ((i == j) ? shift : 0.0);
+      int i = e / l, j = e - (e / l) * l;
+      A[i][j] = (j <= i) ? G[e] : 0.0;
     }
-    if (t == 0) fail = 0;
+    for (int i = t; i < l; i += 256) dX[i] = 1.0;
     __syncthreads();
+    if (attempt == 1) {
+      double trace = 0.0;
+      for (int i = 0; i < l; ++i) trace += A[i][i];
+      const double u = 1.1102230246251565e-16;
+      const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u * trace;
+      __syncthreads();
+      for (int i = t; i < l; i += 256) A[i][i] += shift;
+      __syncthreads();
+    }
+    fail = false;
     for (int j = 0; j < l; ++j) {
-      double d = A[j][j];
-      if (!(d > 0.0) || !(d < INFINITY)) {
-        if (t == 0) fail = 1;
+      const double d = A[j][j];  // same value in every thread: the branch is uniform
+      if (!(d > 0.0) || !(d < INFINITY)) { fail = true; break; }
+      const double r = sqrt(d), ri = 1.0 / r;
+      const int w = l - j - 1;
+      if (t < w) A[j + 1 + t][j] *= ri;
+      if (t >= 128 && t - 128 <= j) {  // X(j, c) /= L(j, j), c <= j
+        const int c = t - 128;
+        if (c < j) A[c][j] *= ri;
+        else dX[j] *= ri;
       }
-      __syncthreads();
-      if (fail) break;
-      double r = sqrt(d);
       if (t == 0) dL[j] = r;
-      for (int i = j + 1 + t; i < l; i += 256) A[i][j] /= r;
       __syncthreads();
-      const int w = l - j - 1;  // trailing size
-      for (int e = t; e < w * w; e += 256) {
-        int i = j + 1 + e / w, p = j + 1 + e % w;
-        if (p <= i) A[i][p] -= A[i][j] * A[p][j];
+      for (int i = j + 1 + ti; i < l; i += 16) {
+        const double lij = A[i][j];
+        for (int p = j + 1 + tp; p <= i; p += 16) A[i][p] -= lij * A[p][j];
+        for (int c = tp; c <= j; c += 16) {
+          const double xjc = (c < j) ? A[c][j] : dX[j];
+          if (c < j) A[c][i] -= lij * xjc;
+          else A[j][i] -= lij * xjc;
+        }
       }
       __syncthreads();
     }
     if (!fail) break;
-    if (attempt == 0 && !allow_shift) break;
+    if (!allow_shift) break;
+    __syncthreads();
   }
   if (fail) {
     if (t == 0) atomicOr(status, ST_NOT_SPD);
@@ -185,19 +207,9 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G,
     atomicOr(status, ST_SHIFTED);
     if (ctl) atomicOr(ctl, 1u);
   }
-  // L^{-1}: row by row, X[i][c] = -(sum_{p=c}^{i-1} L[i][p] X[p][c]) / L[i][i]
-  for (int i = 0; i < l; ++i) {
-    if (t == 0) dX[i] = 1.0 / dL[i];
-    for (int c = t; c < i; c += 256) {
-      double s = A[i][c] * dX[c];
-      for (int p = c + 1; p < i; ++p) s += A[i][p] * A[c][p];
-      A[c][i] = -s / dL[i];
-    }
-    __syncthreads();
-  }
-  // At[c][k] = L^{-1}[c][k] for k <= c, zero elsewhere (lp x lp, packed)
+  // At[c][k] = X(c, k) for k <= c, zero elsewhere (lp x lp, packed)
   for (int e = t; e < lp * lp; e += 256) {
-    int c = e / lp, k = e % lp;
+    int c = e / lp, k = e - (e / lp) * lp;
     double v = 0.0;
     if (c < l && k < l) {
       if (k == c) v = dX[c];

@@ -83,7 +83,8 @@ XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus);
 XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus);
 hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* At,
                      int64_t ldat, int l, void* Y, void* part, const XPlan& pl,
-                     unsigned* status, int check, hipStream_t s);
+                     unsigned* status, int check, hipStream_t s,
+                     const unsigned* skip = nullptr);
 // Z = X^T Q: writes Z (n x l) if !transposed, else Z^T (l x n).
 hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt,
                      int64_t ldqt, int l, void* Z, int transposed, void* part,
@@ -92,7 +93,7 @@ hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
 // qr.hip: Cholesky QR pass pieces.
 int gram_splits(int64_t rows, int cus);
 hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart, int splits,
-                       double* G, hipStream_t s);
+                       double* G, hipStream_t s, const unsigned* skip = nullptr);
 // One workgroup: Cholesky of G (l x l, FP64) with optional shift; writes the
 // transposed inverse factor packed for the GEMM (lp x lp, dtype cdt) and
 // updates flags.  `pass_ctl`: 0 first pass of a pair, 1 second pass, 2 extra.

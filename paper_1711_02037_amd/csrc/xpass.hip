@@ -158,7 +158,9 @@ template <int NT, int VW, int RW>
 __global__ __launch_bounds__(256) void nn_f32_kernel(const float* __restrict__ X, int64_t m, int64_t n,
                                                      int64_t ldx, const float* __restrict__ At, int64_t ldat,
                                                      int l, float* __restrict__ Y, float* __restrict__ part,
-                                                     int64_t klen, unsigned* status, int check) {
+                                                     int64_t klen, unsigned* status, int check,
+                                                     const unsigned* skip) {
+  if (skip && *skip == 0u) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int64_t row_base = (int64_t)blockIdx.x * (64 * RW) + wave * (16 * RW);
@@ -504,7 +506,8 @@ template <typename XT, typename CT, typename AT, int NT>
 __global__ __launch_bounds__(256) void nn_valu_kernel(const XT* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                       const AT* __restrict__ At, int64_t ldat, int lp_all, int l,
                                                       CT* __restrict__ Y, CT* __restrict__ part, int64_t klen,
-                                                      unsigned* status, int check) {
+                                                      unsigned* status, int check, const unsigned* skip) {
+  if (skip && *skip == 0u) return;
   constexpr int KC = 16;
   __shared__ CT Xs[64][KC + 1];
   __shared__ CT As[KC][NT * 16 + 1];
@@ -732,7 +735,8 @@ XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus) {
   }
 
 hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* At, int64_t ldat,
-                     int l, void* Y, void* part, const XPlan& pl, unsigned* status, int check, hipStream_t s) {
+                     int l, void* Y, void* part, const XPlan& pl, unsigned* status, int check, hipStream_t s,
+                     const unsigned* skip) {
   const int ntile = ceil_div(l, 16);
   const int lp = ntile * 16;
   const int splits = pl.splits;
@@ -744,13 +748,13 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
     int vw = vec_width(X, ldx, 4);
     if (vw == 4) {
       NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 4, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
-                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check, skip));
     } else if (vw == 2) {
       NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 2, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
-                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check, skip));
     } else {
       NT_SWITCH(ntile, hipLaunchKernelGGL((nn_f32_kernel<NT, 1, 2>), grid, dim3(256), 0, s, (const float*)X, m, n,
-                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check));
+                                          ldx, (const float*)At, ldat, l, (float*)Y, pp, klen, status, check, skip));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || rs == 1) return e;
@@ -768,7 +772,7 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
       dim3 g2((unsigned)ceil_div(m, 64), (unsigned)rs);
       NT_SWITCH(ntile, hipLaunchKernelGGL((nn_valu_kernel<bf16_t, float, bf16_t, NT>), g2, dim3(256), 0, s,
                                           (const bf16_t*)X, m, n, ldx, (const bf16_t*)At, ldat, lp, l, (float*)Y,
-                                          pp, klen, status, 0));
+                                          pp, klen, status, 0, skip));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || rs == 1) return e;
@@ -781,7 +785,7 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
   double* pp = rs > 1 ? (double*)part : nullptr;
   NT_SWITCH(ntile, hipLaunchKernelGGL((nn_valu_kernel<double, double, double, NT>), grid, dim3(256), 0, s,
                                       (const double*)X, m, n, ldx, (const double*)At, ldat, lp, l, (double*)Y,
-                                      pp, klen, status, check));
+                                      pp, klen, status, check, skip));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || rs == 1) return e;
   return launch_reduce<double, double>((const double*)part, rs, m, l, lp, (double*)Y, 0, s);

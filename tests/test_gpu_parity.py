@@ -319,3 +319,40 @@ def test_exactly_low_rank_input_gives_a_valid_basis():
     W, H, info = rn.factorize(dev(X), 3, 5, 1, max_iter=300, precision="fp64", seed=3)
     assert host(W).min() >= 0 and host(H).min() >= 0
     assert info["rel_err"] < 1e-3
+
+
+def test_exactly_low_rank_fp32_gives_a_valid_basis():
+    # rank 3 < l = 8 in FP32: rounding in Y = X Omega keeps the Gram numerically
+    # positive definite, and Cholesky QR2 still returns an orthonormal basis
+    # that captures range(X) to FP32 accuracy.
+    m, n, r = 3000, 500, 3
+    g = s.stream(41, 0)
+    X = (g.random((m, r)) @ g.random((r, n))).astype(np.float32)
+    Q = host(rn.sketch(dev(X), 3, 5, 1, precision="fp32", seed=5))
+    l = Q.shape[1]
+    assert np.linalg.norm(Q.T @ Q - np.eye(l)) <= 1e-5
+    Xd = X.astype(np.float64)
+    assert np.linalg.norm(Xd - Q @ (Q.T @ Xd)) / np.linalg.norm(Xd) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_shifted_cholesky_qr3_matches_oracle_basis(prec, tol):
+    # shifted pass first, then two plain passes (the third runs in place):
+    # the basis is the same thin QR, so it spans the oracle's subspace
+    m, n, k, p, q = 4000, 900, 12, 8, 1
+    dt = np.float64 if prec == "fp64" else np.float32
+    X, Om, _, _ = problem(m, n, 20, k, p, 45, dtype=dt)
+    Q = host(rn.sketch(dev(X), k, p, q, omega=dev(Om), precision=prec, shift="always"))
+    Qo = o.range_finder(X.astype(np.float64), Om.astype(np.float64), q)
+    l = Q.shape[1]
+    assert np.linalg.norm(Q.T @ Q - np.eye(l)) <= tol
+    assert np.linalg.norm(Q @ Q.T @ Qo - Qo) / np.linalg.norm(Qo) <= 100 * tol
+    _, _, info = rn.factorize(dev(X), k, p, q, max_iter=3, precision=prec, omega=dev(Om), shift="always")
+    assert info["shifted_qr"]
+
+
+def test_well_conditioned_sketch_needs_no_shift():
+    X, Om, W0, H0 = problem(2000, 700, 10, 10, 10, 43)
+    _, _, info = rn.factorize(dev(X), 10, 10, 1, max_iter=2, precision="fp32", omega=dev(Om), W0=dev(W0),
+                              H0=dev(H0))
+    assert not info["shifted_qr"]
