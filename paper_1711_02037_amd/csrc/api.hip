@@ -178,7 +178,7 @@ struct SketchBufs {
 SketchBufs plan_sketch(Arena& a, int64_t m, int64_t n, int l, const Mode& md, const Dev& d) {
   SketchBufs b;
   const int lp = ceil_div(l, 16) * 16;
-  b.ldp = (int64_t)round_up((size_t)(m > n ? m : n), 16);
+  b.ldp = (int64_t)round_up((size_t)(m > n ? m : n), 64);  // streamed NN reads whole 64-wide stages
   b.om = a.take<char>((size_t)n * l * md.es);
   b.at = a.take<char>((size_t)lp * b.ldp * (md.cdt == 0 ? 8 : 4));  // bf16: two planes of 2 bytes
   b.y = a.take<char>((size_t)m * l * md.es);

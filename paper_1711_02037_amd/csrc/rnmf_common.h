@@ -76,8 +76,12 @@ hipError_t launch_pack_t(const void* src, int dt, int64_t rows, int cols, int lp
 // Y (m x l) = X (m x n) * A, with At = A^T packed (lp x ldat).  Output in dt
 // (float or double).  Split-K partials in `part` (float or double) if needed.
 struct XPlan {
-  int splits;
-  size_t part_elems;
+  int splits;           // reduction splits of the register-blocked kernels
+  size_t part_elems;    // partial-sum elements the workspace must hold
+  int use2 = 0;         // streamed NN kernel applicable (FP32/BF16, l <= 128)
+  int g2 = 0, s2 = 0;   // its row groups and reduction splits
+  int64_t klen2 = 0;    // reduction length per split
+  size_t lds2 = 0;      // its LDS bytes
 };
 XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus);
 XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus);

@@ -336,6 +336,173 @@ __global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// NN, streamed form (FP32 or BF16 X, 16-byte aligned rows).  Total bytes that
+// enter the CUs (X from HBM plus the small operand from L2) bound these
+// passes, so a workgroup of 8 waves owns a contiguous range of 16-row tiles
+// (about m / #CUs rows) and reads the small operand once per pass.  X and
+// operand fragments travel by direct global->LDS loads, one 1 KB wave
+// fragment per instruction, double-buffered by stage; the fragment a lane
+// loads is exactly the MFMA fragment it later reads back, so LDS reads are
+// conflict-free 16-byte reads.
+//   BF16: fragment = 16 rows x 32 k (8 per lane); two operand planes.
+//   FP32: fragment = 16 rows x 16 k (4 per lane: MFMA s uses k = 4g + s).
+// Stage = KU fragments along k.  Wave w owns tiles w, w + 8, ... of the range.
+// ---------------------------------------------------------------------------
+#define RNMF_GPTR(p) ((const __attribute__((address_space(1))) void*)(p))
+#define RNMF_LPTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only: outstanding global loads stay in flight
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename E, int NT, int KU, int RWMAX>
+__global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                  const E* __restrict__ At, int64_t ldat, int lp_all, int l,
+                                                  float* __restrict__ Y, float* __restrict__ part, int64_t klen,
+                                                  int tiles, int G, unsigned* status, int check,
+                                                  const unsigned* skip) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char nn2_lds[];
+  if (skip && *skip == 0u) return;
+  constexpr bool BF = sizeof(E) == 2;
+  constexpr int KS = BF ? 32 : 16;       // k per fragment
+  constexpr int EPC = BF ? 8 : 4;        // elements per lane chunk (16 bytes)
+  constexpr int NPL = BF ? 2 : 1;        // operand planes
+  constexpr int AF = NPL * NT * KU;      // operand fragments per stage
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, gq = lane >> 4;
+  const int gidx = blockIdx.x;
+  const int t0 = (int)((int64_t)tiles * gidx / G), t1 = (int)((int64_t)tiles * (gidx + 1) / G);
+  const int nt = t1 - t0;               // tiles of this workgroup, <= 8 * RWMAX
+  const int XF = nt * KU;               // X fragments per stage
+  const int F = XF + AF;
+  const int64_t kb = (int64_t)blockIdx.y * klen;
+  const int64_t ke = (kb + klen < n) ? kb + klen : n;
+  const int nst = (int)((ke - kb + KS * KU - 1) / (KS * KU));
+  const int64_t plane = (int64_t)lp_all * ldat;
+  floatx4 acc[RWMAX][NT];
+#pragma unroll
+  for (int a = 0; a < RWMAX; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  auto issue = [&](int st) {
+    const int64_t k = kb + (int64_t)st * KS * KU;
+    unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
+    for (int f = wave; f < F; f += 8) {
+      const E* src;
+      if (f < XF) {
+        const int tau = f / KU, u = f - (f / KU) * KU;
+        int64_t r = (int64_t)(t0 + tau) * 16 + i;
+        if (r >= m) r = m - 1;
+        int64_t c = k + u * KS + gq * EPC;
+        if (c >= ke) c = 0;              // valid address; zeroed after arrival
+        src = X + r * ldx + c;
+      } else {
+        const int a = f - XF;
+        const int pl = a / (NT * KU), rem = a - pl * (NT * KU);
+        const int ct = rem / KU, u = rem - (rem / KU) * KU;
+        src = At + pl * plane + (int64_t)(ct * 16 + i) * ldat + k + u * KS + gq * EPC;
+      }
+      __builtin_amdgcn_global_load_lds(RNMF_GPTR(src), RNMF_LPTR(base + (size_t)f * 1024), 16, 0, 0);
+    }
+  };
+  // zero the X elements at or beyond ke in this lane's own chunks (tail stage)
+  auto patch = [&](int st) {
+    const int64_t k = kb + (int64_t)st * KS * KU;
+    unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
+    for (int f = wave; f < XF; f += 8) {
+      const int u = f - (f / KU) * KU;
+      const int64_t c = k + u * KS + gq * EPC;
+      if (c + EPC > ke) {
+        E* dst = (E*)(base + (size_t)f * 1024 + lane * 16);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e)
+          if (c + e >= ke) dst[e] = (E)0;
+      }
+    }
+  };
+
+  unsigned flag = 0;
+  if (nst > 0) issue(0);
+  for (int st = 0; st < nst; ++st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this stage has landed (only it is in flight)
+    const int64_t k = kb + (int64_t)st * KS * KU;
+    if (k + KS * KU > ke) patch(st);
+    lds_barrier();
+    if (st + 1 < nst) issue(st + 1);
+    const unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k + u * KS >= ke) break;
+      if constexpr (BF) {
+        bf16x8 xa[RWMAX];
+#pragma unroll
+        for (int rt = 0; rt < RWMAX; ++rt) {
+          const int tau = wave + 8 * rt;
+          if (tau < nt) xa[rt] = *(const bf16x8*)(base + (size_t)(tau * KU + u) * 1024 + lane * 16);
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const bf16x8 h = *(const bf16x8*)(base + (size_t)(XF + ct * KU + u) * 1024 + lane * 16);
+          const bf16x8 lo = *(const bf16x8*)(base + (size_t)(XF + (NT + ct) * KU + u) * 1024 + lane * 16);
+#pragma unroll
+          for (int rt = 0; rt < RWMAX; ++rt)
+            if (wave + 8 * rt < nt) {
+              acc[rt][ct] = mfma_bf(xa[rt], h, acc[rt][ct]);
+              acc[rt][ct] = mfma_bf(xa[rt], lo, acc[rt][ct]);
+            }
+        }
+      } else {
+        floatx4 xa[RWMAX];
+#pragma unroll
+        for (int rt = 0; rt < RWMAX; ++rt) {
+          const int tau = wave + 8 * rt;
+          if (tau < nt) {
+            xa[rt] = *(const floatx4*)(base + (size_t)(tau * KU + u) * 1024 + lane * 16);
+            if (check)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) flag |= scan_f32(xa[rt][e]);
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const floatx4 av = *(const floatx4*)(base + (size_t)(XF + ct * KU + u) * 1024 + lane * 16);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int rt = 0; rt < RWMAX; ++rt)
+              if (wave + 8 * rt < nt) acc[rt][ct] = mfma4(xa[rt][e], av[e], acc[rt][ct]);
+        }
+      }
+    }
+  }
+  if (check && __ballot(flag != 0)) {
+    for (int o = 32; o > 0; o >>= 1) flag |= __shfl_xor(flag, o);
+    if (lane == 0 && flag) atomicOr(status, flag);
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int rt = 0; rt < RWMAX; ++rt) {
+    const int tau = wave + 8 * rt;
+    if (tau >= nt) continue;
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = (int64_t)(t0 + tau) * 16 + 4 * gq + e;
+        const int c = ct * 16 + i;
+        if (r < m && c < l) {
+          if (part) part[((int64_t)blockIdx.y * m + r) * lp + c] = acc[rt][ct][e];
+          else Y[r * l + c] = acc[rt][ct][e];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // TN, FP32 matrix cores.  Each wave owns 16 * VW columns of X; lane (i, g)
 // loads rows m0 + 4g + s (s < 4) x VW columns; MFMA (s, c) uses row 4g + s
 // and column VW * i + c, paired with Qt rows t * 16 + i at m0 + 4g + s.
@@ -690,6 +857,51 @@ static int vec_width(const void* X, int64_t ldx, int esize) {
   return 1;
 }
 
+// Streamed NN (nn2_kernel) plan: G row groups x S reduction splits.  The
+// bytes entering the CUs are X once, the small operand once per row group,
+// and the split partials written and read back; a plan that leaves CUs idle
+// or needs a second round of workgroups is charged for it.
+static constexpr int NN2_KU = 2, NN2_RWMAX = 4, NN2_LDS_KB = 160;
+
+static void plan_nn2(XPlan& p, int64_t m, int64_t n, int l, int cdt, int cus) {
+  p.use2 = 0;
+  const int nt = ceil_div(l, 16);
+  if (!(cdt == 1 || cdt == 2) || nt > 8 || m < 16) return;
+  const int lp = nt * 16;
+  const int ks = (cdt == 2) ? 32 : 16, stage = ks * NN2_KU;
+  const int af = (cdt == 2 ? 2 : 1) * nt * NN2_KU;
+  int ntmax = (NN2_LDS_KB / 2 - af) / NN2_KU;
+  if (ntmax > 8 * NN2_RWMAX) ntmax = 8 * NN2_RWMAX;
+  if (ntmax < 1) return;
+  const int64_t tiles = ceil_div(m, 16);
+  const int64_t gmin = ceil_div(tiles, ntmax);
+  const double xbytes = (double)m * n * (cdt == 2 ? 2 : 4);
+  const double abytes = (double)n * lp * 4.0;
+  double best = 0.0;
+  for (int sp = 1; sp <= 16; ++sp) {
+    if (sp > 1 && n < (int64_t)sp * stage * 2) break;
+    int64_t g = cus / sp;
+    if (g < gmin) g = gmin;
+    if (g > tiles) g = tiles;
+    if (g < 1) g = 1;
+    const int64_t klen = round_up((size_t)ceil_div(n, sp), (size_t)stage);
+    const int se = (int)ceil_div(n, klen);
+    const int64_t wgs = g * se;
+    const int64_t rounds = ceil_div(wgs, cus);
+    const double util = (double)wgs / (double)(rounds * cus);
+    const double bytes = xbytes + (double)g * abytes + (se > 1 ? 2.0 * se * m * lp * 4.0 : 0.0);
+    const double cost = bytes / util;
+    if (!p.use2 || cost < best) {
+      best = cost;
+      p.use2 = 1;
+      p.g2 = (int)g;
+      p.s2 = se;
+      p.klen2 = klen;
+      p.lds2 = (size_t)2 * ((size_t)ceil_div(tiles, g) * NN2_KU + af) * 1024;
+    }
+  }
+}
+
 XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus) {
   XPlan p;
   const int lp = ceil_div(l, 16) * 16;
@@ -703,6 +915,11 @@ XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus) {
   if (splits > 64) splits = 64;
   p.splits = splits;
   p.part_elems = splits > 1 ? (size_t)splits * (size_t)m * (size_t)lp : 0;
+  plan_nn2(p, m, n, l, cdt, cus);
+  if (p.use2 && p.s2 > 1) {
+    size_t e2 = (size_t)p.s2 * (size_t)m * (size_t)lp;
+    if (e2 > p.part_elems) p.part_elems = e2;
+  }
   return p;
 }
 
@@ -734,12 +951,43 @@ XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus) {
     default: { constexpr int NT = 8; CALL; } break; \
   }
 
+template <typename E, int NT>
+static hipError_t launch_nn2_t(dim3 grid, const XPlan& pl, hipStream_t s, const E* X, int64_t m, int64_t n,
+                               int64_t ldx, const E* At, int64_t ldat, int lp, int l, float* Y, float* part,
+                               int tiles, unsigned* status, int check, const unsigned* skip) {
+  auto fn = nn2_kernel<E, NT, NN2_KU, NN2_RWMAX>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, grid, dim3(512), pl.lds2, s, X, m, n, ldx, At, ldat, lp, l, Y, part, pl.klen2, tiles,
+                     pl.g2, status, check, skip);
+  return hipGetLastError();
+}
+
 hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* At, int64_t ldat,
                      int l, void* Y, void* part, const XPlan& pl, unsigned* status, int check, hipStream_t s,
                      const unsigned* skip) {
   const int ntile = ceil_div(l, 16);
   const int lp = ntile * 16;
   const int splits = pl.splits;
+  if (pl.use2 && (cdt == 1 || cdt == 2) && ldat % 64 == 0 &&
+      ((cdt == 1 && vec_width(X, ldx, 4) == 4) || (cdt == 2 && ldx % 8 == 0 && ((uintptr_t)X % 16) == 0))) {
+    const int rs = pl.s2;
+    dim3 grid((unsigned)pl.g2, (unsigned)rs);
+    float* pp = rs > 1 ? (float*)part : nullptr;
+    const int tiles = (int)ceil_div(m, 16);
+    hipError_t e0;
+    if (cdt == 1) {
+      NT_SWITCH(ntile, e0 = (launch_nn2_t<float, NT>)(grid, pl, s, (const float*)X, m, n, ldx, (const float*)At, ldat,
+                                                    lp, l, (float*)Y, pp, tiles, status, check, skip));
+    } else {
+      NT_SWITCH(ntile, e0 = (launch_nn2_t<bf16_t, NT>)(grid, pl, s, (const bf16_t*)X, m, n, ldx, (const bf16_t*)At,
+                                                     ldat, lp, l, (float*)Y, pp, tiles, status, 0, skip));
+    }
+    if (e0 != hipSuccess) return e0;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || rs == 1) return e;
+    return launch_reduce<float, float>((const float*)part, rs, m, l, lp, (float*)Y, 0, s);
+  }
   if (cdt == 1) {
     const int64_t klen = round_up((size_t)ceil_div(n, splits), 16);
     const int rs = ceil_div(n, klen);

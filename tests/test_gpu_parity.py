@@ -356,3 +356,33 @@ def test_well_conditioned_sketch_needs_no_shift():
     _, _, info = rn.factorize(dev(X), 10, 10, 1, max_iter=2, precision="fp32", omega=dev(Om), W0=dev(W0),
                               H0=dev(H0))
     assert not info["shifted_qr"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m,n,ld,k,p", [(500, 400, 400, 10, 20), (3001, 2410, 2432, 16, 20),
+                                        (5003, 1711, 1728, 50, 20), (20007, 333, 384, 8, 8)])
+def test_sketch_pass_spans_x_omega(prec, m, n, ld, k, p):
+    # with q = 0, Q = qr(X Omega): every column of X Omega (computed here in
+    # FP64 from the same rounded inputs) must lie in span(Q).  An error in the
+    # streamed product (a lost tail, a wrong split or tile) shows up directly.
+    # Shapes: ragged m, ragged n inside a padded row (ld > n), one to several
+    # reduction splits.
+    g = s.stream(47, m, n)
+    Xf = np.zeros((m, ld), dtype=np.float32)
+    Xf[:, :n] = g.random((m, n), dtype=np.float32)
+    Xf[:, n:] = np.nan                       # padding must never be read as data
+    l = s.sketch_cols(k, p, m, n)
+    Om = g.standard_normal((n, l)).astype(np.float32)
+    Xd = dev(Xf)
+    if prec == "bf16":
+        Xd = Xd.to(torch.bfloat16)[:, :n]     # round to nearest even, padded rows
+        Xh = host(Xd)
+    else:
+        Xd = Xd[:, :n]
+        Xh = Xf[:, :n].astype(np.float64)
+    # exact_q: the BF16 form would otherwise add one subspace iteration
+    Q = host(rn.sketch(Xd, k, p, 0, omega=dev(Om), precision=prec, exact_q=True))
+    Y = Xh @ Om.astype(np.float64)
+    err = np.linalg.norm(Y - Q @ (Q.T @ Y)) / np.linalg.norm(Y)
+    assert err <= 2e-6, err
+    assert np.linalg.norm(Q.T @ Q - np.eye(l)) <= 1e-5
