@@ -204,7 +204,7 @@ struct CompressBufs {
 CompressBufs plan_compress(Arena& a, int64_t m, int64_t n, int l, const Mode& md, const Dev& d) {
   CompressBufs b;
   const int lp = ceil_div(l, 16) * 16;
-  b.ldp = (int64_t)round_up((size_t)m, 16);
+  b.ldp = (int64_t)round_up((size_t)m, 64);  // streamed TN reads whole 32-row stages
   b.at = a.take<char>((size_t)lp * b.ldp * (md.cdt == 0 ? 8 : 4));
   b.tn = plan_tn(m, n, l, md.cdt, d.cus);
   b.part = a.take<char>(b.tn.part_elems * (md.cdt == 0 ? 8 : 4));
@@ -220,7 +220,7 @@ struct InitBufs {
 InitBufs plan_init(Arena& a, int64_t m, int k, int l, const Mode& md, const Dev& d) {
   InitBufs b;
   const int lp = ceil_div(l, 16) * 16;
-  b.ldp = (int64_t)round_up((size_t)m, 16);
+  b.ldp = (int64_t)round_up((size_t)m, 64);
   b.at = a.take<char>((size_t)lp * b.ldp * md.es);
   b.tn = plan_tn(m, k, l, md.dt, d.cus);
   b.part = a.take<char>(b.tn.part_elems * md.es);

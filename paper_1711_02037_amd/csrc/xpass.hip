@@ -398,7 +398,7 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
         int64_t r = (int64_t)(t0 + tau) * 16 + i;
         if (r >= m) r = m - 1;
         int64_t c = k + u * KS + gq * EPC;
-        if (c >= ke) c = 0;              // valid address; zeroed after arrival
+        if (c >= ke || c + EPC > n) c = 0;  // in-bounds address; fixed up after arrival
         src = X + r * ldx + c;
       } else {
         const int a = f - XF;
@@ -409,18 +409,23 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
       __builtin_amdgcn_global_load_lds(RNMF_GPTR(src), RNMF_LPTR(base + (size_t)f * 1024), 16, 0, 0);
     }
   };
-  // zero the X elements at or beyond ke in this lane's own chunks (tail stage)
+  // tail stage: in this lane's own chunks, zero the elements at or beyond ke
+  // and load element by element a chunk that runs past the end of the row
   auto patch = [&](int st) {
     const int64_t k = kb + (int64_t)st * KS * KU;
     unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
     for (int f = wave; f < XF; f += 8) {
-      const int u = f - (f / KU) * KU;
+      const int tau = f / KU, u = f - (f / KU) * KU;
       const int64_t c = k + u * KS + gq * EPC;
       if (c + EPC > ke) {
+        int64_t r = (int64_t)(t0 + tau) * 16 + i;
+        if (r >= m) r = m - 1;
+        const bool reload = c < ke && c + EPC > n;
         E* dst = (E*)(base + (size_t)f * 1024 + lane * 16);
 #pragma unroll
         for (int e = 0; e < EPC; ++e)
           if (c + e >= ke) dst[e] = (E)0;
+          else if (reload) dst[e] = X[r * ldx + c + e];
       }
     }
   };
@@ -500,6 +505,154 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
         }
       }
   }
+}
+
+// ---------------------------------------------------------------------------
+// TN, streamed form: Z = X^T Q over a row split, for a block of 512 columns
+// (8 waves x 64).  Each stage is 32 rows: X arrives row-major in LDS by
+// direct loads of whole 1 KB row segments, Q^T fragments (packed transposed,
+// zero beyond m) arrive in fragment layout.  Lane (i, g) of a wave owns
+// columns c + 4i + j (j < 4).
+//   BF16: MFMA depth 32 rows; the lane reads rows 8g + e (e < 8) x 4 columns
+//         with 8-byte LDS reads and regroups them into four B fragments.
+//   FP32: two MFMA groups of 16 rows; the lane reads rows 4g + s (s < 4) x 4
+//         columns with 16-byte LDS reads; each value is one MFMA operand.
+// ---------------------------------------------------------------------------
+template <typename E, int NT>
+__global__ __launch_bounds__(512) void tn2_kernel(const E* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                  const E* __restrict__ Qt, int64_t ldqt, int lp_all,
+                                                  float* __restrict__ part, int64_t mlen) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char tn2_lds[];
+  constexpr bool BF = sizeof(E) == 2;
+  constexpr int SR = 32;                       // rows per stage
+  constexpr int EPC = BF ? 8 : 4;              // elements per 16-byte chunk
+  constexpr int RB = 512 * (int)sizeof(E);     // bytes of one row of the block
+  constexpr int PITCH = RB + 16;               // LDS row pitch
+  constexpr int XI = SR * (RB / 1024);         // X load instructions per stage
+  constexpr int QF = (BF ? 2 : 1) * NT * (BF ? 1 : 2);  // Q fragments per stage (1 KB each)
+  constexpr int FI = XI + QF;
+  constexpr int SLOT = SR * PITCH + QF * 1024;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, gq = lane >> 4;
+  const int64_t cb = (int64_t)blockIdx.x * 512;
+  const int64_t mb = (int64_t)blockIdx.y * mlen;
+  const int64_t me = (mb + mlen < m) ? mb + mlen : m;
+  const int nst = (int)((me - mb + SR - 1) / SR);
+  const int64_t plane = (int64_t)lp_all * ldqt;
+  floatx4 acc[NT][4];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  auto issue = [&](int st) {
+    const int64_t r0 = mb + (int64_t)st * SR;
+    unsigned char* base = tn2_lds + (size_t)(st & 1) * SLOT;
+    for (int f = wave; f < FI; f += 8) {
+      if (f < XI) {
+        const int rr = f / (RB / 1024), pp = f - (f / (RB / 1024)) * (RB / 1024);
+        int64_t r = r0 + rr;
+        if (r >= m) r = m - 1;
+        int64_t c = cb + (int64_t)pp * (1024 / (int)sizeof(E)) + lane * EPC;
+        if (c + EPC > n) c = 0;  // in-bounds address; a straddling chunk is reloaded
+        __builtin_amdgcn_global_load_lds(RNMF_GPTR(X + r * ldx + c),
+                                         RNMF_LPTR(base + (size_t)rr * PITCH + (size_t)pp * 1024), 16, 0, 0);
+      } else {
+        const int a = f - XI;
+        const E* src;
+        if constexpr (BF) {
+          const int pl = a / NT, t = a - (a / NT) * NT;   // fragment: 16 l x 32 rows
+          src = Qt + pl * plane + (int64_t)(t * 16 + i) * ldqt + r0 + 8 * gq;
+        } else {
+          const int h = a / NT, t = a - (a / NT) * NT;    // fragment: 16 l x 16 rows
+          src = Qt + (int64_t)(t * 16 + i) * ldqt + r0 + 16 * h + 4 * gq;
+        }
+        __builtin_amdgcn_global_load_lds(RNMF_GPTR(src), RNMF_LPTR(base + (size_t)SR * PITCH + (size_t)a * 1024),
+                                         16, 0, 0);
+      }
+    }
+  };
+  // a chunk that runs past the end of the row: load its valid elements one by one
+  auto patch = [&](int st) {
+    const int64_t r0 = mb + (int64_t)st * SR;
+    unsigned char* base = tn2_lds + (size_t)(st & 1) * SLOT;
+    for (int f = wave; f < XI; f += 8) {
+      const int rr = f / (RB / 1024), pp = f - (f / (RB / 1024)) * (RB / 1024);
+      const int64_t c = cb + (int64_t)pp * (1024 / (int)sizeof(E)) + lane * EPC;
+      if (c < n && c + EPC > n) {
+        int64_t r = r0 + rr;
+        if (r >= m) r = m - 1;
+        E* dst = (E*)(base + (size_t)rr * PITCH + (size_t)pp * 1024 + lane * 16);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) dst[e] = (c + e < n) ? X[r * ldx + c + e] : (E)0;
+      }
+    }
+  };
+
+  const bool edge = cb + 512 > n && (n % EPC) != 0;
+  if (nst > 0) issue(0);
+  for (int st = 0; st < nst; ++st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this stage has landed (only it is in flight)
+    if (edge) patch(st);
+    lds_barrier();
+    if (st + 1 < nst) issue(st + 1);
+    const unsigned char* base = tn2_lds + (size_t)(st & 1) * SLOT;
+    const unsigned char* qb = base + (size_t)SR * PITCH;
+    const int cofs = (wave * 64 + 4 * i) * (int)sizeof(E);
+    if constexpr (BF) {
+      typedef unsigned uint2v __attribute__((ext_vector_type(2)));
+      uint2v xv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xv[e] = *(const uint2v*)(base + (size_t)(8 * gq + e) * PITCH + cofs);
+      bf16x8 b[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const unsigned a0 = xv[2 * d].x, a1 = xv[2 * d + 1].x, b0 = xv[2 * d].y, b1 = xv[2 * d + 1].y;
+        typedef unsigned uint4v __attribute__((ext_vector_type(4)));
+        // column j of rows 2d, 2d + 1 packed into one dword of fragment j
+        const unsigned w0 = (a0 & 0xFFFFu) | (a1 << 16), w1 = (a0 >> 16) | (a1 & 0xFFFF0000u);
+        const unsigned w2 = (b0 & 0xFFFFu) | (b1 << 16), w3 = (b0 >> 16) | (b1 & 0xFFFF0000u);
+        uint4v t0 = __builtin_bit_cast(uint4v, b[0]), t1 = __builtin_bit_cast(uint4v, b[1]);
+        uint4v t2 = __builtin_bit_cast(uint4v, b[2]), t3 = __builtin_bit_cast(uint4v, b[3]);
+        t0[d] = w0; t1[d] = w1; t2[d] = w2; t3[d] = w3;
+        b[0] = __builtin_bit_cast(bf16x8, t0); b[1] = __builtin_bit_cast(bf16x8, t1);
+        b[2] = __builtin_bit_cast(bf16x8, t2); b[3] = __builtin_bit_cast(bf16x8, t3);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x8 h = *(const bf16x8*)(qb + (size_t)t * 1024 + lane * 16);
+        const bf16x8 lo = *(const bf16x8*)(qb + (size_t)(NT + t) * 1024 + lane * 16);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[t][j] = mfma_bf(h, b[j], acc[t][j]);
+          acc[t][j] = mfma_bf(lo, b[j], acc[t][j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        floatx4 xv[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) xv[s4] = *(const floatx4*)(base + (size_t)(16 * h + 4 * gq + s4) * PITCH + cofs);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const floatx4 qa = *(const floatx4*)(qb + (size_t)(h * NT + t) * 1024 + lane * 16);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[t][j] = mfma4(qa[s4], xv[s4][j], acc[t][j]);
+        }
+      }
+    }
+  }
+  const int lp = NT * 16;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = cb + wave * 64 + 4 * i + j;
+      if (col < n) *(floatx4*)(part + ((int64_t)blockIdx.y * n + col) * lp + t * 16 + 4 * gq) = acc[t][j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -923,6 +1076,56 @@ XPlan plan_nn(int64_t m, int64_t n, int l, int cdt, int cus) {
   return p;
 }
 
+// Streamed TN (tn2_kernel) plan: 512-column blocks x S row splits.  Bytes:
+// X once, Q^T once per column block, split partials written and read back.
+static void plan_tn2(XPlan& p, int64_t m, int64_t n, int l, int cdt, int cus) {
+  p.use2 = 0;
+  const int nt = ceil_div(l, 16);
+  if (!(cdt == 1 || cdt == 2) || nt > 8 || m < 32) return;
+  const int lp = nt * 16;
+  const int64_t nb = ceil_div(n, 512);
+  const double xbytes = (double)m * n * (cdt == 2 ? 2 : 4);
+  const double qbytes = (double)m * lp * 4.0;
+  double best = 0.0;
+  for (int64_t sp = 1; sp <= 1024; sp = (sp < 8) ? sp + 1 : sp * 2) {
+    int64_t spl = sp;
+    if (spl * 64 > m) break;
+    const int64_t mlen = round_up((size_t)ceil_div(m, spl), 32);
+    const int64_t se = ceil_div(m, mlen);
+    const int64_t wgs = nb * se;
+    const int64_t rounds = ceil_div(wgs, cus);
+    const double util = (double)wgs / (double)(rounds * cus);
+    const double bytes = xbytes + (double)nb * qbytes + 2.0 * se * n * lp * 4.0;
+    const double cost = bytes / util;
+    if (!p.use2 || cost < best) {
+      best = cost;
+      p.use2 = 1;
+      p.g2 = (int)nb;
+      p.s2 = (int)se;
+      p.klen2 = mlen;
+    }
+  }
+  {  // the split count that exactly fills the CUs
+    int64_t spl = cus / nb;
+    if (spl >= 1 && spl * 64 <= m) {
+      const int64_t mlen = round_up((size_t)ceil_div(m, spl), 32);
+      const int64_t se = ceil_div(m, mlen);
+      const int64_t wgs = nb * se;
+      const int64_t rounds = ceil_div(wgs, cus);
+      const double util = (double)wgs / (double)(rounds * cus);
+      const double cost = (xbytes + (double)nb * qbytes + 2.0 * se * n * lp * 4.0) / util;
+      if (!p.use2 || cost < best) {
+        p.use2 = 1;
+        p.g2 = (int)nb;
+        p.s2 = (int)se;
+        p.klen2 = mlen;
+      }
+    }
+  }
+  const int es = (cdt == 2) ? 2 : 4;
+  p.lds2 = (size_t)2 * (32 * (512 * es + 16) + (size_t)2 * nt * 1024);  // two stages: X rows + Q^T fragments
+}
+
 XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus) {
   XPlan p;
   const int lp = ceil_div(l, 16) * 16;
@@ -936,6 +1139,11 @@ XPlan plan_tn(int64_t m, int64_t n, int l, int cdt, int cus) {
   if (splits < 1) splits = 1;
   p.splits = splits;
   p.part_elems = (size_t)splits * (size_t)n * (size_t)lp;
+  plan_tn2(p, m, n, l, cdt, cus);
+  if (p.use2) {
+    size_t e2 = (size_t)p.s2 * (size_t)n * (size_t)lp;
+    if (e2 > p.part_elems) p.part_elems = e2;
+  }
   return p;
 }
 
@@ -1039,11 +1247,35 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
   return launch_reduce<double, double>((const double*)part, rs, m, l, lp, (double*)Y, 0, s);
 }
 
+template <typename E, int NT>
+static hipError_t launch_tn2_t(dim3 grid, const XPlan& pl, hipStream_t s, const E* X, int64_t m, int64_t n,
+                               int64_t ldx, const E* Qt, int64_t ldqt, int lp, float* part) {
+  auto fn = tn2_kernel<E, NT>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, grid, dim3(512), pl.lds2, s, X, m, n, ldx, Qt, ldqt, lp, part, pl.klen2);
+  return hipGetLastError();
+}
+
 hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt, int64_t ldqt,
                      int l, void* Z, int transposed, void* part, const XPlan& pl, hipStream_t s) {
   const int ntile = ceil_div(l, 16);
   const int lp = ntile * 16;
   const int splits = pl.splits;
+  if (pl.use2 && (cdt == 1 || cdt == 2) && ldqt % 64 == 0 &&
+      ((cdt == 1 && vec_width(X, ldx, 4) == 4) || (cdt == 2 && ldx % 8 == 0 && ((uintptr_t)X % 16) == 0))) {
+    dim3 grid((unsigned)pl.g2, (unsigned)pl.s2);
+    hipError_t e0;
+    if (cdt == 1) {
+      NT_SWITCH(ntile, e0 = (launch_tn2_t<float, NT>)(grid, pl, s, (const float*)X, m, n, ldx, (const float*)Qt,
+                                                    ldqt, lp, (float*)part));
+    } else {
+      NT_SWITCH(ntile, e0 = (launch_tn2_t<bf16_t, NT>)(grid, pl, s, (const bf16_t*)X, m, n, ldx, (const bf16_t*)Qt,
+                                                     ldqt, lp, (float*)part));
+    }
+    if (e0 != hipSuccess) return e0;
+    return launch_reduce<float, float>((const float*)part, pl.s2, n, l, lp, (float*)Z, transposed, s);
+  }
   if (cdt == 1) {
     const int64_t mlen = round_up((size_t)ceil_div(m, splits), 16);
     const int rs = ceil_div(m, mlen);

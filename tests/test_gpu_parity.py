@@ -386,3 +386,23 @@ def test_sketch_pass_spans_x_omega(prec, m, n, ld, k, p):
     err = np.linalg.norm(Y - Q @ (Q.T @ Y)) / np.linalg.norm(Y)
     assert err <= 2e-6, err
     assert np.linalg.norm(Q.T @ Q - np.eye(l)) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("m,n,ld,l", [(500, 400, 400, 30), (3001, 1711, 1728, 70), (20007, 333, 336, 28),
+                                      (4099, 5000, 5000, 70)])
+def test_compress_streamed_shapes(prec, m, n, ld, l):
+    # B = Q^T X against the product in FP64 of the same rounded inputs:
+    # ragged m and n, n inside padded rows whose padding is NaN (never data),
+    # several column blocks and row splits
+    g = s.stream(53, m, n)
+    Xf = np.full((m, ld), np.nan, dtype=np.float32)
+    Xf[:, :n] = g.random((m, n), dtype=np.float32)
+    Qn, _ = np.linalg.qr(g.standard_normal((m, l)))
+    Qn = Qn.astype(np.float32)
+    Xd = dev(Xf)
+    Xd = (Xd.to(torch.bfloat16) if prec == "bf16" else Xd)[:, :n]
+    B = host(rn.compress(Xd, dev(Qn), precision=prec))
+    Bo = Qn.astype(np.float64).T @ host(Xd)
+    assert np.isfinite(B).all()
+    assert relf(B, Bo) <= 1e-5
