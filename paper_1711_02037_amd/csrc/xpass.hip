@@ -988,11 +988,55 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const CT* __restrict_
   }
 }
 
+// FP32 partials: a block sums a 16-row tile of every split with 16-byte reads
+// along the row (the same split order as above), then writes the tile through
+// LDS, so that the transposed output is stored along its rows too.
+__global__ __launch_bounds__(256) void reduce_tile_kernel(const float* __restrict__ part, int splits, int64_t rows,
+                                                          int l, int lp, float* __restrict__ out, int transposed) {
+  constexpr int RT = 16;
+  __shared__ float tile[RT][LMAX + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * RT;
+  const int nq = lp / 4;
+  for (int q = threadIdx.x; q < RT * nq; q += 256) {
+    const int rr = q / nq, cq = q - (q / nq) * nq;
+    const int64_t r = r0 + rr;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (r < rows) {
+      const float* src = part + r * lp + 4 * cq;
+#pragma unroll 8
+      for (int p = 0; p < splits; ++p) acc += *(const floatx4*)(src + (int64_t)p * rows * lp);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tile[rr][4 * cq + e] = acc[e];
+  }
+  __syncthreads();
+  if (transposed) {
+    for (int e = threadIdx.x; e < l * RT; e += 256) {
+      const int c = e / RT, rr = e - (e / RT) * RT;
+      const int64_t r = r0 + rr;
+      if (r < rows) out[(int64_t)c * rows + r] = tile[rr][c];
+    }
+  } else {
+    for (int e = threadIdx.x; e < RT * l; e += 256) {
+      const int rr = e / l, c = e - (e / l) * l;
+      const int64_t r = r0 + rr;
+      if (r < rows) out[r * l + c] = tile[rr][c];
+    }
+  }
+}
+
 template <typename CT, typename OT>
 static hipError_t launch_reduce(const CT* part, int splits, int64_t rows, int l, int lp, OT* out, int tr,
                                 hipStream_t s) {
   int64_t total = rows * l;
   if (total == 0) return hipSuccess;
+  if constexpr (sizeof(CT) == 4 && sizeof(OT) == 4) {
+    if (lp % 4 == 0 && lp <= LMAX && ((uintptr_t)part % 16) == 0) {
+      hipLaunchKernelGGL(reduce_tile_kernel, dim3((unsigned)ceil_div(rows, 16)), dim3(256), 0, s,
+                         (const float*)part, splits, rows, l, lp, (float*)out, tr);
+      return hipGetLastError();
+    }
+  }
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL((reduce_parts_kernel<CT, OT>), dim3((unsigned)blocks), dim3(256), 0, s, part, splits,
