@@ -65,33 +65,45 @@ __device__ __forceinline__ void put(u64* base, int elem, V v, unsigned e) {
 }
 
 // Fixed-order sum over nsrc slots (slot s at base + s * stride) of element
-// `elem`, waiting for epoch e on every word.  All loads are issued first, then
-// each source is polled in turn (polling every stale word each round loads the
-// memory system enough to slow the whole device down).
+// `elem`, waiting for epoch e on every word.  Sources are taken in windows of
+// WN: the window's loads are issued together and only its stale words are
+// polled again, so a window costs about one round trip once its data has
+// landed.  Polling every source at once loads the memory system enough to
+// slow the whole device down; polling one source at a time pays a round trip
+// per source.
 template <typename V>
 __device__ __forceinline__ V gather_sum(const u64* base, size_t stride, int nsrc, int elem, unsigned e,
                                         bool& ok) {
   constexpr int W = Words<V>::n;
-  u64 w[MAXSRC][W];
-#pragma unroll
-  for (int s = 0; s < MAXSRC; ++s)
-    if (s < nsrc)
-#pragma unroll
-      for (int h = 0; h < W; ++h) w[s][h] = ld_ll(base + s * stride + (size_t)elem * W + h);
+  constexpr int WN = (W == 1) ? 8 : 4;
   V sum = (V)0;
+  for (int s0 = 0; s0 < nsrc; s0 += WN) {
+    u64 w[WN][W];
 #pragma unroll
-  for (int s = 0; s < MAXSRC; ++s) {
-    if (s < nsrc) {
+    for (int q = 0; q < WN; ++q)
+      if (s0 + q < nsrc)
 #pragma unroll
-      for (int h = 0; h < W; ++h) {
-        long spins = 0;
-        while ((unsigned)(w[s][h] >> 32) != e) {
-          if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
-          w[s][h] = ld_ll(base + s * stride + (size_t)elem * W + h);
-        }
-      }
-      sum += value_of<V>(w[s]);
+        for (int h = 0; h < W; ++h) w[q][h] = ld_ll(base + (s0 + q) * stride + (size_t)elem * W + h);
+    long spins = 0;
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int q = 0; q < WN; ++q)
+        if (s0 + q < nsrc)
+#pragma unroll
+          for (int h = 0; h < W; ++h) all = all && ((unsigned)(w[q][h] >> 32) == e);
+      if (all) break;
+      if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
+#pragma unroll
+      for (int q = 0; q < WN; ++q)
+        if (s0 + q < nsrc)
+#pragma unroll
+          for (int h = 0; h < W; ++h)
+            if ((unsigned)(w[q][h] >> 32) != e) w[q][h] = ld_ll(base + (s0 + q) * stride + (size_t)elem * W + h);
     }
+#pragma unroll
+    for (int q = 0; q < WN; ++q)
+      if (s0 + q < nsrc) sum += value_of<V>(w[q]);
   }
   return sum;
 }
