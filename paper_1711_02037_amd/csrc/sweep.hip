@@ -241,6 +241,65 @@ __device__ __forceinline__ T readlane(T v, int lane) {
   }
 }
 
+// Cross-lane sums on the VALU (no LDS round trip).  sum8: over the 8 lanes of
+// an aligned group (lane ^ 1, ^ 2, ^ 4 by DPP quad permutes and the half-row
+// mirror).  sum_stride8: over the 8 lanes with equal lane % 8 (lane ^ 8 by a
+// DPP row rotation, ^ 16 and ^ 32 by the permlane swaps of gfx950).  Every
+// lane of a group obtains the bit-identical sum.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp32(unsigned x) {
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_mov(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float(dpp32<CTRL>(__float_as_uint(x)));
+  } else {
+    const u64 b = (u64)__double_as_longlong(x);
+    const u64 lo = dpp32<CTRL>((unsigned)b), hi = dpp32<CTRL>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+  }
+}
+template <typename T>
+__device__ __forceinline__ T swap_sum16(T x) {
+  if constexpr (sizeof(T) == 4) {
+    auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  } else {
+    const u64 b = (u64)__double_as_longlong(x);
+    auto pl = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    auto ph = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double a0 = __longlong_as_double((long long)((u64)pl[0] | ((u64)ph[0] << 32)));
+    const double a1 = __longlong_as_double((long long)((u64)pl[1] | ((u64)ph[1] << 32)));
+    return a0 + a1;
+  }
+}
+template <typename T>
+__device__ __forceinline__ T swap_sum32(T x) {
+  if constexpr (sizeof(T) == 4) {
+    auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  } else {
+    const u64 b = (u64)__double_as_longlong(x);
+    auto pl = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    auto ph = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double a0 = __longlong_as_double((long long)((u64)pl[0] | ((u64)ph[0] << 32)));
+    const double a1 = __longlong_as_double((long long)((u64)pl[1] | ((u64)ph[1] << 32)));
+    return a0 + a1;
+  }
+}
+template <typename T>
+__device__ __forceinline__ T sum8(T x) {
+  x = x + dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
+  x = x + dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
+  return x + dpp_mov<0x141>(x);  // row_half_mirror
+}
+template <typename T>
+__device__ __forceinline__ T sum_stride8(T x) {
+  x = x + dpp_mov<0x128>(x);   // row_ror:8
+  return swap_sum32(swap_sum16(x));
+}
+
 template <typename T> __device__ __forceinline__ T clip0(T x) { return x > (T)0 ? x : (T)0; }
 
 // Maps a linear block index to (row block, column block) of the upper block
@@ -569,43 +628,86 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     }
     lds_sync();
     // FP64 arithmetic: the update cancels R against H^T S, and S is the Gram
-    // of a nonnegative factor, so its rounding is amplified.
-    for (int cc = wave; cc < nc; cc += NTH / 64) {
-      const int jj = lane < k ? lane : 0;
-      // lane holds B(lane, c) and B(lane + 64, c); H(lane, c)
-      const T b0 = lane < l ? Bp[(size_t)lane * ldB + cc] : (T)0;
-      const T b1 = lane + 64 < l ? Bp[(size_t)(lane + 64) * ldB + cc] : (T)0;
-      double h = lane < k ? (double)Hp[(size_t)lane * ldH + cc] : 0.0;
-      double R0 = 0.0, R1 = 0.0;
-      const int l0 = l < 64 ? l : 64;
+    // of a nonnegative factor, so its rounding is amplified.  A wave takes up
+    // to HI columns at once (columns cc, cc + 8, ...): their Gauss-Seidel
+    // chains are independent, so their latencies overlap.
+    constexpr int HI = 3;
+    const int jj = lane < k ? lane : 0;
+    const int l0 = l < 64 ? l : 64;
+    for (int cb = wave; cb < nc; cb += (NTH / 64) * HI) {
+      bool live[HI];
+      T b0[HI], b1[HI];
+      double h[HI], R0[HI], R1[HI];
+#pragma unroll
+      for (int q = 0; q < HI; ++q) {
+        const int cc = cb + (NTH / 64) * q;
+        live[q] = cc < nc;
+        const int c = live[q] ? cc : cb;
+        // lane holds B(lane, c) and B(lane + 64, c); H(lane, c)
+        b0[q] = lane < l ? Bp[(size_t)lane * ldB + c] : (T)0;
+        b1[q] = lane + 64 < l ? Bp[(size_t)(lane + 64) * ldB + c] : (T)0;
+        h[q] = lane < k ? (double)Hp[(size_t)lane * ldH + c] : 0.0;
+        R0[q] = 0.0;
+        R1[q] = 0.0;
+      }
       int aa = 0;
       for (; aa + 2 <= l0; aa += 2) {
-        R0 = fma((double)readlane<T>(b0, aa), (double)Wts[aa * k + jj], R0);
-        R1 = fma((double)readlane<T>(b0, aa + 1), (double)Wts[(aa + 1) * k + jj], R1);
+        const double w0 = (double)Wts[aa * k + jj], w1 = (double)Wts[(aa + 1) * k + jj];
+#pragma unroll
+        for (int q = 0; q < HI; ++q) {
+          R0[q] = fma((double)readlane<T>(b0[q], aa), w0, R0[q]);
+          R1[q] = fma((double)readlane<T>(b0[q], aa + 1), w1, R1[q]);
+        }
       }
-      for (; aa < l0; ++aa) R0 = fma((double)readlane<T>(b0, aa), (double)Wts[aa * k + jj], R0);
-      for (aa = 64; aa < l; ++aa) R1 = fma((double)readlane<T>(b1, aa - 64), (double)Wts[aa * k + jj], R1);
-      double g0 = R0 + R1, g1 = 0.0;
+      for (; aa < l0; ++aa) {
+        const double w0 = (double)Wts[aa * k + jj];
+#pragma unroll
+        for (int q = 0; q < HI; ++q) R0[q] = fma((double)readlane<T>(b0[q], aa), w0, R0[q]);
+      }
+      for (aa = 64; aa < l; ++aa) {
+        const double w1 = (double)Wts[aa * k + jj];
+#pragma unroll
+        for (int q = 0; q < HI; ++q) R1[q] = fma((double)readlane<T>(b1[q], aa - 64), w1, R1[q]);
+      }
+      double g0[HI], g1[HI];
+#pragma unroll
+      for (int q = 0; q < HI; ++q) { g0[q] = R0[q] + R1[q]; g1[q] = 0.0; }
       int ii = 0;
       for (; ii + 2 <= k; ii += 2) {
-        g0 = fma(-(double)Snum[ii * k + jj], readlane<double>(h, ii), g0);
-        g1 = fma(-(double)Snum[(ii + 1) * k + jj], readlane<double>(h, ii + 1), g1);
+        const double s0 = (double)Snum[ii * k + jj], s1 = (double)Snum[(ii + 1) * k + jj];
+#pragma unroll
+        for (int q = 0; q < HI; ++q) {
+          g0[q] = fma(-s0, readlane<double>(h[q], ii), g0[q]);
+          g1[q] = fma(-s1, readlane<double>(h[q], ii + 1), g1[q]);
+        }
       }
-      for (; ii < k; ++ii) g0 = fma(-(double)Snum[ii * k + jj], readlane<double>(h, ii), g0);
-      double gsum = g0 + g1;
+      for (; ii < k; ++ii) {
+        const double s0 = (double)Snum[ii * k + jj];
+#pragma unroll
+        for (int q = 0; q < HI; ++q) g0[q] = fma(-s0, readlane<double>(h[q], ii), g0[q]);
+      }
+      double gsum[HI];
+#pragma unroll
+      for (int q = 0; q < HI; ++q) gsum[q] = g0[q] + g1[q];
       for (ii = 0; ii < k; ++ii) {
         const double rd = rinv[ii];
         if (rd > 0.0) {
-          const double hi = readlane<double>(h, ii);
-          const double gi = readlane<double>(gsum, ii);
-          // the new row is rounded to the storage type before it is used
-          const double hn = (double)clip0<T>((T)fma(gi, rd, hi));
-          const double delta = hn - hi;
-          if (lane == ii) h = hn;
-          gsum = fma(-(double)Snum[ii * k + jj], delta, gsum);
+          const double sij = (double)Snum[ii * k + jj];
+#pragma unroll
+          for (int q = 0; q < HI; ++q) {
+            const double hi = readlane<double>(h[q], ii);
+            const double gi = readlane<double>(gsum[q], ii);
+            // the new row is rounded to the storage type before it is used
+            const double hn = (double)clip0<T>((T)fma(gi, rd, hi));
+            const double delta = hn - hi;
+            if (lane == ii) h[q] = hn;
+            gsum[q] = fma(-sij, delta, gsum[q]);
+          }
         }
       }
-      if (lane < k) Hp[(size_t)lane * ldH + cc] = (T)h;
+#pragma unroll
+      for (int q = 0; q < HI; ++q)
+        if (live[q] && lane < k) Hp[(size_t)lane * ldH + cb + (NTH / 64) * q] = (T)h[q];
     }
     if constexpr (REGQ) lds_sync();
     else __syncthreads();
@@ -614,7 +716,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // --- W phase: columns of W in order, one device-wide exchange each --------
   // W phase with the Q slab in registers.  Per column: lift and clip (a
   // register GEMV reduced over the 8 column-group lanes), the local map-back
-  // (reduced over the 64 row groups: lanes, then waves through LDS), one
+  // (reduced over the row groups: the 8 of a wave by lane permutes, then the
+  // waves through LDS), one
   // device-wide exchange by threads t < l; while it is in flight, threads
   // t >= 128 prepare the next column's update vector without the column being
   // exchanged, whose term is added once its value arrives.
@@ -658,11 +761,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           u1 = fma(qreg[i][s + 1], vs[s + 1], u1);
         }
         if (CQ & 1) u0 = fma(qreg[i][CQ - 1], vs[CQ - 1], u0);
-        T u = u0 + u1;
-        u += __shfl_xor(u, 1);
-        u += __shfl_xor(u, 2);
-        u += __shfl_xor(u, 4);
-        w[i] = clip0<T>(u);
+        w[i] = clip0<T>(sum8<T>(u0 + u1));
       }
       if (gc == 0) {
 #pragma unroll
@@ -685,11 +784,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           p1 = fma(qreg[i + 1][s], w[i + 1], p1);
         }
         if (RQ & 1) p0 = fma(qreg[RQ - 1][s], w[RQ - 1], p0);
-        T p = p0 + p1;
-        p += __shfl_xor(p, 8);
-        p += __shfl_xor(p, 16);
-        p += __shfl_xor(p, 32);
-        pv[s] = p;
+        pv[s] = sum_stride8<T>(p0 + p1);
       }
       if (lane < 8) {
 #pragma unroll
