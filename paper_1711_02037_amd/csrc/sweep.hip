@@ -767,10 +767,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < RQ; ++i) {
           const int rr = ga + 64 * i;
-          if (rr < nr) {
-            a.W[(size_t)(r0 + rr) * k + jj] = w[i];
-            Ws[rr * k + jj] = w[i];
-          }
+          if (rr < nr) Ws[rr * k + jj] = w[i];  // W is written back once, at the end
         }
       }
       // local map-back partials: sum_i Q(r_i, a) w_i over this thread's rows
@@ -1093,6 +1090,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       const int r = e / nc, cc = e - (e / nc) * nc;
       a.H[(size_t)r * n + c0 + cc] = Hs[r * cp + cc];
     }
+    for (int e = t; e < nr * k; e += NTH) a.W[(size_t)r0 * k + e] = Ws[e];
   }
   if (g == 0) {
     for (int e = t; e < l * k; e += NTH) a.Wt[e] = Wts[e];
