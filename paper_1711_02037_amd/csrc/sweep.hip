@@ -620,13 +620,12 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       Snum = Tm;
       if (a.gram_mode == 1) Ssc = Tm;
     }
-    // reciprocal scales, computed once per phase (0 marks a skipped row)
-    double* rinv = (double*)red2;
-    if (t < k) {
-      const double d = (double)Ssc[t * k + t];
-      rinv[t] = d > 0.0 ? 1.0 / d : 0.0;
+    // reciprocal scales, one per lane (0 marks a skipped row)
+    double rinv_l = 0.0;
+    if (lane < k) {
+      const double d = (double)Ssc[lane * k + lane];
+      rinv_l = d > 0.0 ? 1.0 / d : 0.0;
     }
-    lds_sync();
     // FP64 arithmetic: the update cancels R against H^T S, and S is the Gram
     // of a nonnegative factor, so its rounding is amplified.  A wave takes up
     // to HI columns at once (columns cc, cc + 8, ...): their Gauss-Seidel
@@ -650,13 +649,18 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         R0[q] = 0.0;
         R1[q] = 0.0;
       }
+      // R(c, jj) = sum_a B(a, c) W~(a, jj): four LDS reads in flight per step
       int aa = 0;
-      for (; aa + 2 <= l0; aa += 2) {
-        const double w0 = (double)Wts[aa * k + jj], w1 = (double)Wts[(aa + 1) * k + jj];
+      for (; aa + 4 <= l0; aa += 4) {
+        double w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = (double)Wts[(aa + u) * k + jj];
 #pragma unroll
         for (int q = 0; q < HI; ++q) {
-          R0[q] = fma((double)readlane<T>(b0[q], aa), w0, R0[q]);
-          R1[q] = fma((double)readlane<T>(b0[q], aa + 1), w1, R1[q]);
+          R0[q] = fma((double)readlane<T>(b0[q], aa), w[0], R0[q]);
+          R1[q] = fma((double)readlane<T>(b0[q], aa + 1), w[1], R1[q]);
+          R0[q] = fma((double)readlane<T>(b0[q], aa + 2), w[2], R0[q]);
+          R1[q] = fma((double)readlane<T>(b0[q], aa + 3), w[3], R1[q]);
         }
       }
       for (; aa < l0; ++aa) {
@@ -673,12 +677,16 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
       for (int q = 0; q < HI; ++q) { g0[q] = R0[q] + R1[q]; g1[q] = 0.0; }
       int ii = 0;
-      for (; ii + 2 <= k; ii += 2) {
-        const double s0 = (double)Snum[ii * k + jj], s1 = (double)Snum[(ii + 1) * k + jj];
+      for (; ii + 4 <= k; ii += 4) {
+        double sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sv[u] = (double)Snum[(ii + u) * k + jj];
 #pragma unroll
         for (int q = 0; q < HI; ++q) {
-          g0[q] = fma(-s0, readlane<double>(h[q], ii), g0[q]);
-          g1[q] = fma(-s1, readlane<double>(h[q], ii + 1), g1[q]);
+          g0[q] = fma(-sv[0], readlane<double>(h[q], ii), g0[q]);
+          g1[q] = fma(-sv[1], readlane<double>(h[q], ii + 1), g1[q]);
+          g0[q] = fma(-sv[2], readlane<double>(h[q], ii + 2), g0[q]);
+          g1[q] = fma(-sv[3], readlane<double>(h[q], ii + 3), g1[q]);
         }
       }
       for (; ii < k; ++ii) {
@@ -689,20 +697,26 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       double gsum[HI];
 #pragma unroll
       for (int q = 0; q < HI; ++q) gsum[q] = g0[q] + g1[q];
+      // Gauss-Seidel over the rows: the scale comes from a register by lane
+      // broadcast and the next S entry is loaded one step ahead, so no LDS
+      // round trip sits on the chain
+      // (a zero scale leaves the row unchanged: h stays, delta is +0)
+      double s_cur = (double)Snum[jj];
+      double s_nxt = (double)Snum[(k > 1 ? 1 : 0) * k + jj];
       for (ii = 0; ii < k; ++ii) {
-        const double rd = rinv[ii];
-        if (rd > 0.0) {
-          const double sij = (double)Snum[ii * k + jj];
+        const double sij = s_cur;
+        s_cur = s_nxt;
+        s_nxt = (double)Snum[min(ii + 2, k - 1) * k + jj];  // two steps ahead
+        const double rd = readlane<double>(rinv_l, ii);
 #pragma unroll
-          for (int q = 0; q < HI; ++q) {
-            const double hi = readlane<double>(h[q], ii);
-            const double gi = readlane<double>(gsum[q], ii);
-            // the new row is rounded to the storage type before it is used
-            const double hn = (double)clip0<T>((T)fma(gi, rd, hi));
-            const double delta = hn - hi;
-            if (lane == ii) h[q] = hn;
-            gsum[q] = fma(-sij, delta, gsum[q]);
-          }
+        for (int q = 0; q < HI; ++q) {
+          const double hi = readlane<double>(h[q], ii);
+          const double gi = readlane<double>(gsum[q], ii);
+          // the new row is rounded to the storage type before it is used
+          const double hn = (rd > 0.0) ? (double)clip0<T>((T)fma(gi, rd, hi)) : hi;
+          const double delta = hn - hi;
+          if (lane == ii) h[q] = hn;
+          gsum[q] = fma(-sij, delta, gsum[q]);
         }
       }
 #pragma unroll
