@@ -12,6 +12,8 @@
  *   rnmf_hals_step : compressed HALS sweeps, Sec. 3.2 and Algorithm 1, with
  *                    the projected-gradient stop of Sec. 3.3.
  *   rnmf_factorize : all of Algorithm 1 plus the relative error of Sec. 4.
+ *   rnmf_hals      : deterministic HALS sweeps on X itself (Sec. 3.1), the
+ *                    baseline that randomized HALS accelerates.
  *
  * Conventions (every entry point):
  *   - Matrices are dense and row-major.  X has a leading dimension ldx >= n
@@ -122,7 +124,7 @@ typedef struct rnmf_report {
 
 /* Operation selector for rnmf_workspace_bytes. */
 enum { RNMF_OP_SKETCH = 0, RNMF_OP_COMPRESS = 1, RNMF_OP_HALS_STEP = 2,
-       RNMF_OP_FACTORIZE = 3, RNMF_OP_REL_ERROR = 4 };
+       RNMF_OP_FACTORIZE = 3, RNMF_OP_REL_ERROR = 4, RNMF_OP_HALS = 5 };
 
 /* Fills opts with the paper's defaults: p = 20, q = 2 (Sec. 4, experimental
  * setup), max_iter = 200, tol = 0, prec F32, Gaussian Omega, FULL Gram,
@@ -203,6 +205,24 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
                            const rnmf_opts* opts, const void* Omega, const void* W0,
                            const void* H0, void* W, void* H, rnmf_report* report,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* nsweeps sweeps of deterministic HALS (Sec. 3.1, residual-free block rules)
+ * on X itself, in place; randomized HALS is this algorithm run on the
+ * compressed B with the lift through Q:
+ *   H phase: R = X^T W, S = W^T W, rows j of H in turn:
+ *            H(j,:) <- max(0, H(j,:) + (R(:,j) - H^T S(:,j)) / S_jj)
+ *   W phase: T = X H^T, V = H H^T, columns j of W in turn:
+ *            W(:,j) <- max(0, W(:,j) + (T(:,j) - W V(:,j)) / V_jj)
+ * in the order opts->order; a block whose scale is exactly zero is skipped.
+ * X: m x n (ldx) in RNMF_F32 (opts->prec RNMF_PREC_F32) or RNMF_F64
+ * (RNMF_PREC_F64); W: m x k and H: k x n (in/out, packed, same dtype).
+ * k = opts->k with 1 <= k <= min(64, m, n).  opts->tol must be <= 0 (a fixed
+ * number of sweeps); gram_mode is not used.  Each sweep streams X twice
+ * (one TN and one NN pass); S and V are formed with FP64 accumulation and
+ * both Gauss-Seidel sweeps accumulate in FP64.  Workspace: RNMF_OP_HALS.
+ * Asynchronous. */
+rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, void* W, void* H,
+                      int32_t nsweeps, const rnmf_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Cast an m x n FP32 matrix (ldx) to packed bfloat16 (round to nearest even),
  * for callers that keep a BF16 copy of X for RNMF_PREC_BF16.  Asynchronous. */

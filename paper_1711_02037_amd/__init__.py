@@ -33,12 +33,12 @@ GRAM = {"full": 0, "lowdim": 1, "mixed": 2}
 ORDER = {"h_first": 0, "w_first": 1}
 OMEGA = {"gaussian": 0, "uniform": 1}
 FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE, FLAG_SHIFTED_QR3 = 0x1, 0x2, 0x4, 0x8, 0x10
-OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR = range(5)
+OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR, OP_HALS = range(6)
 
 EXPORTS = [
     "rnmf_default_opts", "rnmf_workspace_bytes", "rnmf_status_string", "rnmf_last_error",
     "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
-    "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status",
+    "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals",
 ]
 
 
@@ -99,6 +99,8 @@ def lib():
         L.rnmf_factorize.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.POINTER(Opts), vp, vp, vp,
                                      vp, vp, ctypes.POINTER(Report), vp, sz, vp]
         L.rnmf_factorize.restype = ctypes.c_int
+        L.rnmf_hals.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, vp, i32, ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_hals.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
         L.rnmf_cast_bf16.restype = ctypes.c_int
         L.rnmf_read_status.argtypes = [vp, sz, vp]
@@ -273,6 +275,26 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
         t0 = ts[0]
         return int(s[0]), s[1], s[2], [(x - t0) / 100.0 if x else None for x in ts]
     return int(s[0]), s[1], s[2]
+
+
+def hals(X, W, H, nsweeps=1, order="h_first", ws=None):
+    """nsweeps sweeps of deterministic HALS on X itself, in place on W and H
+    (rnmf_hals; Sec. 3.1).  X, W, H: FP32 or FP64 (all the same dtype)."""
+    torch = _torch()
+    _need_dev(X, "X"); _rowmajor(X, "X")
+    for t, nm in ((W, "W"), (H, "H")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, n = X.shape
+    k = H.shape[0]
+    if W.shape != (m, k) or H.shape != (k, n) or W.dtype != X.dtype or H.dtype != X.dtype:
+        raise ValueError("need W (m x k) and H (k x n) in the dtype of X")
+    prec = "fp64" if X.dtype == torch.float64 else "fp32"
+    o = make_opts(k, 0, 0, precision=prec, order=order)
+    nb = workspace_bytes(OP_HALS, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, X.device)
+    _check(lib().rnmf_hals(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(W), _ptr(H), int(nsweeps), ctypes.byref(o),
+                           _ptr(w), w.numel(), _stream(X.device)))
+    _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(X.device)))
 
 
 def rel_error(X, W, H, ws=None):

@@ -238,6 +238,43 @@ SweepBufs plan_hals(Arena& a, int64_t m, int64_t n, int l, int k, const Mode& md
   return b;
 }
 
+struct DHalsBufs {
+  void* wp;         // W packed transposed, lp x ldpm (the TN pass operand)
+  int64_t ldpm;
+  void* hp;         // H zero-padded, lp x ldpn (the NN pass operand)
+  int64_t ldpn;
+  void* R;          // X^T W, n x k
+  void* T;          // X H^T, m x k
+  double* S;        // W^T W, k x k
+  double* V;        // H H^T, k x k
+  double* gpart;    // Gram partials of W^T W
+  int gsplits;
+  double* hpart;    // Gram partials of H H^T
+  void* part;       // split partials of the X passes
+  XPlan nn, tn;
+};
+DHalsBufs plan_dhals(Arena& a, int64_t m, int64_t n, int k, const Mode& md, const Dev& d) {
+  DHalsBufs b;
+  const int lp = ceil_div(k, 16) * 16;
+  const size_t es = md.es;
+  b.ldpm = (int64_t)round_up((size_t)m, 64);
+  b.ldpn = (int64_t)round_up((size_t)n, 64);
+  b.wp = a.take<char>((size_t)lp * b.ldpm * es);
+  b.hp = a.take<char>((size_t)lp * b.ldpn * es);
+  b.R = a.take<char>((size_t)n * k * es);
+  b.T = a.take<char>((size_t)m * k * es);
+  b.S = a.take<double>((size_t)k * k);
+  b.V = a.take<double>((size_t)k * k);
+  b.gsplits = gram_splits(m, d.cus);
+  b.gpart = a.take<double>((size_t)b.gsplits * LMAX * LMAX);
+  b.hpart = a.take<double>((size_t)hgram_splits(n) * LMAX * LMAX);
+  b.nn = plan_nn(m, n, k, md.cdt, d.cus);
+  b.tn = plan_tn(m, n, k, md.cdt, d.cus);
+  const size_t pe = b.nn.part_elems > b.tn.part_elems ? b.nn.part_elems : b.tn.part_elems;
+  b.part = a.take<char>(pe * es);
+  return b;
+}
+
 struct RelBufs {
   double* part;
   int np;
@@ -388,6 +425,9 @@ size_t op_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o, int xt, const 
     case RNMF_OP_REL_ERROR:
       plan_rel(a, m, n);
       return a.used;
+    case RNMF_OP_HALS:
+      plan_dhals(a, m, n, o->k, md, d);
+      return a.used;
     case RNMF_OP_FACTORIZE:
       return factorize_bytes(m, n, o, xt, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nullptr);
@@ -470,10 +510,20 @@ size_t rnmf_workspace_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o) {
     if (m < 1 || n < 1 || o->k < 1 || o->k > KMAX) { fail(RNMF_ERR_ARG, "bad shape or k for the sweep"); return 0; }
   } else if (op == RNMF_OP_REL_ERROR) {
     if (m < 1 || n < 1) { fail(RNMF_ERR_SHAPE, "empty matrix"); return 0; }
+  } else if (op == RNMF_OP_HALS) {
+    if (!o) { fail(RNMF_ERR_ARG, "opts is NULL"); return 0; }
+    if (m < 1 || n < 1 || o->k < 1 || o->k > KMAX || o->k > m || o->k > n) {
+      fail(RNMF_ERR_ARG, "need 1 <= k <= min(%d, m, n)", KMAX);
+      return 0;
+    }
+    if (o->prec != RNMF_PREC_F32 && o->prec != RNMF_PREC_F64) {
+      fail(RNMF_ERR_ARG, "deterministic HALS runs in RNMF_PREC_F32 or RNMF_PREC_F64");
+      return 0;
+    }
   } else {
     if (check_opts(o, m, n, op == RNMF_OP_FACTORIZE) != RNMF_OK) return 0;
   }
-  if (op < RNMF_OP_SKETCH || op > RNMF_OP_REL_ERROR) { fail(RNMF_ERR_ARG, "unknown op %d", op); return 0; }
+  if (op < RNMF_OP_SKETCH || op > RNMF_OP_HALS) { fail(RNMF_ERR_ARG, "unknown op %d", op); return 0; }
   Dev d = default_dev();
   Dev q;
   if (get_dev(q, nullptr)) d = q;
@@ -574,6 +624,63 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   }
   HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, b.xbuf,
                       stats, h.status, trace, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, void* W, void* H, int32_t nsweeps,
+                      const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!X || !W || !H) return fail(RNMF_ERR_ARG, "X, W and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  const int k = o->k;
+  if (k < 1 || k > KMAX || k > m || k > n) return fail(RNMF_ERR_ARG, "need 1 <= k <= min(%d, m, n)", KMAX);
+  if (nsweeps < 0) return fail(RNMF_ERR_ARG, "nsweeps < 0");
+  if (o->prec != RNMF_PREC_F32 && o->prec != RNMF_PREC_F64)
+    return fail(RNMF_ERR_ARG, "deterministic HALS runs in RNMF_PREC_F32 or RNMF_PREC_F64");
+  if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
+  if (o->tol > 0.0) return fail(RNMF_ERR_ARG, "deterministic HALS runs a fixed number of sweeps (tol must be <= 0)");
+  rnmf_status r;
+  if ((r = check_xt(o, xt)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  DHalsBufs b = plan_dhals(a, m, n, k, md, d);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  hipStream_t s = d.stream;
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, s));
+  const int lp = ceil_div(k, 16) * 16;
+  const int hs = hgram_splits(n);
+  auto h_phase = [&]() -> rnmf_status {
+    // R = X^T W, S = W^T W, then the rows of H
+    HIPCHK(launch_pack_t(W, md.dt, m, k, lp, b.ldpm, b.wp, md.cdt, s));
+    HIPCHK(launch_tn(X, md.cdt, m, n, ldx, b.wp, b.ldpm, k, b.R, 0, b.part, b.tn, s));
+    HIPCHK(launch_gram(W, md.dt, m, k, b.gpart, b.gsplits, b.S, s));
+    HIPCHK(launch_hrow(b.R, b.S, H, n, k, md.dt, s));
+    return RNMF_OK;
+  };
+  auto w_phase = [&]() -> rnmf_status {
+    // T = X H^T, V = H H^T, then the columns of W (row by row)
+    HIPCHK(launch_pad(H, k, n, lp, b.ldpn, b.hp, md.dt, s));
+    HIPCHK(launch_hgram(H, k, n, b.hpart, md.dt, s));
+    HIPCHK(launch_gram_sum(b.hpart, hs, k, b.V, s));
+    HIPCHK(launch_nn(X, md.cdt, m, n, ldx, b.hp, b.ldpn, k, b.T, b.part, b.nn, h.status, 0, s));
+    HIPCHK(launch_wrow(b.T, b.V, W, m, k, md.dt, s));
+    return RNMF_OK;
+  };
+  for (int it = 0; it < nsweeps; ++it) {
+    if (o->order == RNMF_ORDER_W_FIRST) {
+      if ((r = w_phase()) != RNMF_OK) return r;
+      if ((r = h_phase()) != RNMF_OK) return r;
+    } else {
+      if ((r = h_phase()) != RNMF_OK) return r;
+      if ((r = w_phase()) != RNMF_OK) return r;
+    }
+  }
   return RNMF_OK;
 }
 

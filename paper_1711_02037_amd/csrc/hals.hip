@@ -1,0 +1,171 @@
+// Deterministic HALS (Sec. 3.1): the block updates applied to X itself, the
+// algorithm that randomized HALS compresses.  One sweep streams X twice:
+//   H phase: R = X^T W (TN pass), S = W^T W (FP64 Gram), then the rows of H
+//            in turn, H(j,:) <- max(0, H(j,:) + (R(:,j) - H^T S(:,j)) / S_jj);
+//   W phase: T = X H^T (NN pass), V = H H^T (FP64 Gram), then the columns of
+//            W in turn, W(:,j) <- max(0, W(:,j) + (T(:,j) - W V(:,j)) / V_jj).
+// The H rows are independent across columns of H and the W columns are
+// independent across rows of W, so both Gauss-Seidel sweeps run without any
+// device-wide exchange; a block with an exactly zero scale is skipped.
+#include "rnmf_common.h"
+
+namespace rnmf {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T clip0h(T x) { return x > (T)0 ? x : (T)0; }
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Rows of H, one wave per column c of H: lane i holds H(i, c) and the running
+// gradient g_i = R(c, i) - sum_p S(p, i) H(p, c) (FP64); the Gauss-Seidel
+// step for row j broadcasts lane j's values and updates every g by rank one.
+template <typename T>
+__global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, const double* __restrict__ S,
+                                                   T* __restrict__ H, int64_t n, int k) {
+  __shared__ double Ss[KMAX * KMAX];
+  for (int e = threadIdx.x; e < k * k; e += 256) Ss[e] = S[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const int i = lane < k ? lane : 0;
+  double h = lane < k ? (double)H[(int64_t)lane * n + c] : 0.0;
+  double g = lane < k ? (double)R[c * k + lane] : 0.0;
+  for (int p = 0; p < k; ++p) g = fma(-Ss[p * k + i], readlane_d(h, p), g);
+  if (lane >= k) g = 0.0;
+  const double rs = (lane < k && Ss[i * k + i] > 0.0) ? 1.0 / Ss[i * k + i] : 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double rd = readlane_d(rs, j);
+    if (rd > 0.0) {
+      const double hj = readlane_d(h, j), gj = readlane_d(g, j);
+      // the new entry is rounded to the storage type before it is used
+      const double hn = (double)clip0h<T>((T)fma(gj, rd, hj));
+      const double delta = hn - hj;
+      if (lane == j) h = hn;
+      g = fma(-Ss[j * k + i], delta, g);
+    }
+  }
+  if (lane < k) H[(int64_t)lane * n + c] = (T)h;
+}
+
+// Columns of W, one thread per row r: the row and V live in LDS (FP64); for
+// each column j the update uses the row as already updated (Gauss-Seidel).
+template <typename T>
+__global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, const double* __restrict__ V,
+                                                   T* __restrict__ W, int64_t m, int k) {
+  __shared__ double Vs[KMAX * KMAX];
+  __shared__ double ws[KMAX][128];
+  for (int e = threadIdx.x; e < k * k; e += 128) Vs[e] = V[e];
+  const int t = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * 128 + t;
+  const bool live = r < m;
+  for (int p = 0; p < k; ++p) ws[p][t] = live ? (double)W[r * k + p] : 0.0;
+  __syncthreads();
+  if (!live) return;
+  for (int j = 0; j < k; ++j) {
+    const double d = Vs[j * k + j];
+    if (!(d > 0.0)) continue;
+    double s0 = 0.0, s1 = 0.0;
+    int p = 0;
+    for (; p + 2 <= k; p += 2) {
+      s0 = fma(ws[p][t], Vs[p * k + j], s0);
+      s1 = fma(ws[p + 1][t], Vs[(p + 1) * k + j], s1);
+    }
+    for (; p < k; ++p) s0 = fma(ws[p][t], Vs[p * k + j], s0);
+    const double num = (double)Tm[r * k + j] - (s0 + s1);
+    ws[j][t] = (double)clip0h<T>((T)(ws[j][t] + num / d));
+  }
+  for (int q = 0; q < k; ++q) W[r * k + q] = (T)ws[q][t];
+}
+
+// Hp (lp x ldp, zero padded) = H (k x n): the small operand of X H^T in the
+// transposed layout the NN pass reads.
+template <typename T>
+__global__ __launch_bounds__(256) void pad_kernel(const T* __restrict__ H, int k, int64_t n, int lp, int64_t ldp,
+                                                  T* __restrict__ Hp) {
+  const int64_t total = (int64_t)lp * ldp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / ldp, c = e - (e / ldp) * ldp;
+    Hp[e] = (i < k && c < n) ? H[i * n + c] : (T)0;
+  }
+}
+
+// Partial V = H H^T over a chunk of 64 columns of H (FP64), written in the
+// partial layout of the Cholesky QR Gram (entry (a, b), a <= b, at a*LMAX+b).
+template <typename T>
+__global__ __launch_bounds__(256) void hgram_kernel(const T* __restrict__ H, int k, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double Hs[KMAX][65];
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < k * 64; e += 256) {
+    const int i = e / 64, cc = e - (e / 64) * 64;
+    Hs[i][cc] = (c0 + cc < n) ? (double)H[(int64_t)i * n + c0 + cc] : 0.0;
+  }
+  __syncthreads();
+  double* dst = part + (size_t)blockIdx.x * LMAX * LMAX;
+  const int np = k * (k + 1) / 2;
+  for (int q = threadIdx.x; q < np; q += 256) {
+    // q -> (a, b) with a <= b, row-major over the upper triangle
+    int a = 0, rem = q;
+    while (rem >= k - a) { rem -= k - a; ++a; }
+    const int b = a + rem;
+    double s0 = 0.0, s1 = 0.0;
+    for (int cc = 0; cc < 64; cc += 2) {
+      s0 = fma(Hs[a][cc], Hs[b][cc], s0);
+      s1 = fma(Hs[a][cc + 1], Hs[b][cc + 1], s1);
+    }
+    dst[a * LMAX + b] = s0 + s1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, int dt, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(n, 4));
+  if (dt == 0)
+    hipLaunchKernelGGL(hrow_kernel<double>, grid, dim3(256), 0, s, (const double*)R, S, (double*)H, n, k);
+  else
+    hipLaunchKernelGGL(hrow_kernel<float>, grid, dim3(256), 0, s, (const float*)R, S, (float*)H, n, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, int dt, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(m, 128));
+  if (dt == 0)
+    hipLaunchKernelGGL(wrow_kernel<double>, grid, dim3(128), 0, s, (const double*)Tm, V, (double*)W, m, k);
+  else
+    hipLaunchKernelGGL(wrow_kernel<float>, grid, dim3(128), 0, s, (const float*)Tm, V, (float*)W, m, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void* Hp, int dt, hipStream_t s) {
+  int64_t blocks = ceil_div((int64_t)lp * ldp, 256);
+  if (blocks > 4096) blocks = 4096;
+  if (dt == 0)
+    hipLaunchKernelGGL(pad_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const double*)H, k, n, lp,
+                       ldp, (double*)Hp);
+  else
+    hipLaunchKernelGGL(pad_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)H, k, n, lp, ldp,
+                       (float*)Hp);
+  return hipGetLastError();
+}
+
+int hgram_splits(int64_t n) { return (int)ceil_div(n, 64); }
+
+hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s) {
+  dim3 grid((unsigned)hgram_splits(n));
+  if (dt == 0)
+    hipLaunchKernelGGL(hgram_kernel<double>, grid, dim3(256), 0, s, (const double*)H, k, n, part);
+  else
+    hipLaunchKernelGGL(hgram_kernel<float>, grid, dim3(256), 0, s, (const float*)H, k, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace rnmf

@@ -133,6 +133,12 @@ hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart
   return hipGetLastError();
 }
 
+hipError_t launch_gram_sum(const double* gpart, int splits, int l, double* G, hipStream_t s) {
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(ceil_div(l * l, 32)), dim3(256), 0, s, gpart, splits, l, G,
+                     (const unsigned*)nullptr);
+  return hipGetLastError();
+}
+
 // Cholesky of G and the inverse of its factor, one workgroup, FP64 in LDS.
 // Right-looking by columns: at step j the column of L is scaled, then the
 // trailing block of G and the rows of X = L^{-1} below j are updated by rank

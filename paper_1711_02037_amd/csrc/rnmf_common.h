@@ -98,6 +98,16 @@ hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
 int gram_splits(int64_t rows, int cus);
 hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart, int splits,
                        double* G, hipStream_t s, const unsigned* skip = nullptr);
+// Fixed-order sum of Gram partials (entry (a, b), a <= b, at a * LMAX + b).
+hipError_t launch_gram_sum(const double* gpart, int splits, int l, double* G, hipStream_t s);
+
+// hals.hip: deterministic HALS pieces (dt: 0 FP64, 1 FP32).
+hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, int dt, hipStream_t s);
+hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, int dt, hipStream_t s);
+hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void* Hp, int dt, hipStream_t s);
+int hgram_splits(int64_t n);
+hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s);
+
 // One workgroup: Cholesky of G (l x l, FP64) with optional shift; writes the
 // transposed inverse factor packed for the GEMM (lp x lp, dtype cdt) and
 // updates flags.  `pass_ctl`: 0 first pass of a pair, 1 second pass, 2 extra.

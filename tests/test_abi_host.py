@@ -122,3 +122,25 @@ def test_hals_step_validation():
                             None) == rn.ERR_ARG
     assert L.rnmf_hals_step(None, p, 100, 80, 15, 10, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
                             None) == rn.ERR_ARG
+
+
+def test_deterministic_hals_validation():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    o = rn.make_opts(10, 0, 0)
+    assert rn.workspace_bytes(rn.OP_HALS, 1000, 300, o) > 0
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_HALS, 1000, 300, rn.make_opts(10, 0, 0, precision="bf16"))
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_HALS, 1000, 300, rn.make_opts(65, 0, 0))
+    call = lambda opts, xt=rn.F32, k_ok=True, sweeps=1, ldx=300: L.rnmf_hals(
+        p, xt, 1000, 300, ldx, p, p, sweeps, ctypes.byref(opts), p, 1 << 30, None)
+    bad = rn.make_opts(10, 0, 0, tol=1e-4)
+    assert call(bad) == rn.ERR_ARG
+    assert b"tol" in L.rnmf_last_error()
+    assert call(rn.make_opts(10, 0, 0, precision="bf16")) == rn.ERR_ARG
+    assert call(rn.make_opts(301, 0, 0)) == rn.ERR_ARG
+    assert call(o, sweeps=-1) == rn.ERR_ARG
+    assert call(o, ldx=299) == rn.ERR_SHAPE
+    assert call(o, xt=rn.F64) == rn.ERR_DTYPE
+    assert L.rnmf_hals(None, rn.F32, 1000, 300, 300, p, p, 1, ctypes.byref(o), p, 1 << 30, None) == rn.ERR_ARG
