@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target protocol")
+    ap.add_argument("--no-hals", action="store_true", help="skip the deterministic HALS comparison")
+    ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
+                    "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -181,6 +184,15 @@ def main():
     if not args.no_target:
         ttt = time_to_target(rn, torch, X, Om, W0, H0, k, p, q, sweeps, ws, step, reps_f[-1]["rel_err"])
 
+    # ---- deterministic HALS on the same X (Sec. 3.1 vs Sec. 3.2) -------------
+    hals = None
+    if not args.no_hals:
+        hals = hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev=dev)
+        log(f"HALS: {hals['ms_per_sweep']:.3f} ms/sweep, rHALS {hals['rhals_ms_per_sweep']:.3f} ms/sweep, "
+            f"speedup {hals['speedup_per_sweep']:.2f}x per sweep, {hals['speedup_200_sweeps']:.2f}x per run")
+        if args.speedup_ks:
+            hals["by_k"] = speedup_series(rn, torch, X, [int(v) for v in args.speedup_ks.split(",") if v], p, q)
+
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -207,6 +219,7 @@ def main():
                               for kk in ("ms_qb", "ms_sweeps", "ms_error")}},
         "sweeps_per_s_kernel": round(sweeps / (ms_sw * 1e-3), 1),
         "time_to_target": ttt,
+        "hals_vs_rhals": hals,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -252,6 +265,62 @@ def time_to_target(rn, torch, X, Om, W0, H0, k, p, q, sweeps, ws, step, e32_fina
     if res.get("fp32", {}).get("seconds") and res.get("bf16", {}).get("seconds"):
         res["bf16_speedup"] = round(res["fp32"]["seconds"] / res["bf16"]["seconds"], 4)
     return res
+
+
+def hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev):
+    """Deterministic HALS (two passes over X per sweep) against randomized HALS
+    on the same X, W0, H0 and sweep count, FP32: time per sweep (events on the
+    current stream), the error after `sweeps` sweeps, and the speedups."""
+    m, n = X.shape
+    k = H0.shape[0]
+    W, H = W0.clone(), H0.clone()
+    hws = rn._workspace(rn.workspace_bytes(rn.OP_HALS, m, n, rn.make_opts(k, 0, 0)), ws_dev)
+    rn.hals(X, W, H, nsweeps=1, ws=hws)  # warm-up sweep
+    W, H = W0.clone(), H0.clone()
+    st = torch.cuda.current_stream(ws_dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    rn.hals(X, W, H, nsweeps=sweeps, ws=hws)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    err = rn.rel_error(X, W, H)
+    r_ms_sweep = statistics.mean(r["ms_sweeps"] for r in reps_f) / sweeps
+    r_ms_run = statistics.mean(r["ms_qb"] + r["ms_sweeps"] + r["ms_error"] for r in reps_f)
+    return {"precision": "fp32", "sweeps": sweeps, "ms_per_sweep": round(ms / sweeps, 4),
+            "seconds": round(ms / 1e3, 5), "rel_err": err,
+            "rhals_ms_per_sweep": round(r_ms_sweep, 4), "rhals_seconds": round(r_ms_run / 1e3, 5),
+            "rhals_rel_err": reps_f[-1]["rel_err"],
+            "speedup_per_sweep": round(ms / sweeps / r_ms_sweep, 3),
+            "speedup_200_sweeps": round(ms / r_ms_run, 3),
+            "note": "HALS streams X twice per sweep; rHALS streams it (2q+2) times once, then sweeps on B"}
+
+
+def speedup_series(rn, torch, X, ks, p, q, nsw=20):
+    """Per-sweep time of HALS and rHALS for several ranks k (FP32, seeded init)."""
+    out = []
+    m, n = X.shape
+    dev = X.device
+    for k in ks:
+        g = torch.Generator(device="cpu").manual_seed(1000 + k)
+        W0 = torch.rand((m, k), generator=g).to(dev)
+        H0 = torch.rand((k, n), generator=g).to(dev)
+        W, H = W0.clone(), H0.clone()
+        hws = rn._workspace(rn.workspace_bytes(rn.OP_HALS, m, n, rn.make_opts(k, 0, 0)), dev)
+        rn.hals(X, W, H, nsweeps=1, ws=hws)
+        st = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        rn.hals(X, W, H, nsweeps=nsw, ws=hws)
+        e1.record(st)
+        e1.synchronize()
+        h_ms = e0.elapsed_time(e1) / nsw
+        _, _, info = rn.factorize(X, k, p, q, max_iter=nsw, precision="fp32", W0=W0, H0=H0)
+        r_ms = info["ms_sweeps"] / nsw
+        out.append({"k": k, "hals_ms_per_sweep": round(h_ms, 4), "rhals_ms_per_sweep": round(r_ms, 4),
+                    "speedup_per_sweep": round(h_ms / r_ms, 3)})
+        log(f"k={k}: HALS {h_ms:.3f} ms/sweep, rHALS {r_ms:.3f} ms/sweep, {h_ms / r_ms:.2f}x")
+    return out
 
 
 def cpu_baseline(Xh, Omh, W0h, H0h, k, q, sweeps, nsweeps=80):
