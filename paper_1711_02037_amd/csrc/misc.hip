@@ -285,11 +285,138 @@ __global__ __launch_bounds__(1024) void sum_pairs_kernel(const double* __restric
   if (threadIdx.x == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
 }
 
+// FP32 X: ||X - W H||_F^2 and ||X||_F^2 with W H on FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32: lane (i, g) holds A[i][g], B[g][i], and D[4g + e][i]
+// in element e).  A workgroup owns a balanced range of 16-row tiles (wave w:
+// tiles w, w + 8, ...) and keeps their W fragments in registers; H passes
+// through LDS 64 columns at a time (register prefetch, double buffer), and X
+// is read once, in the layout of the MFMA result.  Squared differences are
+// added per tile in FP32 and across tiles in FP64.
+typedef float rfloatx4 __attribute__((ext_vector_type(4)));
+
+template <int RWMAX>
+__global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n,
+                                                          int64_t ldx, const float* __restrict__ W,
+                                                          const float* __restrict__ H, int k, int tiles, int G,
+                                                          double* __restrict__ part) {
+  constexpr int KSM = 16;                 // 4-wide reduction steps, k <= 64
+  constexpr int PF = KSM * 4 * 64 / 512;  // H elements per thread per block
+  __shared__ float hs[2][KSM * 4 * 64];
+  __shared__ double red[2][8];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int i = lane & 15, gq = lane >> 4;
+  const int gidx = blockIdx.x;
+  const int t0 = (int)((int64_t)tiles * gidx / G), t1 = (int)((int64_t)tiles * (gidx + 1) / G);
+  const int nt = t1 - t0;
+  const int ks = (k + 3) >> 2;
+  float wf[RWMAX][KSM];
+#pragma unroll
+  for (int rt = 0; rt < RWMAX; ++rt) {
+    const int tau = wave + 8 * rt;
+    const int64_t r = (int64_t)(t0 + tau) * 16 + i;
+#pragma unroll
+    for (int s = 0; s < KSM; ++s) {
+      const int kk = 4 * s + gq;
+      wf[rt][s] = (tau < nt && r < m && kk < k) ? W[r * k + kk] : 0.0f;
+    }
+  }
+  const int64_t nb = (n + 63) / 64;
+  float pre[PF];
+  auto fetch = [&](int64_t cb) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = t + q * 512;
+      const int kk = e >> 6, c = e & 63;
+      const int64_t col = cb * 64 + c;
+      pre[q] = (kk < k && col < n) ? H[(int64_t)kk * n + col] : 0.0f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = t + q * 512;
+      const int kk = e >> 6, c = e & 63;
+      // fragment layout [s][ct][g][i]: lane (i, g) of column tile ct reads one word
+      hs[buf][((((kk >> 2) * 4) + (c >> 4)) * 4 + (kk & 3)) * 16 + (c & 15)] = pre[q];
+    }
+  };
+  double se = 0.0, sx = 0.0;
+  fetch(0);
+  store(0);
+  __syncthreads();
+  for (int64_t cb = 0; cb < nb; ++cb) {
+    const int buf = (int)(cb & 1);
+    if (cb + 1 < nb) fetch(cb + 1);
+    for (int ct = 0; ct < 4; ++ct) {
+      const int64_t col = cb * 64 + ct * 16 + i;
+      float xv[RWMAX][4];
+#pragma unroll
+      for (int rt = 0; rt < RWMAX; ++rt) {
+        const int tau = wave + 8 * rt;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = (int64_t)(t0 + tau) * 16 + 4 * gq + e;
+          xv[rt][e] = (tau < nt && row < m && col < n) ? X[row * ldx + col] : 0.0f;
+        }
+      }
+      float hf[KSM];
+#pragma unroll
+      for (int s = 0; s < KSM; ++s) hf[s] = (s < ks) ? hs[buf][(s * 4 + ct) * 64 + lane] : 0.0f;
+#pragma unroll
+      for (int rt = 0; rt < RWMAX; ++rt) {
+        if (wave + 8 * rt >= nt) continue;
+        rfloatx4 d = rfloatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KSM; ++s)
+          if (s < ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(wf[rt][s], hf[s], d, 0, 0, 0);
+        float le = 0.0f, lx = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float df = xv[rt][e] - d[e];  // rows and columns outside X hold x = 0 and d = 0
+          le = fmaf(df, df, le);
+          lx = fmaf(xv[rt][e], xv[rt][e], lx);
+        }
+        se += (double)le;
+        sx += (double)lx;
+      }
+    }
+    if (cb + 1 < nb) store(buf ^ 1);
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    se += __shfl_xor(se, o);
+    sx += __shfl_xor(sx, o);
+  }
+  if (lane == 0) { red[0][wave] = se; red[1][wave] = sx; }
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 8; ++w) { a += red[0][w]; b += red[1][w]; }
+    part[2 * gidx] = a;
+    part[2 * gidx + 1] = b;
+  }
+}
+
 int relerr_parts(int64_t m, int64_t n) { return ceil_div(m, 64) * ceil_div(n, 64); }
 
 hipError_t launch_relerr(const void* X, int xt, int dt, int64_t m, int64_t n, int64_t ldx,
                          const void* W, const void* H, int k, double* part, int nparts_max,
                          double* out, hipStream_t s) {
+  if (dt == 1 && xt != 2 && k <= 64) {
+    // one workgroup per CU over balanced 16-row tiles, at most 32 tiles each
+    const int64_t tiles = ceil_div(m, 16);
+    int64_t g = 256;
+    if (g > tiles) g = tiles;
+    if (g < ceil_div(tiles, 32)) g = ceil_div(tiles, 32);
+    if (g <= nparts_max) {
+      hipLaunchKernelGGL(relerr_mfma_kernel<4>, dim3((unsigned)g), dim3(512), 0, s, (const float*)X, m, n, ldx,
+                         (const float*)W, (const float*)H, k, (int)tiles, (int)g, part);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, part, (int)g, out);
+      return hipGetLastError();
+    }
+  }
   int gx = ceil_div(n, 64), gy = ceil_div(m, 64);
   if ((int64_t)gx * gy > nparts_max || gy > 65535) return hipErrorInvalidValue;
   dim3 grid(gx, gy);

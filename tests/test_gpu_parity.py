@@ -406,3 +406,16 @@ def test_compress_streamed_shapes(prec, m, n, ld, l):
     Bo = Qn.astype(np.float64).T @ host(Xd)
     assert np.isfinite(B).all()
     assert relf(B, Bo) <= 1e-5
+
+
+@pytest.mark.parametrize("m,n,k", [(1000, 300, 10), (3001, 2411, 50), (20007, 333, 7), (100000, 130, 64),
+                                   (50, 40, 3)])
+def test_rel_error_matches_fp64(m, n, k):
+    g = s.stream(71, m, n)
+    X = g.random((m, n), dtype=np.float32)
+    W = g.random((m, k), dtype=np.float32)
+    H = (g.random((k, n), dtype=np.float32) / k).astype(np.float32)
+    e = rn.rel_error(dev(X), dev(W), dev(H))
+    Xd = X.astype(np.float64)
+    eo = np.linalg.norm(Xd - W.astype(np.float64) @ H.astype(np.float64)) / np.linalg.norm(Xd)
+    assert abs(e - eo) <= 1e-6 * eo
