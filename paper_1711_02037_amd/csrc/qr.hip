@@ -139,31 +139,45 @@ hipError_t launch_gram_sum(const double* gpart, int splits, int l, double* G, hi
   return hipGetLastError();
 }
 
-// Cholesky of G and the inverse of its factor, one workgroup, FP64 in LDS.
-// Right-looking by columns: at step j the column of L is scaled, then the
-// trailing block of G and the rows of X = L^{-1} below j are updated by rank
-// one (X starts as I; X(j,:) is final once scaled by 1/L(j,j)).  Storage in A:
-// the strict lower triangle holds L, the strict upper triangle holds X
-// transposed (X(i,c) at A[c][i], c < i); dL and dX hold the diagonals.
-// Threads form a 16 x 16 grid for the rank-one updates.
+// Cholesky of G and the inverse of its factor, one workgroup, FP64 in LDS,
+// right-looking in blocks of CB columns.  Storage in A: the strict lower
+// triangle holds L, the strict upper triangle holds X = L^{-1} transposed
+// (X(i,c) at A[c][i], c < i); dL and dX hold the diagonals.  X starts as I.
+// For each block b (rows and columns jb .. jb + nb - 1):
+//   1. wave 0 factors the diagonal block (unblocked, no workgroup barrier);
+//   2. threads by row solve the panel below, L(i,b) = A(i,b) L(b,b)^{-T},
+//      and threads by column finish the block rows of X (forward
+//      substitution with L(b,b) on what earlier blocks left in them);
+//   3. rank-nb updates of the trailing part of A and of the X rows below.
+// Three workgroup barriers per block instead of two per column.
+__device__ __forceinline__ void wave_lds_fence() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <typename OT>
 __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G, int l, int64_t rows,
                                                    OT* __restrict__ At, int lp, unsigned* ctl, int mode,
                                                    int allow_shift, unsigned* status) {
+  constexpr int CB = 8;
   __shared__ double A[LMAX][LMAX + 1];
   __shared__ double dL[LMAX], dX[LMAX];
+  __shared__ int fail_s;
   const int t = threadIdx.x;
-  const int ti = t >> 4, tp = t & 15;
+  const int wave = t >> 6, lane = t & 63;
   if (mode == 2 && ctl && *ctl == 0u) return;  // no shifted pass happened: nothing to do
   bool fail = false;
   int shifted = 0;
   for (int attempt = (allow_shift == 2) ? 1 : 0; attempt < 2; ++attempt) {
     shifted = attempt;
     for (int e = t; e < l * l; e += 256) {
-      int i = e / l, j = e - (e / l) * l;
+      const int i = e / l, j = e - (e / l) * l;
       A[i][j] = (j <= i) ? G[e] : 0.0;
     }
     for (int i = t; i < l; i += 256) dX[i] = 1.0;
+    if (t == 0) fail_s = 0;
+    fail = false;
     __syncthreads();
     if (attempt == 1) {
       double trace = 0.0;
@@ -174,27 +188,85 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G,
       for (int i = t; i < l; i += 256) A[i][i] += shift;
       __syncthreads();
     }
-    fail = false;
-    for (int j = 0; j < l; ++j) {
-      const double d = A[j][j];  // same value in every thread: the branch is uniform
-      if (!(d > 0.0) || !(d < INFINITY)) { fail = true; break; }
-      const double r = sqrt(d), ri = 1.0 / r;
-      const int w = l - j - 1;
-      if (t < w) A[j + 1 + t][j] *= ri;
-      if (t >= 128 && t - 128 <= j) {  // X(j, c) /= L(j, j), c <= j
-        const int c = t - 128;
-        if (c < j) A[c][j] *= ri;
-        else dX[j] *= ri;
+    for (int jb = 0; jb < l; jb += CB) {
+      const int nb = (l - jb < CB) ? l - jb : CB;
+      const int je = jb + nb;
+      // 1. diagonal block by wave 0
+      if (wave == 0) {
+        for (int jj = jb; jj < je; ++jj) {
+          const double d = A[jj][jj];
+          if (!(d > 0.0) || !(d < INFINITY)) {  // uniform across the wave
+            if (lane == 0) fail_s = 1;
+            break;
+          }
+          const double r = sqrt(d), ri = 1.0 / r;
+          const int ii = jj + 1 + lane;
+          if (ii < je) A[ii][jj] *= ri;
+          if (lane == 0) dL[jj] = r;
+          wave_lds_fence();
+          // within-block trailing update: pairs (ii, pp), jj < pp <= ii < je
+          const int w = je - jj - 1;
+          for (int q = lane; q < w * w; q += 64) {
+            const int a = jj + 1 + q / w, b = jj + 1 + q - (q / w) * w;
+            if (b <= a) A[a][b] -= A[a][jj] * A[b][jj];
+          }
+          wave_lds_fence();
+        }
       }
-      if (t == 0) dL[j] = r;
       __syncthreads();
-      for (int i = j + 1 + ti; i < l; i += 16) {
-        const double lij = A[i][j];
-        for (int p = j + 1 + tp; p <= i; p += 16) A[i][p] -= lij * A[p][j];
-        for (int c = tp; c <= j; c += 16) {
-          const double xjc = (c < j) ? A[c][j] : dX[j];
-          if (c < j) A[c][i] -= lij * xjc;
-          else A[j][i] -= lij * xjc;
+      if (fail_s) { fail = true; break; }
+      // 2a. panel rows i >= je (threads t < 128): forward substitution with L(b,b)
+      if (t < 128) {
+        const int i = je + t;
+        if (i < l) {
+          for (int jj = jb; jj < je; ++jj) {
+            double x = A[i][jj];
+            for (int p = jb; p < jj; ++p) x -= A[i][p] * A[jj][p];
+            A[i][jj] = x / dL[jj];
+          }
+        }
+      } else {
+        // 2b. block rows of X, column c < je (threads t >= 128): row jj of X
+        // becomes (X(jj,:) - sum_{jb <= p < jj} L(jj,p) X(p,:)) / L(jj,jj)
+        const int c = t - 128;
+        if (c < je) {
+          for (int jj = (c > jb ? c : jb); jj < je; ++jj) {
+            double x = (jj == c) ? dX[jj] : A[c][jj];
+            for (int p = (c > jb ? c : jb); p < jj; ++p) {
+              const double xp = (p == c) ? dX[p] : A[c][p];
+              x -= A[jj][p] * xp;
+            }
+            x /= dL[jj];
+            if (jj == c) dX[jj] = x;
+            else A[c][jj] = x;
+          }
+        }
+      }
+      __syncthreads();
+      // 3. rank-nb updates below the block: A(i,p) for je <= p <= i, and X(i,c)
+      //    for i >= je, c < je
+      const int w = l - je;
+      const int na = w * (w + 1) / 2, nx = w * je;
+      for (int q = t; q < na + nx; q += 256) {
+        if (q < na) {
+          // q -> (i, p) with p <= i, row-major over the lower triangle
+          int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+          while ((i + 1) * (i + 2) / 2 <= q) ++i;
+          while (i * (i + 1) / 2 > q) --i;
+          const int pp = q - i * (i + 1) / 2;
+          const int ri = je + i, rp = je + pp;
+          double acc = A[ri][rp];
+          for (int cc = jb; cc < je; ++cc) acc -= A[ri][cc] * A[rp][cc];
+          A[ri][rp] = acc;
+        } else {
+          const int e = q - na;
+          const int i = je + e / je, c = e - (e / je) * je;
+          double acc = A[c][i];
+          for (int qq = (c > jb ? c : jb); qq < je; ++qq) {
+            const double xq = (qq == c) ? dX[qq] : A[c][qq];
+            acc -= A[i][qq] * xq;
+          }
+          A[c][i] = acc;
         }
       }
       __syncthreads();
@@ -215,11 +287,11 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G,
   }
   // At[c][k] = X(c, k) for k <= c, zero elsewhere (lp x lp, packed)
   for (int e = t; e < lp * lp; e += 256) {
-    int c = e / lp, k = e - (e / lp) * lp;
+    const int c = e / lp, kk = e - (e / lp) * lp;
     double v = 0.0;
-    if (c < l && k < l) {
-      if (k == c) v = dX[c];
-      else if (k < c) v = A[k][c];
+    if (c < l && kk < l) {
+      if (kk == c) v = dX[c];
+      else if (kk < c) v = A[kk][c];
     }
     At[e] = (OT)v;
   }
