@@ -27,6 +27,8 @@ from .rhals import (  # noqa: F401
     GRAM_MIXED,
     ORDER_H_FIRST,
     ORDER_W_FIRST,
+    NO_REG,
+    Reg,
     clip,
     qr_positive,
     range_finder,
@@ -40,5 +42,6 @@ from .rhals import (  # noqa: F401
     projected_gradient_sq,
     projected_gradient_sq_compressed,
     rel_error,
+    objective,
     sketch_width,
 )

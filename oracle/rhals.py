@@ -40,7 +40,23 @@ R10 The projected gradient of Sec. 3.3 is evaluated after each full sweep, with
     taken on the surrogate X^ = Q B.
 R11 "Relative error" is ||X - W H||_F / ||X||_F, computed directly.
 R12 max(0, x) is computed as (x if x > 0 else +0).
+R18 Regularized rules (Sec. 3.4 and its appendix) are taken as printed: the
+    ridge weight alpha enlarges the scale (S_jj + alpha, V_jj + alpha) and
+    damps the old block by S_jj / (S_jj + alpha); the LASSO weight beta is
+    subtracted from the cross product.  These are the exact block minimisers of
+    1/2 ||X - W H||_F^2 + alpha/2 ||F||_F^2 + beta sum(F) over F >= 0, so the
+    projected gradient of Sec. 3.3 gains + alpha F + beta (factor 2 dropped as
+    in R10).  The H rule's misprinted W^T W~ in the first scale is read as the
+    scale used everywhere else.  The elastic net (the two combined) keeps
+    these letters: alpha for the squared norm, beta for the 1-norm.
+R19 In randomized HALS the ridge part acts on W~ (it is linear) while the
+    LASSO shift beta / (V_jj + alpha) is applied to the lifted column before
+    the clip: substituting X ~ Q B and W ~ Q W~ into the printed W rule leaves
+    the all-ones m-vector outside the range of Q.  With Q square and
+    orthogonal the sweep is the deterministic regularized sweep.
 """
+
+from typing import NamedTuple
 
 import numpy as np
 
@@ -50,6 +66,19 @@ GRAM_MIXED = 2    # numerator W~^T W~, scale (W^T W)_jj (Sec. 3.2, note)
 
 ORDER_H_FIRST = 0  # Algorithm 1: rows of H, then columns of W
 ORDER_W_FIRST = 1  # Sec. 3.2, second cyclic order: columns of W, then rows of H
+
+
+class Reg(NamedTuple):
+    """Regularization weights of Sec. 3.4 (reading R18): alpha_* for the
+    squared Frobenius norm (ridge), beta_* for the 1-norm (LASSO); both
+    nonzero is the elastic net.  All zero is plain HALS."""
+    alpha_w: float = 0.0
+    alpha_h: float = 0.0
+    beta_w: float = 0.0
+    beta_h: float = 0.0
+
+
+NO_REG = Reg()
 
 
 def clip(x):
@@ -136,30 +165,35 @@ def qb_streaming(X, Omega, q, block=1):
 # Sweeps
 # ----------------------------------------------------------------------------
 
-def _h_rows(H, R, S_num, S_scale):
+def _h_rows(H, R, S_num, S_scale, alpha=0.0, beta=0.0):
     """Row-by-row H update, Gauss-Seidel over j (Algorithm 1; Sec. 3.1 and 3.2
-    H rules): H(j,:) <- [H(j,:) + (R(:,j) - H^T S(:,j)) / S_jj]_+ , with the
-    numerator Gram S_num and the scale S_scale (equal except in GRAM_MIXED).
-    Rows with zero scale are skipped (reading R9)."""
+    H rules, with the regularized form of Sec. 3.4):
+    H(j,:) <- [s/(s+alpha) H(j,:) + (R(:,j) - beta - H^T S(:,j)) / (s+alpha)]_+
+    with s = S_jj, the numerator Gram S_num and the scale S_scale (equal except
+    in GRAM_MIXED).  Rows with zero scale s + alpha are skipped (reading R9).
+    With alpha = beta = 0 this is the plain rule to the last bit."""
     k = H.shape[0]
     for j in range(k):
-        d = S_scale[j, j]
+        s = S_scale[j, j]
+        d = s + alpha
         if d > 0.0:
-            H[j, :] = clip(H[j, :] + (R[:, j] - H.T @ S_num[:, j]) / d)
+            H[j, :] = clip(s / d * H[j, :] + (R[:, j] - beta - H.T @ S_num[:, j]) / d)
     return H
 
 
-def rhals_sweep(Q, B, W, Wt, H, gram_mode=GRAM_FULL, order=ORDER_H_FIRST):
+def rhals_sweep(Q, B, W, Wt, H, gram_mode=GRAM_FULL, order=ORDER_H_FIRST, reg=NO_REG):
     """One sweep of randomized HALS (Algorithm 1; Sec. 3.2).
 
     Q: m x l orthonormal basis; B: l x n compressed data; W: m x k; Wt: the
     compressed factor W~ (l x k); H: k x n.  Returns new copies (W, Wt, H).
 
     H phase:  R = B^T W~, S = W^T W (see GRAM_*), then rows of H in turn.
-    W phase:  T = B H^T, V = H H^T, then for each column j:
-              W~(:,j) <- W~(:,j) + (T(:,j) - W~ V(:,j)) / V_jj   (no clip)
-              W(:,j)  <- [Q W~(:,j)]_+                          (lift, clip)
-              W~(:,j) <- Q^T W(:,j)                             (map back)
+    W phase:  T = B H^T, V = H H^T, then for each column j (d = V_jj + alpha_w):
+              W~(:,j) <- V_jj/d W~(:,j) + (T(:,j) - W~ V(:,j)) / d   (no clip)
+              W(:,j)  <- [Q W~(:,j) - beta_w / d]_+                 (lift, clip)
+              W~(:,j) <- Q^T W(:,j)                                 (map back)
+    The regularization terms follow Sec. 3.4 (readings R18, R19); with the
+    default zero weights they vanish exactly.
     """
     Q = np.asarray(Q, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
@@ -179,16 +213,17 @@ def rhals_sweep(Q, B, W, Wt, H, gram_mode=GRAM_FULL, order=ORDER_H_FIRST):
             S_scale = W.T @ W
         else:
             raise ValueError("unknown gram_mode")
-        _h_rows(H, R, S_num, S_scale)
+        _h_rows(H, R, S_num, S_scale, reg.alpha_h, reg.beta_h)
 
     def w_phase():
         T = B @ H.T
         V = H @ H.T
         for j in range(k):
-            d = V[j, j]
+            v = V[j, j]
+            d = v + reg.alpha_w
             if d > 0.0:
-                Wt[:, j] = Wt[:, j] + (T[:, j] - Wt @ V[:, j]) / d
-                W[:, j] = clip(Q @ Wt[:, j])
+                Wt[:, j] = v / d * Wt[:, j] + (T[:, j] - Wt @ V[:, j]) / d
+                W[:, j] = clip(Q @ Wt[:, j] - reg.beta_w / d)
                 Wt[:, j] = Q.T @ W[:, j]
 
     if order == ORDER_H_FIRST:
@@ -202,11 +237,13 @@ def rhals_sweep(Q, B, W, Wt, H, gram_mode=GRAM_FULL, order=ORDER_H_FIRST):
     return W, Wt, H
 
 
-def hals_sweep(X, W, H, order=ORDER_H_FIRST):
-    """One sweep of deterministic HALS with the residual-free rules of Sec. 3.1:
-    H(j,:) <- [H(j,:) + ((X^T W)(:,j) - H^T (W^T W)(:,j)) / (W^T W)_jj]_+ and
-    W(:,j) <- [W(:,j) + ((X H^T)(:,j) - W (H H^T)(:,j)) / (H H^T)_jj]_+ .
-    Returns new copies (W, H)."""
+def hals_sweep(X, W, H, order=ORDER_H_FIRST, reg=NO_REG):
+    """One sweep of deterministic HALS with the residual-free rules of Sec. 3.1
+    and their regularized form of Sec. 3.4 (reading R18):
+    H(j,:) <- [s/(s+a_h) H(j,:) + ((X^T W)(:,j) - b_h - H^T (W^T W)(:,j)) / (s+a_h)]_+
+    with s = (W^T W)_jj, and
+    W(:,j) <- [v/(v+a_w) W(:,j) + ((X H^T)(:,j) - b_w - W (H H^T)(:,j)) / (v+a_w)]_+
+    with v = (H H^T)_jj.  Returns new copies (W, H)."""
     X = np.asarray(X, dtype=np.float64)
     W = np.array(W, dtype=np.float64)
     H = np.array(H, dtype=np.float64)
@@ -214,15 +251,16 @@ def hals_sweep(X, W, H, order=ORDER_H_FIRST):
 
     def h_phase():
         S = W.T @ W
-        _h_rows(H, X.T @ W, S, S)
+        _h_rows(H, X.T @ W, S, S, reg.alpha_h, reg.beta_h)
 
     def w_phase():
         V = H @ H.T
         P = X @ H.T
         for j in range(k):
-            d = V[j, j]
+            v = V[j, j]
+            d = v + reg.alpha_w
             if d > 0.0:
-                W[:, j] = clip(W[:, j] + (P[:, j] - W @ V[:, j]) / d)
+                W[:, j] = clip(v / d * W[:, j] + (P[:, j] - reg.beta_w - W @ V[:, j]) / d)
 
     if order == ORDER_H_FIRST:
         h_phase()
@@ -245,31 +283,45 @@ def _proj(G, F):
     return np.where(F > 0.0, G, np.minimum(G, 0.0))
 
 
-def projected_gradient_sq(X, W, H):
+def projected_gradient_sq(X, W, H, reg=NO_REG):
     """||grad^P f(W, H)||_F^2 for f = ||X - W H||_F^2 (Sec. 3.3), with the
     gradients W (H H^T) - X H^T and (W^T W) H - W^T X (factor 2 dropped,
-    reading R10)."""
+    reading R10), plus alpha F + beta for the regularized cost (R18)."""
     X = np.asarray(X, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     H = np.asarray(H, dtype=np.float64)
-    GW = W @ (H @ H.T) - X @ H.T
-    GH = (W.T @ W) @ H - W.T @ X
+    GW = W @ (H @ H.T) - X @ H.T + reg.alpha_w * W + reg.beta_w
+    GH = (W.T @ W) @ H - W.T @ X + reg.alpha_h * H + reg.beta_h
     return float(np.sum(_proj(GW, W) ** 2) + np.sum(_proj(GH, H) ** 2))
 
 
-def projected_gradient_sq_compressed(Q, B, W, Wt, H):
+def projected_gradient_sq_compressed(Q, B, W, Wt, H, reg=NO_REG):
     """Projected-gradient norm of Sec. 3.3 evaluated on the surrogate
     X^ = Q B without forming it (reading R10): the W gradient is
     W (H H^T) - Q (B H^T) and the H gradient is (W^T W) H - W~^T B, which
-    equals (W^T W) H - W^T X^ when W~ = Q^T W."""
+    equals (W^T W) H - W^T X^ when W~ = Q^T W; the regularized cost adds
+    alpha F + beta to each (R18)."""
     Q = np.asarray(Q, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     Wt = np.asarray(Wt, dtype=np.float64)
     H = np.asarray(H, dtype=np.float64)
-    GW = W @ (H @ H.T) - Q @ (B @ H.T)
-    GH = (W.T @ W) @ H - Wt.T @ B
+    GW = W @ (H @ H.T) - Q @ (B @ H.T) + reg.alpha_w * W + reg.beta_w
+    GH = (W.T @ W) @ H - Wt.T @ B + reg.alpha_h * H + reg.beta_h
     return float(np.sum(_proj(GW, W) ** 2) + np.sum(_proj(GH, H) ** 2))
+
+
+def objective(X, W, H, reg=NO_REG):
+    """The regularized cost whose block minimisers are the rules of Sec. 3.4
+    (reading R18): 1/2 ||X - W H||_F^2 + alpha/2 ||F||_F^2 + beta sum(F) for
+    F = W, H (nonnegative factors, so sum(F) is the 1-norm)."""
+    X = np.asarray(X, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    H = np.asarray(H, dtype=np.float64)
+    E = X - W @ H
+    return float(0.5 * np.sum(E * E)
+                 + 0.5 * reg.alpha_w * np.sum(W * W) + reg.beta_w * np.sum(W)
+                 + 0.5 * reg.alpha_h * np.sum(H * H) + reg.beta_h * np.sum(H))
 
 
 def rel_error(X, W, H):
@@ -284,7 +336,7 @@ def rel_error(X, W, H):
 # ----------------------------------------------------------------------------
 
 def rhals(X, k, Omega, W0, H0, q=2, max_iter=100, tol=0.0,
-          gram_mode=GRAM_FULL, order=ORDER_H_FIRST, trace=False):
+          gram_mode=GRAM_FULL, order=ORDER_H_FIRST, trace=False, reg=NO_REG):
     """Randomized HALS, Algorithm 1.
 
     Omega (n x l), W0 (m x k) and H0 (k x n) are supplied by the caller; the
@@ -302,49 +354,49 @@ def rhals(X, k, Omega, W0, H0, q=2, max_iter=100, tol=0.0,
     W = np.array(W0, dtype=np.float64)
     H = np.array(H0, dtype=np.float64)
     Wt = Q.T @ W                                     # reading R4
-    pg0 = projected_gradient_sq_compressed(Q, B, W, Wt, H)
+    pg0 = projected_gradient_sq_compressed(Q, B, W, Wt, H, reg)
     it = 0
     ratio = 1.0
     errs = []
     while it < max_iter:
-        W, Wt, H = rhals_sweep(Q, B, W, Wt, H, gram_mode, order)
+        W, Wt, H = rhals_sweep(Q, B, W, Wt, H, gram_mode, order, reg)
         it += 1
         if trace:
             errs.append(rel_error(X, W, H))
         if tol > 0.0:
-            pg = projected_gradient_sq_compressed(Q, B, W, Wt, H)
+            pg = projected_gradient_sq_compressed(Q, B, W, Wt, H, reg)
             ratio = pg / pg0 if pg0 > 0 else 0.0
             if ratio < tol:
                 break
     if tol <= 0.0:
-        pg = projected_gradient_sq_compressed(Q, B, W, Wt, H)
+        pg = projected_gradient_sq_compressed(Q, B, W, Wt, H, reg)
         ratio = pg / pg0 if pg0 > 0 else 0.0
     info = dict(Q=Q, B=B, Wt=Wt, iters=it, rel_err=rel_error(X, W, H),
                 pg_ratio=ratio, trace=errs)
     return W, H, info
 
 
-def hals(X, W0, H0, max_iter=100, tol=0.0, order=ORDER_H_FIRST, trace=False):
+def hals(X, W0, H0, max_iter=100, tol=0.0, order=ORDER_H_FIRST, trace=False, reg=NO_REG):
     """Deterministic HALS (Sec. 3.1) with the stopping rule of Sec. 3.3.
     Returns (W, H, info) with iters, rel_err, pg_ratio and an optional per-sweep
     error trace."""
     X = np.asarray(X, dtype=np.float64)
     W = np.array(W0, dtype=np.float64)
     H = np.array(H0, dtype=np.float64)
-    pg0 = projected_gradient_sq(X, W, H)
+    pg0 = projected_gradient_sq(X, W, H, reg)
     it = 0
     ratio = 1.0
     errs = []
     while it < max_iter:
-        W, H = hals_sweep(X, W, H, order)
+        W, H = hals_sweep(X, W, H, order, reg)
         it += 1
         if trace:
             errs.append(rel_error(X, W, H))
         if tol > 0.0:
-            ratio = projected_gradient_sq(X, W, H) / pg0 if pg0 > 0 else 0.0
+            ratio = projected_gradient_sq(X, W, H, reg) / pg0 if pg0 > 0 else 0.0
             if ratio < tol:
                 break
     if tol <= 0.0:
-        ratio = projected_gradient_sq(X, W, H) / pg0 if pg0 > 0 else 0.0
+        ratio = projected_gradient_sq(X, W, H, reg) / pg0 if pg0 > 0 else 0.0
     return W, H, dict(iters=it, rel_err=rel_error(X, W, H), pg_ratio=ratio,
                       trace=errs)
