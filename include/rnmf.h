@@ -93,6 +93,16 @@ enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
 #define RNMF_FLAG_SHIFTED_QR3 0x10u     /* every QR: shifted Cholesky QR pass first, then
                                            two plain passes (shifted CholeskyQR3)   */
 
+/* Regularization (Sec. 3.4 and its appendix): the cost becomes
+ *   1/2 ||X - W H||_F^2 + alpha_w/2 ||W||_F^2 + beta_w sum(W)
+ *                       + alpha_h/2 ||H||_F^2 + beta_h sum(H),
+ * whose exact block minimisers are the printed rules: the ridge weight alpha
+ * is added to the scale (S_jj + alpha_h for a row of H, V_jj + alpha_w for a
+ * column of W) and the LASSO weight beta is subtracted from the cross product;
+ * both nonzero is the elastic net.  In the compressed sweep the ridge part acts
+ * on W~ and the LASSO shift beta_w / (V_jj + alpha_w) is subtracted from the
+ * lifted column Q W~(:,j) before the clip.  The stop test uses the gradient of
+ * this cost.  All four zero (the default) is plain HALS, bit for bit. */
 typedef struct rnmf_opts {
   int32_t k;          /* target rank, 1 <= k < min(m, n)                        */
   int32_t p;          /* oversampling (paper default 20); l = min(k+p, m, n)    */
@@ -106,6 +116,10 @@ typedef struct rnmf_opts {
   int32_t order;      /* RNMF_ORDER_*                                            */
   uint32_t flags;     /* RNMF_FLAG_*                                             */
   int32_t reserved;   /* must be 0                                               */
+  double alpha_w;     /* ridge weight on W, >= 0 (0: none)                       */
+  double alpha_h;     /* ridge weight on H, >= 0                                 */
+  double beta_w;      /* LASSO weight on W, >= 0 (0: none)                       */
+  double beta_h;      /* LASSO weight on H, >= 0                                 */
 } rnmf_opts;
 
 typedef struct rnmf_report {

@@ -46,7 +46,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("prec", ctypes.c_int32), ("omega_dist", ctypes.c_int32), ("gram_mode", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("alpha_w", ctypes.c_double), ("alpha_h", ctypes.c_double), ("beta_w", ctypes.c_double),
+                ("beta_h", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -128,7 +130,9 @@ def _check(status, allow=()):
 
 
 def make_opts(k, p=20, q=2, max_iter=200, tol=0.0, seed=0, precision="fp32", omega="gaussian",
-              gram="full", order="h_first", check_input=True, shift=True, exact_q=False):
+              gram="full", order="h_first", check_input=True, shift=True, exact_q=False, reg=None):
+    """rnmf_opts from keyword arguments.  reg: None or a mapping with any of
+    alpha_w, alpha_h (ridge) and beta_w, beta_h (LASSO) weights (Sec. 3.4)."""
     o = Opts()
     lib().rnmf_default_opts(ctypes.byref(o))
     o.k, o.p, o.q, o.max_iter = int(k), int(p), int(q), int(max_iter)
@@ -139,7 +143,16 @@ def make_opts(k, p=20, q=2, max_iter=200, tol=0.0, seed=0, precision="fp32", ome
     # False = never, "always" = shifted CholeskyQR3 for every QR
     o.flags = (FLAG_CHECK_INPUT if check_input else 0) | (0 if shift else FLAG_NO_SHIFT) | \
         (FLAG_SHIFTED_QR3 if shift == "always" else 0) | (FLAG_EXACT_Q if exact_q else 0)
+    if reg:
+        unknown = set(reg) - set(REG_KEYS)
+        if unknown:
+            raise ValueError(f"unknown regularization keys {sorted(unknown)}")
+        for key in REG_KEYS:
+            setattr(o, key, float(reg.get(key, 0.0)))
     return o
+
+
+REG_KEYS = ("alpha_w", "alpha_h", "beta_w", "beta_h")
 
 
 def sketch_width(k, p, m, n):
@@ -250,8 +263,9 @@ def compress(X, Q, precision="fp32", ws=None):
 
 
 def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, ws=None,
-              trace=False):
-    """nsweeps compressed HALS sweeps in place on W, Wt, H (rnmf_hals_step).
+              trace=False, reg=None):
+    """nsweeps compressed HALS sweeps in place on W, Wt, H (rnmf_hals_step);
+    reg: optional ridge / LASSO weights (see make_opts).
     Returns (sweeps done, pg^2 at entry, pg^2 at exit), plus the list of phase
     timestamps in microseconds when trace is set."""
     torch = _torch()
@@ -260,7 +274,7 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
     m, l = Q.shape
     k, n = H.shape
     prec = precision or ("fp64" if Q.dtype == torch.float64 else "fp32")
-    o = make_opts(k, l - k, 0, tol=tol, precision=prec, gram=gram, order=order)
+    o = make_opts(k, l - k, 0, tol=tol, precision=prec, gram=gram, order=order, reg=reg)
     if trace:
         o.flags |= FLAG_TRACE
     nb = workspace_bytes(OP_HALS_STEP, m, n, o)
@@ -277,9 +291,10 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
     return int(s[0]), s[1], s[2]
 
 
-def hals(X, W, H, nsweeps=1, order="h_first", ws=None):
+def hals(X, W, H, nsweeps=1, order="h_first", ws=None, reg=None):
     """nsweeps sweeps of deterministic HALS on X itself, in place on W and H
-    (rnmf_hals; Sec. 3.1).  X, W, H: FP32 or FP64 (all the same dtype)."""
+    (rnmf_hals; Sec. 3.1, regularized form of Sec. 3.4 when reg is given).
+    X, W, H: FP32 or FP64 (all the same dtype)."""
     torch = _torch()
     _need_dev(X, "X"); _rowmajor(X, "X")
     for t, nm in ((W, "W"), (H, "H")):
@@ -289,7 +304,7 @@ def hals(X, W, H, nsweeps=1, order="h_first", ws=None):
     if W.shape != (m, k) or H.shape != (k, n) or W.dtype != X.dtype or H.dtype != X.dtype:
         raise ValueError("need W (m x k) and H (k x n) in the dtype of X")
     prec = "fp64" if X.dtype == torch.float64 else "fp32"
-    o = make_opts(k, 0, 0, precision=prec, order=order)
+    o = make_opts(k, 0, 0, precision=prec, order=order, reg=reg)
     nb = workspace_bytes(OP_HALS, m, n, o)
     keep, w = ws if ws is not None else _workspace(nb, X.device)
     _check(lib().rnmf_hals(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(W), _ptr(H), int(nsweeps), ctypes.byref(o),
@@ -316,13 +331,14 @@ def rel_error(X, W, H, ws=None):
 
 def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, omega=None, W0=None,
               H0=None, gram="full", order="h_first", omega_dist="gaussian", check_input=True, shift=True,
-              exact_q=False, ws=None):
-    """Algorithm 1 end to end (rnmf_factorize).  Returns (W, H, report dict)."""
+              exact_q=False, ws=None, reg=None):
+    """Algorithm 1 end to end (rnmf_factorize).  Returns (W, H, report dict).
+    reg: optional ridge / LASSO weights (Sec. 3.4; see make_opts)."""
     torch = _torch()
     _need_dev(X, "X"); _rowmajor(X, "X")
     m, n = X.shape
     o = make_opts(k, p, q, max_iter, tol, seed, precision, omega_dist, gram, order, check_input, shift,
-                  exact_q)
+                  exact_q, reg)
     dt = _fdtype(precision)
     for t, nm in ((omega, "omega"), (W0, "W0"), (H0, "H0")):
         if t is not None:

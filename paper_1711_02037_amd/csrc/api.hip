@@ -102,6 +102,16 @@ int lwidth(const rnmf_opts* o, int64_t m, int64_t n) {
   return (int)l;
 }
 
+rnmf_status check_reg(const rnmf_opts* o) {
+  const double w[4] = {o->alpha_w, o->alpha_h, o->beta_w, o->beta_h};
+  for (double v : w)
+    if (!(v >= 0.0) || !(v < INFINITY))
+      return fail(RNMF_ERR_ARG, "regularization weights must be finite and >= 0");
+  return RNMF_OK;
+}
+
+Reg reg_of(const rnmf_opts* o) { return Reg{o->alpha_w, o->alpha_h, o->beta_w, o->beta_h}; }
+
 rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax) {
   if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
   if (o->reserved != 0) return fail(RNMF_ERR_ARG, "opts.reserved must be 0");
@@ -120,6 +130,7 @@ rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax)
                    RNMF_FLAG_SHIFTED_QR3))
     return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
   if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
+  if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
   int l = lwidth(o, m, n);
   if (l > LMAX) return fail(RNMF_ERR_ARG, "sketch width l = min(k + p, m, n) = %d exceeds %d", l, LMAX);
   if (need_kmax && o->k > KMAX) return fail(RNMF_ERR_ARG, "k = %d exceeds the supported %d", o->k, KMAX);
@@ -604,6 +615,7 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
   if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode");
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
+  if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
   const Mode md = mode_of(o);
@@ -622,7 +634,7 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
     trace = (u64*)((char*)ws + TRACE_OFFSET);
     HIPCHK(launch_fill_u32((unsigned*)trace, (HDR_BYTES - TRACE_OFFSET) / 4, 0u, d.stream));
   }
-  HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, b.xbuf,
+  HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, reg_of(o), b.xbuf,
                       stats, h.status, trace, d.stream));
   return RNMF_OK;
 }
@@ -641,6 +653,7 @@ rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, 
     return fail(RNMF_ERR_ARG, "deterministic HALS runs in RNMF_PREC_F32 or RNMF_PREC_F64");
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
   if (o->tol > 0.0) return fail(RNMF_ERR_ARG, "deterministic HALS runs a fixed number of sweeps (tol must be <= 0)");
+  if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
   rnmf_status r;
   if ((r = check_xt(o, xt)) != RNMF_OK) return r;
   Dev d;
@@ -660,7 +673,7 @@ rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, 
     HIPCHK(launch_pack_t(W, md.dt, m, k, lp, b.ldpm, b.wp, md.cdt, s));
     HIPCHK(launch_tn(X, md.cdt, m, n, ldx, b.wp, b.ldpm, k, b.R, 0, b.part, b.tn, s));
     HIPCHK(launch_gram(W, md.dt, m, k, b.gpart, b.gsplits, b.S, s));
-    HIPCHK(launch_hrow(b.R, b.S, H, n, k, md.dt, s));
+    HIPCHK(launch_hrow(b.R, b.S, H, n, k, o->alpha_h, o->beta_h, md.dt, s));
     return RNMF_OK;
   };
   auto w_phase = [&]() -> rnmf_status {
@@ -669,7 +682,7 @@ rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, 
     HIPCHK(launch_hgram(H, k, n, b.hpart, md.dt, s));
     HIPCHK(launch_gram_sum(b.hpart, hs, k, b.V, s));
     HIPCHK(launch_nn(X, md.cdt, m, n, ldx, b.hp, b.ldpn, k, b.T, b.part, b.nn, h.status, 0, s));
-    HIPCHK(launch_wrow(b.T, b.V, W, m, k, md.dt, s));
+    HIPCHK(launch_wrow(b.T, b.V, W, m, k, o->alpha_w, o->beta_w, md.dt, s));
     return RNMF_OK;
   };
   for (int it = 0; it < nsweeps; ++it) {
@@ -752,7 +765,7 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, 1, s));
   if ((r = run_init_wt(Q, W, m, k, l, Wt, ib, md, d)) != RNMF_OK) return r;
   HIPCHK(hipEventRecord(ev[1], s));
-  HIPCHK(launch_sweep(wb.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, o->max_iter, o->tol, o->gram_mode, o->order,
+  HIPCHK(launch_sweep(wb.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, o->max_iter, o->tol, o->gram_mode, o->order, reg_of(o),
                       wb.xbuf, h.stats, h.status, nullptr, s));
   HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_relerr(X, xt, md.dt, m, n, ldx, W, H, k, rb.part, rb.np, h.rel, s));

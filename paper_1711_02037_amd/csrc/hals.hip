@@ -26,9 +26,12 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // Rows of H, one wave per column c of H: lane i holds H(i, c) and the running
 // gradient g_i = R(c, i) - sum_p S(p, i) H(p, c) (FP64); the Gauss-Seidel
 // step for row j broadcasts lane j's values and updates every g by rank one.
+// Regularized rule (Sec. 3.4): the scale is S_jj + ah and the numerator gains
+// - bh - ah H(j, c); since lane j's g is read only at step j, when H(j, c)
+// still holds its old value, that constant is folded into g at the start.
 template <typename T>
 __global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, const double* __restrict__ S,
-                                                   T* __restrict__ H, int64_t n, int k) {
+                                                   T* __restrict__ H, int64_t n, int k, double ah, double bh) {
   __shared__ double Ss[KMAX * KMAX];
   for (int e = threadIdx.x; e < k * k; e += 256) Ss[e] = S[e];
   __syncthreads();
@@ -39,8 +42,10 @@ __global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, cons
   double h = lane < k ? (double)H[(int64_t)lane * n + c] : 0.0;
   double g = lane < k ? (double)R[c * k + lane] : 0.0;
   for (int p = 0; p < k; ++p) g = fma(-Ss[p * k + i], readlane_d(h, p), g);
+  g -= fma(ah, h, bh);
   if (lane >= k) g = 0.0;
-  const double rs = (lane < k && Ss[i * k + i] > 0.0) ? 1.0 / Ss[i * k + i] : 0.0;
+  const double dj = Ss[i * k + i] + ah;
+  const double rs = (lane < k && dj > 0.0) ? 1.0 / dj : 0.0;
   for (int j = 0; j < k; ++j) {
     const double rd = readlane_d(rs, j);
     if (rd > 0.0) {
@@ -57,9 +62,10 @@ __global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, cons
 
 // Columns of W, one thread per row r: the row and V live in LDS (FP64); for
 // each column j the update uses the row as already updated (Gauss-Seidel).
+// Regularized rule (Sec. 3.4): scale V_jj + aw, numerator - bw - aw W(r, j).
 template <typename T>
 __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, const double* __restrict__ V,
-                                                   T* __restrict__ W, int64_t m, int k) {
+                                                   T* __restrict__ W, int64_t m, int k, double aw, double bw) {
   __shared__ double Vs[KMAX * KMAX];
   __shared__ double ws[KMAX][128];
   for (int e = threadIdx.x; e < k * k; e += 128) Vs[e] = V[e];
@@ -70,7 +76,7 @@ __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, con
   __syncthreads();
   if (!live) return;
   for (int j = 0; j < k; ++j) {
-    const double d = Vs[j * k + j];
+    const double d = Vs[j * k + j] + aw;
     if (!(d > 0.0)) continue;
     double s0 = 0.0, s1 = 0.0;
     int p = 0;
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, con
       s1 = fma(ws[p + 1][t], Vs[(p + 1) * k + j], s1);
     }
     for (; p < k; ++p) s0 = fma(ws[p][t], Vs[p * k + j], s0);
-    const double num = (double)Tm[r * k + j] - (s0 + s1);
+    const double num = ((double)Tm[r * k + j] - (s0 + s1)) - fma(aw, ws[j][t], bw);
     ws[j][t] = (double)clip0h<T>((T)(ws[j][t] + num / d));
   }
   for (int q = 0; q < k; ++q) W[r * k + q] = (T)ws[q][t];
@@ -127,21 +133,23 @@ __global__ __launch_bounds__(256) void hgram_kernel(const T* __restrict__ H, int
 
 }  // namespace
 
-hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, int dt, hipStream_t s) {
+hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, double ah, double bh, int dt,
+                       hipStream_t s) {
   dim3 grid((unsigned)ceil_div(n, 4));
   if (dt == 0)
-    hipLaunchKernelGGL(hrow_kernel<double>, grid, dim3(256), 0, s, (const double*)R, S, (double*)H, n, k);
+    hipLaunchKernelGGL(hrow_kernel<double>, grid, dim3(256), 0, s, (const double*)R, S, (double*)H, n, k, ah, bh);
   else
-    hipLaunchKernelGGL(hrow_kernel<float>, grid, dim3(256), 0, s, (const float*)R, S, (float*)H, n, k);
+    hipLaunchKernelGGL(hrow_kernel<float>, grid, dim3(256), 0, s, (const float*)R, S, (float*)H, n, k, ah, bh);
   return hipGetLastError();
 }
 
-hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, int dt, hipStream_t s) {
+hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, double aw, double bw, int dt,
+                       hipStream_t s) {
   dim3 grid((unsigned)ceil_div(m, 128));
   if (dt == 0)
-    hipLaunchKernelGGL(wrow_kernel<double>, grid, dim3(128), 0, s, (const double*)Tm, V, (double*)W, m, k);
+    hipLaunchKernelGGL(wrow_kernel<double>, grid, dim3(128), 0, s, (const double*)Tm, V, (double*)W, m, k, aw, bw);
   else
-    hipLaunchKernelGGL(wrow_kernel<float>, grid, dim3(128), 0, s, (const float*)Tm, V, (float*)W, m, k);
+    hipLaunchKernelGGL(wrow_kernel<float>, grid, dim3(128), 0, s, (const float*)Tm, V, (float*)W, m, k, aw, bw);
   return hipGetLastError();
 }
 

@@ -102,8 +102,15 @@ hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart
 hipError_t launch_gram_sum(const double* gpart, int splits, int l, double* G, hipStream_t s);
 
 // hals.hip: deterministic HALS pieces (dt: 0 FP64, 1 FP32).
-hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, int dt, hipStream_t s);
-hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, int dt, hipStream_t s);
+// Regularization weights of the HALS rules (ridge alpha, LASSO beta; Sec. 3.4).
+struct Reg {
+  double aw, ah, bw, bh;
+};
+
+hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k, double ah, double bh, int dt,
+                       hipStream_t s);
+hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, double aw, double bw, int dt,
+                       hipStream_t s);
 hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void* Hp, int dt, hipStream_t s);
 int hgram_splits(int64_t n);
 hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s);
@@ -124,7 +131,7 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
 size_t sweep_ws_words(const SweepShape& sh, int l);
 hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void* B, void* W,
                         void* Wt, void* H, int64_t m, int64_t n, int l, int k, int nsweeps,
-                        double tol, int gram_mode, int order, u64* xbuf, double* stats,
+                        double tol, int gram_mode, int order, const Reg& reg, u64* xbuf, double* stats,
                         unsigned* status, u64* trace, hipStream_t s);
 
 }  // namespace rnmf

@@ -13,6 +13,11 @@
 //   lift W(:,j) = max(0, Q W~(:,j)) on the local rows, the local partial of
 //   Q^T W(:,j), and one device-wide all-reduce of that l-vector.
 // S = W^T W: slab partials (register-blocked), one all-reduce.
+// Regularized rules (Sec. 3.4): the ridge weight is added to the scales and
+// subtracts alpha * (old block) in the numerators; the LASSO weight is
+// subtracted from the H numerators and, for W, from the lifted column before
+// the clip (beta_w / (V_jj + alpha_w)).  With zero weights every added term
+// is an exact zero.
 //
 // Device-wide all-reduce: partials are written as 64-bit words (32-bit payload
 // | 32-bit epoch) with agent-scope relaxed atomic stores, so every word carries
@@ -125,6 +130,7 @@ struct SweepArgs {
   const T* Q; const T* B; T* W; T* Wt; T* H;
   int m, n, l, k;
   int nsweeps; double tol; int gram_mode, order;
+  double aw, ah, bw, bh;  // ridge (alpha) and LASSO (beta) weights
   int G, GR, GC, rows_per, cols_per, rows_lds, lq, cb;
   int red2_elems;
   int alias_sv;          // S shares V's LDS slot (no projected gradient needed)
@@ -623,7 +629,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     // reciprocal scales, one per lane (0 marks a skipped row)
     double rinv_l = 0.0;
     if (lane < k) {
-      const double d = (double)Ssc[lane * k + lane];
+      const double d = (double)Ssc[lane * k + lane] + a.ah;
       rinv_l = d > 0.0 ? 1.0 / d : 0.0;
     }
     // FP64 arithmetic: the update cancels R against H^T S, and S is the Gram
@@ -694,9 +700,11 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
         for (int q = 0; q < HI; ++q) g0[q] = fma(-s0, readlane<double>(h[q], ii), g0[q]);
       }
+      // regularized numerator: - bh - ah H(lane, c); lane i's g is read only at
+      // step i, while H(i, c) still holds its old value, so it is added here
       double gsum[HI];
 #pragma unroll
-      for (int q = 0; q < HI; ++q) gsum[q] = g0[q] + g1[q];
+      for (int q = 0; q < HI; ++q) gsum[q] = (g0[q] + g1[q]) - fma(a.ah, h[q], a.bh);
       // Gauss-Seidel over the rows: the scale comes from a register by lane
       // broadcast and the next S entry is loaded one step ahead, so no LDS
       // round trip sits on the chain
@@ -740,9 +748,10 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     T* cpart = red2 + 8 * 72;          // 5 x LPS: partial sums for the next update vector
     double* spart = (double*)(red2 + 8 * 72 + 5 * LPS);  // 2 x 384: local S partial sums
     int jprev = -1;  // column whose S partials await their reduction
+    const T aw = (T)a.aw, bw = (T)a.bw;
     auto next_col = [&](int j) __attribute__((always_inline)) -> int {
       int q = j + 1;
-      while (q < k && !(Vm[q * k + q] > (T)0)) ++q;
+      while (q < k && !(Vm[q * k + q] + aw > (T)0)) ++q;
       return q;
     };
     int jj = next_col(-1);
@@ -757,11 +766,13 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         s1 = fma(-wr[ii + 1], Vm[(ii + 1) * k + jj], s1);
       }
       for (; ii < k; ++ii) s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
-      vec[t] = Wts[t * k + jj] + (s0 + s1) / Vm[jj * k + jj];
+      const T wo = Wts[t * k + jj];
+      vec[t] = wo + ((s0 + s1) - aw * wo) / (Vm[jj * k + jj] + aw);
     }
     lds_sync();
     while (jj < k) {
-      // lift and clip: W(r, j) = max(0, Q(r, :) v)
+      // lift and clip: W(r, j) = max(0, Q(r, :) v - beta_w / (V_jj + alpha_w))
+      const T shift = bw / (Vm[jj * k + jj] + aw);
       T vs[CQ];
 #pragma unroll
       for (int s = 0; s < CQ; ++s) vs[s] = (gc * CQ + s < l) ? vec[gc * CQ + s] : (T)0;
@@ -775,7 +786,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           u1 = fma(qreg[i][s + 1], vs[s + 1], u1);
         }
         if (CQ & 1) u0 = fma(qreg[i][CQ - 1], vs[CQ - 1], u0);
-        w[i] = clip0<T>(sum8<T>(u0 + u1));
+        w[i] = clip0<T>(sum8<T>(u0 + u1) - shift);
       }
       if (gc == 0) {
 #pragma unroll
@@ -876,7 +887,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
           for (int pt = 1; pt < 5; ++pt) s += cpart[pt * LPS + t];
           s = fma(wt, Vm[jj * k + nj], s);
-          vec[t] = Wts[t * k + nj] + (Tm[t * k + nj] - s) / Vm[nj * k + nj];
+          const T wo = Wts[t * k + nj];
+          vec[t] = wo + ((Tm[t * k + nj] - s) - aw * wo) / (Vm[nj * k + nj] + aw);
         }
       }
       if (tr_sweep) { TRACE(6 + 2 * jj); }
@@ -899,9 +911,11 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   };
 
   auto w_phase = [&]() __attribute__((always_inline)) -> bool {
+    const T aw = (T)a.aw, bw = (T)a.bw;
     for (int jj = 0; jj < k; ++jj) {
-      const T d = Vm[jj * k + jj];
+      const T d = Vm[jj * k + jj] + aw;
       if (!(d > (T)0)) continue;
+      const T shift = bw / d;
       if (t < l) {
         const T* wr = Wts + t * k;
         T s0 = Tm[t * k + jj], s1 = (T)0, s2 = (T)0, s3 = (T)0;
@@ -913,7 +927,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           s3 = fma(-wr[ii + 3], Vm[(ii + 3) * k + jj], s3);
         }
         for (; ii < k; ++ii) s0 = fma(-wr[ii], Vm[ii * k + jj], s0);
-        vec[t] = Wts[t * k + jj] + ((s0 + s1) + (s2 + s3)) / d;
+        const T wo = Wts[t * k + jj];
+        vec[t] = wo + (((s0 + s1) + (s2 + s3)) - aw * wo) / d;
       }
       lds_sync();
       if (tr_sweep && jj == 1) { TRACE(10 + 2 * k); }
@@ -940,7 +955,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           }
           for (; aa < l; ++aa) u0 = fma(q[aa], vec[aa], u0);
         }
-        const T w = clip0<T>((u0 + u1) + (u2 + u3));
+        const T w = clip0<T>(((u0 + u1) + (u2 + u3)) - shift);
         wcol[rr] = w;
         a.W[(size_t)(r0 + rr) * k + jj] = w;
       }
@@ -981,7 +996,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     return true;
   };
 
-  // projected gradient norm^2 on X^ = Q B (factor 2 dropped)
+  // projected gradient norm^2 on X^ = Q B (factor 2 dropped), with alpha F + beta
+  // added for the regularized cost
   auto pgrad = [&](double& out) __attribute__((always_inline)) -> bool {
     __syncthreads();  // W and H written by other threads of this workgroup
     double s = 0.0;
@@ -998,6 +1014,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       } else {
         for (int aa = 0; aa < l; ++aa) gval = fma(-a.Q[(size_t)(r0 + rr) * l + aa], Tm[aa * k + cc], gval);
       }
+      gval = fma((T)a.aw, wr[cc], gval) + (T)a.bw;
       T p = wr[cc] > (T)0 ? gval : (gval < (T)0 ? gval : (T)0);
       s += (double)p * (double)p;
     }
@@ -1007,6 +1024,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       for (int ii = 0; ii < k; ++ii) gval = fma(Sm[jj * k + ii], Hp[(size_t)ii * ldH + cc], gval);
       for (int aa = 0; aa < l; ++aa) gval = fma(-Wts[aa * k + jj], Bp[(size_t)aa * ldB + cc], gval);
       T hv = Hp[(size_t)jj * ldH + cc];
+      gval = fma((T)a.ah, hv, gval) + (T)a.bh;
       T p = hv > (T)0 ? gval : (gval < (T)0 ? gval : (T)0);
       s += (double)p * (double)p;
     }
@@ -1164,7 +1182,7 @@ size_t sweep_ws_words(const SweepShape& sh, int l) {
 }
 
 hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void* B, void* W, void* Wt, void* H,
-                        int64_t m, int64_t n, int l, int k, int nsweeps, double tol, int gram_mode, int order,
+                        int64_t m, int64_t n, int l, int k, int nsweeps, double tol, int gram_mode, int order, const Reg& reg,
                         u64* xbuf, double* stats, unsigned* status, u64* trace, hipStream_t s) {
   size_t words = sweep_ws_words(sh, l);
   hipError_t e = launch_fill_u32((unsigned*)xbuf, words * 2, 0u, s);
@@ -1183,6 +1201,7 @@ hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void*
   a.Q = (const TT*)Q; a.B = (const TT*)B; a.W = (TT*)W; a.Wt = (TT*)Wt; a.H = (TT*)H;            \
   a.m = (int)m; a.n = (int)n; a.l = l; a.k = k;                                                  \
   a.nsweeps = nsweeps; a.tol = tol; a.gram_mode = gram_mode; a.order = order;                   \
+  a.aw = reg.aw; a.ah = reg.ah; a.bw = reg.bw; a.bh = reg.bh;                                    \
   a.G = sh.G; a.GR = sh.GR; a.GC = sh.GC; a.rows_per = sh.rows_per; a.cols_per = sh.cols_per;  \
   a.rows_lds = sh.rows_lds; a.lq = l | 1; a.cb = sh.cb; a.red2_elems = sh.red2_elems;               \
   a.alias_sv = sh.alias_sv; a.trace = trace;                                                     \

@@ -144,3 +144,30 @@ def test_deterministic_hals_validation():
     assert call(o, ldx=299) == rn.ERR_SHAPE
     assert call(o, xt=rn.F64) == rn.ERR_DTYPE
     assert L.rnmf_hals(None, rn.F32, 1000, 300, 300, p, p, 1, ctypes.byref(o), p, 1 << 30, None) == rn.ERR_ARG
+
+
+def test_opts_layout_matches_the_header():
+    # rnmf_opts: 4 x int32, double tol, uint64 seed, 6 x int32, 4 x double
+    assert ctypes.sizeof(rn.Opts) == 88
+    assert rn.Opts.alpha_w.offset == 56 and rn.Opts.beta_h.offset == 80
+    o = rn.Opts()
+    rn.lib().rnmf_default_opts(ctypes.byref(o))
+    assert (o.alpha_w, o.alpha_h, o.beta_w, o.beta_h) == (0.0, 0.0, 0.0, 0.0)
+
+
+@pytest.mark.parametrize("bad", [{"alpha_w": -1.0}, {"beta_h": float("nan")}, {"alpha_h": float("inf")},
+                                 {"beta_w": -1e-30}])
+def test_regularization_weights_are_validated(bad):
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    o = rn.make_opts(10, 20, 2, reg=bad)
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_FACTORIZE, 2000, 500, o)
+    assert L.rnmf_hals_step(p, p, 2000, 500, 30, 10, p, p, p, 1, ctypes.byref(o), None, p, 1 << 30,
+                            None) == rn.ERR_ARG
+    assert b"regularization" in L.rnmf_last_error()
+    assert L.rnmf_hals(p, rn.F32, 2000, 500, 500, p, p, 1, ctypes.byref(o), p, 1 << 30, None) == rn.ERR_ARG
+    with pytest.raises(ValueError):
+        rn.make_opts(10, reg={"gamma": 1.0})
+    good = rn.make_opts(10, 20, 2, reg={"alpha_w": 0.5, "beta_h": 2.0})
+    assert rn.workspace_bytes(rn.OP_FACTORIZE, 2000, 500, good) > 0

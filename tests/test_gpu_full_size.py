@@ -8,7 +8,8 @@ initial factors) promoted to float64 and recomputes the step from them.
     - compression B = Q^T X against the product in FP64 on the same Q;
     - Q orthonormal, and its range captures X as well as the oracle's basis;
     - one compressed-HALS sweep from identical inputs: W, W~, H each within
-      1e-5 relative (Frobenius) of the oracle's sweep.
+      1e-5 relative (Frobenius) of the oracle's sweep, plain and with the
+      elastic-net rules of Sec. 3.4.
   stack 32,256 x 2,410, k = 16 (the image-stack shape), 500 sweeps:
     - FP32 form: final relative error within 1e-4 of the oracle's;
     - BF16 form: final relative error at most 1.01 x the oracle's.
@@ -107,6 +108,29 @@ def test_tall_full_size_one_sweep_matches_oracle(tall):
     assert relf(host(Wt), Wto) <= 1e-5
     assert relf(host(H), Ho) <= 1e-5
     assert host(W).min() >= 0.0 and host(H).min() >= 0.0
+
+
+def test_tall_full_size_regularized_sweep_matches_oracle(tall):
+    # the elastic-net rules (Sec. 3.4) in the same launch configuration
+    X, Om, W0, H0, w = tall
+    k, p, q = w["k"], w["p"], w["q"]
+    Xd = dev(X)
+    Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
+    B = rn.compress(Xd, Q)
+    del Xd
+    W = dev(W0)
+    H = dev(H0)
+    Wt = rn.compress(W, Q)
+    Qh, Bh, Wh, Wth, Hh = host(Q), host(B), host(W), host(Wt), host(H)
+    reg = dict(alpha_w=0.15 * float(np.mean(np.sum(Hh * Hh, axis=1))),
+               alpha_h=0.15 * float(np.mean(np.sum(Wh * Wh, axis=0))),
+               beta_w=0.02 * float(np.mean(np.abs(Qh @ (Bh @ Hh.T)))),
+               beta_h=0.02 * float(np.mean(np.abs(Bh.T @ Wth))))
+    rn.hals_step(Q, B, W, Wt, H, nsweeps=1, reg=reg)
+    Wo, Wto, Ho = o.rhals_sweep(Qh, Bh, Wh, Wth, Hh, reg=o.Reg(**reg))
+    assert relf(host(W), Wo) <= 1e-5
+    assert relf(host(Wt), Wto) <= 1e-5
+    assert relf(host(H), Ho) <= 1e-5
 
 
 @pytest.fixture(scope="module")
