@@ -36,6 +36,8 @@ from .rhals import (  # noqa: F401
     qb,
     qb_streaming,
     rhals_sweep,
+    nndsvd,
+    svd_init,
     hals_sweep,
     rhals,
     hals,

@@ -54,6 +54,14 @@ R19 In randomized HALS the ridge part acts on W~ (it is linear) while the
     the clip: substituting X ~ Q B and W ~ Q W~ into the printed W rule leaves
     the all-ones m-vector outside the range of Q.  With Q square and
     orthogonal the sweep is the deterministic regularized sweep.
+R20 SVD-based initialization (the Remark on initialization after Algorithm 1
+    points to the nonnegative double SVD of Boutsidis and Gallopoulos, 2008)
+    is taken on the randomized SVD of the QB decomposition: B = U_B S V^T,
+    U = Q U_B.  Component 1 takes |u_1|, |v_1|; every other component keeps
+    the positive or the negative parts of (u_j, v_j), whichever has the
+    larger product of norms (ties go to the negative parts), scaled by
+    sqrt(s_j * that product).  A component whose two products are both zero
+    is set to zero.  Zero entries stay zero (no fill).
 """
 
 from typing import NamedTuple
@@ -159,6 +167,54 @@ def qb_streaming(X, Omega, q, block=1):
     for j0 in range(0, n, block):
         B[:, j0:j0 + block] = Q.T @ X[:, j0:j0 + block]
     return Q, B
+
+
+# ----------------------------------------------------------------------------
+# SVD-based initialization (Remark on initialization; reading R20)
+# ----------------------------------------------------------------------------
+
+def nndsvd(U, sv, Vt):
+    """Nonnegative double SVD (Boutsidis and Gallopoulos, 2008) of the
+    singular triplets U (m x k), sv (k, descending), Vt (k x n): returns
+    W (m x k) and H (k x n), both nonnegative (reading R20)."""
+    U = np.asarray(U, dtype=np.float64)
+    Vt = np.asarray(Vt, dtype=np.float64)
+    sv = np.asarray(sv, dtype=np.float64)
+    m, k = U.shape
+    W = np.zeros((m, k))
+    H = np.zeros((k, Vt.shape[1]))
+    for j in range(k):
+        x, y = U[:, j], Vt[j, :]
+        if j == 0:
+            W[:, 0] = np.sqrt(sv[0]) * np.abs(x)
+            H[0, :] = np.sqrt(sv[0]) * np.abs(y)
+            continue
+        xp, xn = np.maximum(x, 0.0), np.maximum(-x, 0.0)
+        yp, yn = np.maximum(y, 0.0), np.maximum(-y, 0.0)
+        mp = np.linalg.norm(xp) * np.linalg.norm(yp)
+        mn = np.linalg.norm(xn) * np.linalg.norm(yn)
+        if mp > mn:
+            u, v, sig = xp, yp, mp
+        else:
+            u, v, sig = xn, yn, mn
+        if sig > 0.0:
+            c = np.sqrt(sv[j] * sig)
+            W[:, j] = c * u / np.linalg.norm(u)
+            H[j, :] = c * v / np.linalg.norm(v)
+    return W, H
+
+
+def svd_init(Q, B, k):
+    """W0, H0 from the randomized SVD of the QB decomposition (Sec. 2.3:
+    X ~ Q B, B = U_B S V^T, so X ~ (Q U_B) S V^T) followed by the
+    nonnegative double SVD of its k leading triplets (reading R20).  The SVD
+    of the small l x n matrix B is LAPACK's."""
+    Q = np.asarray(Q, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if not (1 <= k <= B.shape[0]):
+        raise ValueError("need 1 <= k <= l")
+    Ub, sv, Vt = np.linalg.svd(B, full_matrices=False)
+    return nndsvd(Q @ Ub[:, :k], sv[:k], Vt[:k])
 
 
 # ----------------------------------------------------------------------------
