@@ -90,6 +90,8 @@ enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
 #define RNMF_FLAG_NO_SHIFT 0x2u         /* no shifted Cholesky QR fallback     */
 #define RNMF_FLAG_EXACT_Q 0x4u          /* BF16: do not add one power iteration */
 #define RNMF_FLAG_TRACE 0x8u            /* rnmf_hals_step: record phase timestamps */
+#define RNMF_FLAG_SVD_INIT 0x20u        /* rnmf_factorize: W0, H0 by the SVD-based
+                                           initialization (rnmf_svd_init)      */
 #define RNMF_FLAG_SHIFTED_QR3 0x10u     /* every QR: shifted Cholesky QR pass first, then
                                            two plain passes (shifted CholeskyQR3)   */
 
@@ -138,7 +140,8 @@ typedef struct rnmf_report {
 
 /* Operation selector for rnmf_workspace_bytes. */
 enum { RNMF_OP_SKETCH = 0, RNMF_OP_COMPRESS = 1, RNMF_OP_HALS_STEP = 2,
-       RNMF_OP_FACTORIZE = 3, RNMF_OP_REL_ERROR = 4, RNMF_OP_HALS = 5 };
+       RNMF_OP_FACTORIZE = 3, RNMF_OP_REL_ERROR = 4, RNMF_OP_HALS = 5,
+       RNMF_OP_SVD_INIT = 6 };
 
 /* Fills opts with the paper's defaults: p = 20, q = 2 (Sec. 4, experimental
  * setup), max_iter = 200, tol = 0, prec F32, Gaussian Omega, FULL Gram,
@@ -212,13 +215,32 @@ rnmf_status rnmf_rel_error(const void* X, int xt, int64_t m, int64_t n, int64_t 
 /* Algorithm 1 end to end: sketch, compression, W~ = Q^T W0, sweeps until the
  * stop test or max_iter, then the relative error.  Omega (n x l), W0 (m x k),
  * H0 (k x n) are optional device inputs in the factor dtype; NULL draws them
- * from opts->seed (W0, H0 uniform on [0, 1)).  W (out, m x k), H (out, k x n).
+ * from opts->seed (W0, H0 uniform on [0, 1)); with RNMF_FLAG_SVD_INIT, W0 and
+ * H0 must be NULL and come from rnmf_svd_init on this call's Q and B (needs
+ * l <= 96).  W (out, m x k), H (out, k x n).
  * report (host, may be NULL) is filled after the stream is synchronised.
  * Returns the run's status (RNMF_NOT_CONVERGED only when tol > 0). */
 rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t ldx,
                            const rnmf_opts* opts, const void* Omega, const void* W0,
                            const void* H0, void* W, void* H, rnmf_report* report,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* SVD-based initialization (the Remark on initialization after Algorithm 1):
+ * the nonnegative double SVD of Boutsidis and Gallopoulos (2008) of the k
+ * leading singular triplets of the randomized SVD from the QB decomposition
+ * (Sec. 2.3): B = U_B S V^T, U = Q U_B.  Component 1 is sqrt(s_1) |u_1|,
+ * sqrt(s_1) |v_1|; component j > 1 keeps the positive parts of (u_j, v_j) if
+ * ||u+|| ||v+|| > ||u-|| ||v-||, else the negative parts, scaled so that the
+ * product of its two factors is s_j times the larger product; a component
+ * whose two products vanish is zero.  The SVD of B comes from FP64 Jacobi on
+ * B B^T.
+ * Q: m x l orthonormal, B: l x n, both packed, in the factor dtype of
+ * opts->prec (RNMF_F64 for RNMF_PREC_F64, else RNMF_F32); 1 <= k <= min(l, 64),
+ * l <= 96, k = opts->k.  W (out, m x k) and H (out, k x n), packed.
+ * Workspace: RNMF_OP_SVD_INIT.  Asynchronous; no device status is set. */
+rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k,
+                          void* W, void* H, const rnmf_opts* opts, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* nsweeps sweeps of deterministic HALS (Sec. 3.1, residual-free block rules)
  * on X itself, in place; randomized HALS is this algorithm run on the

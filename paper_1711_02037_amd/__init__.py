@@ -33,12 +33,13 @@ GRAM = {"full": 0, "lowdim": 1, "mixed": 2}
 ORDER = {"h_first": 0, "w_first": 1}
 OMEGA = {"gaussian": 0, "uniform": 1}
 FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE, FLAG_SHIFTED_QR3 = 0x1, 0x2, 0x4, 0x8, 0x10
-OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR, OP_HALS = range(6)
+FLAG_SVD_INIT = 0x20
+OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR, OP_HALS, OP_SVD_INIT = range(7)
 
 EXPORTS = [
     "rnmf_default_opts", "rnmf_workspace_bytes", "rnmf_status_string", "rnmf_last_error",
     "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
-    "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals",
+    "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
         L.rnmf_factorize.restype = ctypes.c_int
         L.rnmf_hals.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, vp, i32, ctypes.POINTER(Opts), vp, sz, vp]
         L.rnmf_hals.restype = ctypes.c_int
+        L.rnmf_svd_init.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_svd_init.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
         L.rnmf_cast_bf16.restype = ctypes.c_int
         L.rnmf_read_status.argtypes = [vp, sz, vp]
@@ -312,6 +315,27 @@ def hals(X, W, H, nsweeps=1, order="h_first", ws=None, reg=None):
     _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(X.device)))
 
 
+def svd_init(Q, B, k, ws=None):
+    """W0 (m x k) and H0 (k x n) by the SVD-based initialization
+    (rnmf_svd_init: nonnegative double SVD of the randomized SVD Q B)."""
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    n = B.shape[1]
+    if B.shape[0] != l or B.dtype != Q.dtype:
+        raise ValueError("need B (l x n) in the dtype of Q")
+    prec = "fp64" if Q.dtype == torch.float64 else "fp32"
+    o = make_opts(k, l - k, 0, precision=prec)
+    nb = workspace_bytes(OP_SVD_INIT, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, Q.device)
+    W = torch.empty((m, k), dtype=Q.dtype, device=Q.device)
+    H = torch.empty((k, n), dtype=Q.dtype, device=Q.device)
+    _check(lib().rnmf_svd_init(_ptr(Q), _ptr(B), m, n, l, int(k), _ptr(W), _ptr(H), ctypes.byref(o), _ptr(w),
+                               w.numel(), _stream(Q.device)))
+    return W, H
+
+
 def rel_error(X, W, H, ws=None):
     """||X - W H||_F / ||X||_F with FP64 accumulation (rnmf_rel_error)."""
     torch = _torch()
@@ -331,14 +355,20 @@ def rel_error(X, W, H, ws=None):
 
 def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, omega=None, W0=None,
               H0=None, gram="full", order="h_first", omega_dist="gaussian", check_input=True, shift=True,
-              exact_q=False, ws=None, reg=None):
+              exact_q=False, ws=None, reg=None, init="random"):
     """Algorithm 1 end to end (rnmf_factorize).  Returns (W, H, report dict).
-    reg: optional ridge / LASSO weights (Sec. 3.4; see make_opts)."""
+    reg: optional ridge / LASSO weights (Sec. 3.4; see make_opts).
+    init: "random" (W0, H0 given or uniform from seed) or "svd" (the
+    SVD-based initialization on this run's Q and B)."""
     torch = _torch()
     _need_dev(X, "X"); _rowmajor(X, "X")
     m, n = X.shape
     o = make_opts(k, p, q, max_iter, tol, seed, precision, omega_dist, gram, order, check_input, shift,
                   exact_q, reg)
+    if init == "svd":
+        o.flags |= FLAG_SVD_INIT
+    elif init != "random":
+        raise ValueError("init must be 'random' or 'svd'")
     dt = _fdtype(precision)
     for t, nm in ((omega, "omega"), (W0, "W0"), (H0, "H0")):
         if t is not None:

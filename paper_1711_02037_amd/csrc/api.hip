@@ -127,13 +127,15 @@ rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax)
   if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode %d", o->gram_mode);
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order %d", o->order);
   if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q | RNMF_FLAG_TRACE |
-                   RNMF_FLAG_SHIFTED_QR3))
+                   RNMF_FLAG_SHIFTED_QR3 | RNMF_FLAG_SVD_INIT))
     return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
   if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
   if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
   int l = lwidth(o, m, n);
   if (l > LMAX) return fail(RNMF_ERR_ARG, "sketch width l = min(k + p, m, n) = %d exceeds %d", l, LMAX);
   if (need_kmax && o->k > KMAX) return fail(RNMF_ERR_ARG, "k = %d exceeds the supported %d", o->k, KMAX);
+  if ((o->flags & RNMF_FLAG_SVD_INIT) && l > LSVD)
+    return fail(RNMF_ERR_ARG, "the SVD-based initialization needs l <= %d (l = %d)", LSVD, l);
   return RNMF_OK;
 }
 
@@ -235,6 +237,18 @@ InitBufs plan_init(Arena& a, int64_t m, int k, int l, const Mode& md, const Dev&
   b.at = a.take<char>((size_t)lp * b.ldp * md.es);
   b.tn = plan_tn(m, k, l, md.dt, d.cus);
   b.part = a.take<char>(b.tn.part_elems * md.es);
+  return b;
+}
+
+SvdBufs plan_svd(Arena& a, int64_t m, int64_t n, int l, int k) {
+  SvdBufs b;
+  b.gpart = a.take<double>((size_t)hgram_splits(n) * LMAX * LMAX);
+  b.C = a.take<double>((size_t)l * l);
+  b.Ub = a.take<double>((size_t)l * k);
+  b.sv = a.take<double>((size_t)k);
+  b.upart = a.take<double>((size_t)svd_row_blocks(m) * k * 2);
+  b.vpart = a.take<double>((size_t)svd_col_blocks(n) * k * 2);
+  b.coef = a.take<double>((size_t)k * 3);
   return b;
 }
 
@@ -388,7 +402,7 @@ rnmf_status status_from_bits(unsigned bits) {
 
 size_t factorize_bytes(int64_t m, int64_t n, const rnmf_opts* o, int xt, const Dev& d, void* base,
                        void** pQ, void** pB, void** pWt, void** pXb, SketchBufs* sb, CompressBufs* cb, InitBufs* ib,
-                       SweepBufs* wb, RelBufs* rb) {
+                       SweepBufs* wb, RelBufs* rb, SvdBufs* vb = nullptr) {
   const Mode md = mode_of(o);
   const int l = lwidth(o, m, n);
   Arena a(base);
@@ -406,6 +420,12 @@ size_t factorize_bytes(int64_t m, int64_t n, const rnmf_opts* o, int xt, const D
   { Arena s(sub); InitBufs t = plan_init(s, m, o->k, l, md, d); if (ib) *ib = t; mx = s.used > mx ? s.used : mx; }
   { Arena s(sub); SweepBufs t = plan_hals(s, m, n, l, o->k, md, d, o->tol > 0.0); if (wb) *wb = t; mx = s.used > mx ? s.used : mx; }
   { Arena s(sub); RelBufs t = plan_rel(s, m, n); if (rb) *rb = t; mx = s.used > mx ? s.used : mx; }
+  if (o->flags & RNMF_FLAG_SVD_INIT) {
+    Arena s(sub);
+    SvdBufs t = plan_svd(s, m, n, l, o->k);
+    if (vb) *vb = t;
+    mx = s.used > mx ? s.used : mx;
+  }
   if (pQ) *pQ = Q;
   if (pB) *pB = B;
   if (pWt) *pWt = Wt;
@@ -442,6 +462,9 @@ size_t op_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o, int xt, const 
     case RNMF_OP_FACTORIZE:
       return factorize_bytes(m, n, o, xt, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                              nullptr, nullptr, nullptr);
+    case RNMF_OP_SVD_INIT:
+      plan_svd(a, m, n, l, o->k);
+      return a.used;
     default:
       return 0;
   }
@@ -531,10 +554,17 @@ size_t rnmf_workspace_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o) {
       fail(RNMF_ERR_ARG, "deterministic HALS runs in RNMF_PREC_F32 or RNMF_PREC_F64");
       return 0;
     }
+  } else if (op == RNMF_OP_SVD_INIT) {
+    if (!o) { fail(RNMF_ERR_ARG, "opts is NULL"); return 0; }
+    const int l = lwidth(o, m, n);
+    if (m < 1 || n < 1 || o->k < 1 || o->k > KMAX || o->k > l || l > LSVD) {
+      fail(RNMF_ERR_ARG, "the SVD-based initialization needs 1 <= k <= min(l, %d) and l <= %d", KMAX, LSVD);
+      return 0;
+    }
   } else {
     if (check_opts(o, m, n, op == RNMF_OP_FACTORIZE) != RNMF_OK) return 0;
   }
-  if (op < RNMF_OP_SKETCH || op > RNMF_OP_HALS) { fail(RNMF_ERR_ARG, "unknown op %d", op); return 0; }
+  if (op < RNMF_OP_SKETCH || op > RNMF_OP_SVD_INIT) { fail(RNMF_ERR_ARG, "unknown op %d", op); return 0; }
   Dev d = default_dev();
   Dev q;
   if (get_dev(q, nullptr)) d = q;
@@ -639,6 +669,27 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   return RNMF_OK;
 }
 
+rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
+                          void* H, const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!Q || !B || !W || !H) return fail(RNMF_ERR_ARG, "Q, B, W and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (l < 1 || l > LSVD || l > m) return fail(RNMF_ERR_SHAPE, "need 1 <= l <= min(m, %d)", LSVD);
+  if (k < 1 || k > l || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= min(l, %d)", KMAX);
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  SvdBufs b = plan_svd(a, m, n, l, k);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  HIPCHK(launch_svd_init(Q, B, m, n, l, k, W, H, md.dt, b, d.stream));
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, void* W, void* H, int32_t nsweeps,
                       const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -727,6 +778,8 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   if ((r = check_xt(o, xt)) != RNMF_OK) return r;
   if (!X || !W || !H) return fail(RNMF_ERR_ARG, "X, W and H must be non-NULL");
   if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
+  const bool svd = (o->flags & RNMF_FLAG_SVD_INIT) != 0;
+  if (svd && (W0 || H0)) return fail(RNMF_ERR_ARG, "RNMF_FLAG_SVD_INIT needs W0 and H0 to be NULL");
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
   const Mode md = mode_of(o);
@@ -738,10 +791,11 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   InitBufs ib;
   SweepBufs wb;
   RelBufs rb;
+  SvdBufs vb;
   size_t need = factorize_bytes(m, n, o, xt, d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, nullptr, nullptr);
   if ((r = check_ws(ws, ws_bytes, need)) != RNMF_OK) return r;
-  factorize_bytes(m, n, o, xt, d, ws, &Q, &B, &Wt, &Xb, &sb, &cb, &ib, &wb, &rb);
+  factorize_bytes(m, n, o, xt, d, ws, &Q, &B, &Wt, &Xb, &sb, &cb, &ib, &wb, &rb, &vb);
   Hdr h = header(ws);
   hipStream_t s = d.stream;
   HIPCHK(launch_fill_u32((unsigned*)ws, HDR_BYTES / 4, 0u, s));
@@ -759,10 +813,14 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   if ((r = prepare_x(X, xt, m, n, ldx, o, md, Xb, h, d, &Xc, &ldc, &check)) != RNMF_OK) return r;
   if ((r = run_sketch(Xc, m, n, ldc, Omega, o, Q, sb, md, h, check, d)) != RNMF_OK) return r;
   if ((r = run_compress(Xc, m, n, ldc, Q, l, B, cb, md, d)) != RNMF_OK) return r;
-  if (W0) HIPCHK(hipMemcpyAsync(W, W0, (size_t)m * k * md.es, hipMemcpyDeviceToDevice, s));
-  else HIPCHK(launch_philox(W, md.dt, m, k, o->seed, 4u, 1, s));
-  if (H0) HIPCHK(hipMemcpyAsync(H, H0, (size_t)k * n * md.es, hipMemcpyDeviceToDevice, s));
-  else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, 1, s));
+  if (svd) {
+    HIPCHK(launch_svd_init(Q, B, m, n, l, k, W, H, md.dt, vb, s));
+  } else {
+    if (W0) HIPCHK(hipMemcpyAsync(W, W0, (size_t)m * k * md.es, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(launch_philox(W, md.dt, m, k, o->seed, 4u, 1, s));
+    if (H0) HIPCHK(hipMemcpyAsync(H, H0, (size_t)k * n * md.es, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, 1, s));
+  }
   if ((r = run_init_wt(Q, W, m, k, l, Wt, ib, md, d)) != RNMF_OK) return r;
   HIPCHK(hipEventRecord(ev[1], s));
   HIPCHK(launch_sweep(wb.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, o->max_iter, o->tol, o->gram_mode, o->order, reg_of(o),

@@ -103,12 +103,13 @@ __global__ __launch_bounds__(256) void pad_kernel(const T* __restrict__ H, int k
   }
 }
 
-// Partial V = H H^T over a chunk of 64 columns of H (FP64), written in the
-// partial layout of the Cholesky QR Gram (entry (a, b), a <= b, at a*LMAX+b).
-template <typename T>
+// Partial Gram H H^T of a k x n row-major matrix (k <= RMAX) over a chunk of
+// 64 columns (FP64), written in the partial layout of the Cholesky QR Gram
+// (entry (a, b), a <= b, at a*LMAX+b).  Used for V = H H^T and for B B^T.
+template <typename T, int RMAX>
 __global__ __launch_bounds__(256) void hgram_kernel(const T* __restrict__ H, int k, int64_t n,
                                                     double* __restrict__ part) {
-  __shared__ double Hs[KMAX][65];
+  __shared__ double Hs[RMAX][65];
   const int64_t c0 = (int64_t)blockIdx.x * 64;
   for (int e = threadIdx.x; e < k * 64; e += 256) {
     const int i = e / 64, cc = e - (e / 64) * 64;
@@ -168,11 +169,21 @@ hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void
 int hgram_splits(int64_t n) { return (int)ceil_div(n, 64); }
 
 hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s) {
+  if (k < 1 || k > GRAM_ROWS_MAX) return hipErrorInvalidValue;
   dim3 grid((unsigned)hgram_splits(n));
-  if (dt == 0)
-    hipLaunchKernelGGL(hgram_kernel<double>, grid, dim3(256), 0, s, (const double*)H, k, n, part);
-  else
-    hipLaunchKernelGGL(hgram_kernel<float>, grid, dim3(256), 0, s, (const float*)H, k, n, part);
+  if (k <= KMAX) {
+    if (dt == 0)
+      hipLaunchKernelGGL((hgram_kernel<double, KMAX>), grid, dim3(256), 0, s, (const double*)H, k, n, part);
+    else
+      hipLaunchKernelGGL((hgram_kernel<float, KMAX>), grid, dim3(256), 0, s, (const float*)H, k, n, part);
+  } else {
+    if (dt == 0)
+      hipLaunchKernelGGL((hgram_kernel<double, GRAM_ROWS_MAX>), grid, dim3(256), 0, s, (const double*)H, k, n,
+                         part);
+    else
+      hipLaunchKernelGGL((hgram_kernel<float, GRAM_ROWS_MAX>), grid, dim3(256), 0, s, (const float*)H, k, n,
+                         part);
+  }
   return hipGetLastError();
 }
 

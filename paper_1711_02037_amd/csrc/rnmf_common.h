@@ -25,6 +25,8 @@ enum : unsigned {
 
 constexpr int LMAX = 128;  // largest sketch width the kernels support
 constexpr int KMAX = 64;   // largest rank the sweep kernel supports
+constexpr int GRAM_ROWS_MAX = 96;  // most rows of a short-wide FP64 Gram (hgram_kernel)
+constexpr int LSVD = 96;           // largest sketch width of the SVD-based initialization
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -114,6 +116,18 @@ hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int 
 hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void* Hp, int dt, hipStream_t s);
 int hgram_splits(int64_t n);
 hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s);
+
+// SVD-based initialization (svdinit.hip).  Workspace pieces, all FP64:
+// gpart (hgram_splits(n) x LMAX x LMAX), C (l x l), Ub (l x k), sv (k),
+// upart (svd_row_blocks(m) x k x 2), vpart (svd_col_blocks(n) x k x 2),
+// coef (k x 3).
+struct SvdBufs {
+  double *gpart, *C, *Ub, *sv, *upart, *vpart, *coef;
+};
+int svd_row_blocks(int64_t m);
+int svd_col_blocks(int64_t n);
+hipError_t launch_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int l, int k, void* W, void* H,
+                           int dt, const SvdBufs& b, hipStream_t s);
 
 // One workgroup: Cholesky of G (l x l, FP64) with optional shift; writes the
 // transposed inverse factor packed for the GEMM (lp x lp, dtype cdt) and

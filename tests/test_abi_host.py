@@ -171,3 +171,31 @@ def test_regularization_weights_are_validated(bad):
         rn.make_opts(10, reg={"gamma": 1.0})
     good = rn.make_opts(10, 20, 2, reg={"alpha_w": 0.5, "beta_h": 2.0})
     assert rn.workspace_bytes(rn.OP_FACTORIZE, 2000, 500, good) > 0
+
+
+def test_svd_init_validation():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    o = rn.make_opts(10, 20, 2)
+    assert rn.workspace_bytes(rn.OP_SVD_INIT, 5000, 700, o) > 0
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_SVD_INIT, 5000, 700, rn.make_opts(40, 60, 2))   # l = 100 > 96
+    call = lambda m=5000, n=700, l=30, k=10, W=p: L.rnmf_svd_init(p, p, m, n, l, k, W, p, ctypes.byref(o), p,
+                                                                   1 << 30, None)
+    assert call(l=97) == rn.ERR_SHAPE
+    assert call(l=30, m=20) == rn.ERR_SHAPE
+    assert call(k=31) == rn.ERR_ARG
+    assert call(k=0) == rn.ERR_ARG
+    assert call(W=None) == rn.ERR_ARG
+    # factorize: the flag needs l <= 96 and no W0 / H0
+    big = rn.make_opts(40, 60, 2)
+    big.flags |= rn.FLAG_SVD_INIT
+    with pytest.raises(rn.RnmfError):
+        rn.workspace_bytes(rn.OP_FACTORIZE, 5000, 700, big)
+    f = rn.make_opts(10, 20, 2)
+    f.flags |= rn.FLAG_SVD_INIT
+    assert rn.workspace_bytes(rn.OP_FACTORIZE, 5000, 700, f) >= rn.workspace_bytes(rn.OP_FACTORIZE, 5000, 700, o)
+    rep = rn.Report()
+    assert L.rnmf_factorize(p, rn.F32, 5000, 700, 700, ctypes.byref(f), None, p, None, p, p, ctypes.byref(rep),
+                            p, 1 << 40, None) == rn.ERR_ARG
+    assert b"W0" in L.rnmf_last_error()

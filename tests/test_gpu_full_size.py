@@ -9,7 +9,9 @@ initial factors) promoted to float64 and recomputes the step from them.
     - Q orthonormal, and its range captures X as well as the oracle's basis;
     - one compressed-HALS sweep from identical inputs: W, W~, H each within
       1e-5 relative (Frobenius) of the oracle's sweep, plain and with the
-      elastic-net rules of Sec. 3.4.
+      elastic-net rules of Sec. 3.4;
+    - the SVD-based initialization on the device's Q and B, W and H within
+      1e-5 relative of the oracle's.
   stack 32,256 x 2,410, k = 16 (the image-stack shape), 500 sweeps:
     - FP32 form: final relative error within 1e-4 of the oracle's;
     - BF16 form: final relative error at most 1.01 x the oracle's.
@@ -131,6 +133,20 @@ def test_tall_full_size_regularized_sweep_matches_oracle(tall):
     assert relf(host(W), Wo) <= 1e-5
     assert relf(host(Wt), Wto) <= 1e-5
     assert relf(host(H), Ho) <= 1e-5
+
+
+def test_tall_full_size_svd_init_matches_oracle(tall):
+    # the SVD-based initialization on the device's own Q and B
+    X, Om, W0, H0, w = tall
+    k, p, q = w["k"], w["p"], w["q"]
+    Xd = dev(X)
+    Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
+    B = rn.compress(Xd, Q)
+    del Xd
+    W, H = rn.svd_init(Q, B, k)
+    Wo, Ho = o.svd_init(host(Q), host(B), k)
+    assert relf(host(W), Wo) <= 1e-5 and relf(host(H), Ho) <= 1e-5
+    assert host(W).min() >= 0.0 and host(H).min() >= 0.0
 
 
 @pytest.fixture(scope="module")
