@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target protocol")
     ap.add_argument("--no-hals", action="store_true", help="skip the deterministic HALS comparison")
+    ap.add_argument("--no-svd-init", action="store_true", help="skip the SVD-based initialization comparison")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -193,6 +194,13 @@ def main():
         if args.speedup_ks:
             hals["by_k"] = speedup_series(rn, torch, X, [int(v) for v in args.speedup_ks.split(",") if v], p, q)
 
+    # ---- SVD-based initialization against the seeded uniform one -------------
+    svd = None
+    if not args.no_svd_init:
+        svd = svd_init_compare(rn, torch, X, Om, Q32, k, p, q, sweeps, reps_f, dev)
+        log(f"SVD init: {svd['ms']:.3f} ms; error after {sweeps} sweeps {svd['rel_err']:.6f} "
+            f"(uniform init {svd['rel_err_uniform_init']:.6f})")
+
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -220,6 +228,7 @@ def main():
         "sweeps_per_s_kernel": round(sweeps / (ms_sw * 1e-3), 1),
         "time_to_target": ttt,
         "hals_vs_rhals": hals,
+        "svd_init": svd,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -294,6 +303,29 @@ def hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev):
             "speedup_per_sweep": round(ms / sweeps / r_ms_sweep, 3),
             "speedup_200_sweeps": round(ms / r_ms_run, 3),
             "note": "HALS streams X twice per sweep; rHALS streams it (2q+2) times once, then sweeps on B"}
+
+
+def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=5):
+    """rnmf_svd_init on the FP32 Q and B of this workload (events on the current
+    stream, mean of `reps` calls after one warm-up), and the FP32 form's error
+    after `sweeps` sweeps when it starts from that initialization instead of
+    the seeded uniform W0, H0."""
+    m, n = X.shape
+    B = rn.compress(X, Q)
+    sws = rn._workspace(rn.workspace_bytes(rn.OP_SVD_INIT, m, n, rn.make_opts(k, p, 0)), ws_dev)
+    rn.svd_init(Q, B, k, ws=sws)
+    st = torch.cuda.current_stream(ws_dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        rn.svd_init(Q, B, k, ws=sws)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    _, _, info = rn.factorize(X, k, p, q, max_iter=sweeps, precision="fp32", omega=Om, init="svd")
+    return {"ms": round(ms, 4), "rel_err": info["rel_err"], "rel_err_uniform_init": reps_f[-1]["rel_err"],
+            "sweeps": sweeps, "precision": "fp32",
+            "note": "nonnegative double SVD of the randomized SVD Q B (FP64 Jacobi on B B^T)"}
 
 
 def speedup_series(rn, torch, X, ks, p, q, nsw=20):
