@@ -242,6 +242,65 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
                           void* W, void* H, const rnmf_opts* opts, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* ---- Batched randomized HALS ------------------------------------------------
+ * Many independent problems of uneven shapes (Algorithm 1 for each, with the
+ * plain FP32 rules, Gram mode RNMF_GRAM_FULL and order RNMF_ORDER_H_FIRST) in
+ * one persistent launch.  Each workgroup takes whole problems from a work
+ * queue, largest first, and runs sketch, q subspace iterations with
+ * CholeskyQR2, compression, W~ = Q^T W0, nsweeps sweeps and the relative
+ * error on its own, so no workgroup ever waits for another.  FP32 storage
+ * and arithmetic, FP64 Grams, Cholesky factors and error sums.
+ * One problem: all pointers are caller-owned device memory, FP32, row-major
+ * and packed except X.  Requirements: 1 <= k <= min(32, l), 1 <= l <= 64,
+ * l <= min(m, n); ldx >= n. */
+typedef struct rnmf_problem {
+  const float* X;      /* m x n, leading dimension ldx                        */
+  const float* Omega;  /* n x l test matrix                                   */
+  const float* W0;     /* m x k initial W                                     */
+  const float* H0;     /* k x n initial H                                     */
+  float* W;            /* out: m x k                                          */
+  float* H;            /* out: k x n                                          */
+  float* Q;            /* out: m x l orthonormal basis                        */
+  float* B;            /* out: l x n compressed matrix Q^T X                  */
+  float* Z;            /* scratch: n x l (holds B^T during the sweeps)        */
+  int64_t m, n, ldx;
+  int32_t k, l;
+} rnmf_problem;
+
+/* Workspace bytes for a batch of nprob problems (descriptors, queue counter,
+ * per-problem error sums and status). */
+size_t rnmf_batch_workspace_bytes(int32_t nprob);
+
+/* Checks every problem (host array), orders them by estimated cost (largest
+ * first), picks each problem's X-pass tiling from the autotune table and
+ * copies the descriptors into ws (asynchronous copy on stream; the host array
+ * may be reused when the call returns).  Errors: RNMF_ERR_ARG / ERR_SHAPE
+ * name the first bad problem in rnmf_last_error(). */
+rnmf_status rnmf_batch_plan(const rnmf_problem* probs, int32_t nprob, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Runs a planned batch: q subspace iterations and nsweeps sweeps per problem.
+ * Launches one small fill kernel and the persistent kernel and nothing else
+ * (no allocation, no memset, no host synchronisation), so it may be captured
+ * in a HIP graph and replayed.  Asynchronous. */
+rnmf_status rnmf_batch_run(int32_t nprob, int32_t q, int32_t nsweeps, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Synchronises stream and copies the results of the last run to host arrays
+ * in the caller's problem order: rel_err[i] = ||X - W H||_F / ||X||_F (FP64
+ * sums) and status[i] (an rnmf_status; RNMF_OK, RNMF_ERR_NOT_SPD when a
+ * Cholesky QR pass failed even with a shift).  Either pointer may be NULL. */
+rnmf_status rnmf_batch_results(int32_t nprob, void* ws, size_t ws_bytes, double* rel_err, int32_t* status,
+                               void* stream);
+
+/* Times each X-pass tiling on the planned batch (q subspace iterations, no
+ * sweeps), keeps the fastest per sketch-width class in the library's
+ * autotune table (the only library-global state) and re-plans the batch with
+ * it.  tiling_out (host, 4 entries, may be NULL) receives the table: column
+ * groups for l <= 16, <= 32, <= 48, <= 64.  Synchronises the stream. */
+rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_t q, void* ws,
+                                size_t ws_bytes, int32_t* tiling_out, void* stream);
+
 /* nsweeps sweeps of deterministic HALS (Sec. 3.1, residual-free block rules)
  * on X itself, in place; randomized HALS is this algorithm run on the
  * compressed B with the lift through Q:

@@ -40,6 +40,8 @@ EXPORTS = [
     "rnmf_default_opts", "rnmf_workspace_bytes", "rnmf_status_string", "rnmf_last_error",
     "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
     "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
+    "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
+    "rnmf_batch_autotune",
 ]
 
 
@@ -50,6 +52,15 @@ class Opts(ctypes.Structure):
                 ("order", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
                 ("alpha_w", ctypes.c_double), ("alpha_h", ctypes.c_double), ("beta_w", ctypes.c_double),
                 ("beta_h", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    """rnmf_problem: one problem of a batched run (device pointers)."""
+    _fields_ = [("X", ctypes.c_void_p), ("Omega", ctypes.c_void_p), ("W0", ctypes.c_void_p),
+                ("H0", ctypes.c_void_p), ("W", ctypes.c_void_p), ("H", ctypes.c_void_p),
+                ("Q", ctypes.c_void_p), ("B", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("l", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -106,6 +117,16 @@ def lib():
         L.rnmf_hals.restype = ctypes.c_int
         L.rnmf_svd_init.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, ctypes.POINTER(Opts), vp, sz, vp]
         L.rnmf_svd_init.restype = ctypes.c_int
+        L.rnmf_batch_workspace_bytes.argtypes = [i32]
+        L.rnmf_batch_workspace_bytes.restype = sz
+        L.rnmf_batch_plan.argtypes = [ctypes.POINTER(Problem), i32, vp, sz, vp]
+        L.rnmf_batch_plan.restype = ctypes.c_int
+        L.rnmf_batch_run.argtypes = [i32, i32, i32, vp, sz, vp]
+        L.rnmf_batch_run.restype = ctypes.c_int
+        L.rnmf_batch_results.argtypes = [i32, vp, sz, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), vp]
+        L.rnmf_batch_results.restype = ctypes.c_int
+        L.rnmf_batch_autotune.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, sz, ctypes.POINTER(i32), vp]
+        L.rnmf_batch_autotune.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
         L.rnmf_cast_bf16.restype = ctypes.c_int
         L.rnmf_read_status.argtypes = [vp, sz, vp]
@@ -334,6 +355,84 @@ def svd_init(Q, B, k, ws=None):
     _check(lib().rnmf_svd_init(_ptr(Q), _ptr(B), m, n, l, int(k), _ptr(W), _ptr(H), ctypes.byref(o), _ptr(w),
                                w.numel(), _stream(Q.device)))
     return W, H
+
+
+class Batch:
+    """Batched randomized HALS (rnmf_batch_*): many independent problems in one
+    persistent launch.  problems: list of (X, Omega, W0, H0) FP32 device
+    tensors (X m x n with unit column stride, Omega n x l, W0 m x k, H0 k x n).
+    Holds the outputs W, H, Q, B of every problem and the workspace."""
+
+    def __init__(self, problems, autotune=False, q=2):
+        torch = _torch()
+        self.problems = []
+        descs = (Problem * len(problems))()
+        for i, (X, Om, W0, H0) in enumerate(problems):
+            for t, nm in ((X, "X"), (Om, "Omega"), (W0, "W0"), (H0, "H0")):
+                _need_dev(t, nm)
+                if t.dtype != torch.float32:
+                    raise ValueError(f"problem {i}: {nm} must be float32")
+            _rowmajor(X, "X")
+            for t, nm in ((Om, "Omega"), (W0, "W0"), (H0, "H0")):
+                _packed(t, nm)
+            m, n = X.shape
+            l = Om.shape[1]
+            k = W0.shape[1]
+            if Om.shape[0] != n or W0.shape[0] != m or H0.shape != (k, n):
+                raise ValueError(f"problem {i}: inconsistent shapes")
+            dev = X.device
+            out = dict(X=X, Omega=Om, W0=W0, H0=H0,
+                       W=torch.empty((m, k), dtype=torch.float32, device=dev),
+                       H=torch.empty((k, n), dtype=torch.float32, device=dev),
+                       Q=torch.empty((m, l), dtype=torch.float32, device=dev),
+                       B=torch.empty((l, n), dtype=torch.float32, device=dev),
+                       Z=torch.empty((n, l), dtype=torch.float32, device=dev))
+            self.problems.append(out)
+            d = descs[i]
+            for key in ("X", "Omega", "W0", "H0", "W", "H", "Q", "B", "Z"):
+                setattr(d, key, out[key].data_ptr())
+            d.m, d.n, d.ldx, d.k, d.l = m, n, X.stride(0), k, l
+        self.descs = descs
+        self.n = len(problems)
+        self.device = problems[0][0].device
+        nb = lib().rnmf_batch_workspace_bytes(self.n)
+        if nb == 0:
+            raise RnmfError(ERR_ARG, lib().rnmf_last_error().decode())
+        self.keep, self.ws = _workspace(nb, self.device)
+        self.tiling = None
+        if autotune:
+            tab = (ctypes.c_int32 * 4)()
+            _check(lib().rnmf_batch_autotune(descs, self.n, int(q), _ptr(self.ws), self.ws.numel(), tab,
+                                             _stream(self.device)))
+            self.tiling = list(tab)
+        else:
+            _check(lib().rnmf_batch_plan(descs, self.n, _ptr(self.ws), self.ws.numel(), _stream(self.device)))
+
+    def run(self, q=2, nsweeps=100):
+        """One persistent launch (plus a counter reset); asynchronous."""
+        _check(lib().rnmf_batch_run(self.n, int(q), int(nsweeps), _ptr(self.ws), self.ws.numel(),
+                                    _stream(self.device)))
+
+    def results(self):
+        """(rel_err list, status list) of the last run; synchronises."""
+        rel = (ctypes.c_double * self.n)()
+        st = (ctypes.c_int32 * self.n)()
+        _check(lib().rnmf_batch_results(self.n, _ptr(self.ws), self.ws.numel(), rel, st, _stream(self.device)))
+        return list(rel), list(st)
+
+    def capture(self, q=2, nsweeps=100):
+        """A HIP graph (torch.cuda.CUDAGraph) holding one run; replay() reruns it."""
+        torch = _torch()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.run(q, nsweeps)  # warm-up outside the graph sets the kernel attribute
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.graph(g):
+            self.run(q, nsweeps)
+        return g
 
 
 def rel_error(X, W, H, ws=None):

@@ -12,6 +12,8 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 using namespace rnmf;
 
@@ -471,6 +473,70 @@ size_t op_bytes(int op, int64_t m, int64_t n, const rnmf_opts* o, int xt, const 
 }
 
 // Resolves the X operand actually streamed (casting to BF16 into ws if needed).
+// ---- batched runs ----------------------------------------------------------
+struct BatchLayout {
+  unsigned* counter;
+  void* descs;
+  double* err;
+  unsigned* status;
+  size_t bytes;
+};
+BatchLayout batch_layout(void* ws, int nprob) {
+  Arena a(ws);
+  BatchLayout L;
+  L.counter = a.take<unsigned>(64);
+  L.descs = a.take<char>((size_t)nprob * batch_desc_bytes());
+  L.err = a.take<double>(2 * (size_t)nprob);
+  L.status = a.take<unsigned>((size_t)nprob);
+  L.bytes = a.used;
+  return L;
+}
+
+// X-pass column groups per sketch-width class (l <= 16, 32, 48, 64): the
+// autotune table, the library's only global state.
+std::mutex g_batch_mu;
+int g_batch_tc[4] = {4, 8, 16, 16};
+
+int l_class(int l) { return l <= 16 ? 0 : (l <= 32 ? 1 : (l <= 48 ? 2 : 3)); }
+
+rnmf_status check_problem(const rnmf_problem& p, int i) {
+  if (!p.X || !p.Omega || !p.W0 || !p.H0 || !p.W || !p.H || !p.Q || !p.B || !p.Z)
+    return fail(RNMF_ERR_ARG, "problem %d: every pointer must be non-NULL", i);
+  if (p.m < 1 || p.n < 1 || p.m > 0x7fffffffLL || p.n > 0x7fffffffLL)
+    return fail(RNMF_ERR_SHAPE, "problem %d: bad m or n", i);
+  if (p.ldx < p.n) return fail(RNMF_ERR_SHAPE, "problem %d: ldx < n", i);
+  if (p.l < 1 || p.l > 64 || p.l > p.m || p.l > p.n)
+    return fail(RNMF_ERR_SHAPE, "problem %d: need 1 <= l <= min(64, m, n) (l = %d)", i, p.l);
+  if (p.k < 1 || p.k > 32 || p.k > p.l) return fail(RNMF_ERR_ARG, "problem %d: need 1 <= k <= min(32, l)", i);
+  return RNMF_OK;
+}
+
+// Descriptors in cost order (largest first; ties by index), tiling per class.
+rnmf_status upload_plan(const rnmf_problem* probs, int nprob, const BatchLayout& L, const int* table,
+                        std::vector<int>* order_out, hipStream_t s) {
+  std::vector<int> order((size_t)nprob);
+  std::vector<double> cost((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const rnmf_problem& p = probs[i];
+    order[i] = i;
+    // X passes plus 100 sweeps of lift and map-back, in multiply-adds
+    cost[i] = 8.0 * p.m * p.n * p.l + 400.0 * p.m * p.l * p.k;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  const size_t db = batch_desc_bytes();
+  std::vector<char> host((size_t)nprob * db);
+  for (int j = 0; j < nprob; ++j) {
+    const rnmf_problem& p = probs[order[j]];
+    int tc = table[l_class(p.l)];
+    while (4 * tc < p.l) tc *= 2;
+    batch_fill_desc(host.data() + (size_t)j * db, p, order[j], tc);
+  }
+  HIPCHK(hipMemcpyAsync(L.descs, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (order_out) *order_out = order;
+  return RNMF_OK;
+}
+
 rnmf_status prepare_x(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, const rnmf_opts* o, const Mode& md,
                       void* xb_slot, const Hdr& h, const Dev& d, const void** Xc, int64_t* ldc, int* check_in_pass) {
   const int check = (o->flags & RNMF_FLAG_CHECK_INPUT) ? 1 : 0;
@@ -688,6 +754,141 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
   if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
   HIPCHK(launch_svd_init(Q, B, m, n, l, k, W, H, md.dt, b, d.stream));
   return RNMF_OK;
+}
+
+size_t rnmf_batch_workspace_bytes(int32_t nprob) {
+  g_err.clear();
+  if (nprob < 1) { fail(RNMF_ERR_ARG, "nprob must be >= 1"); return 0; }
+  return batch_layout(nullptr, nprob).bytes;
+}
+
+rnmf_status rnmf_batch_plan(const rnmf_problem* probs, int32_t nprob, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!probs || nprob < 1) return fail(RNMF_ERR_ARG, "need a host array of nprob >= 1 problems");
+  for (int i = 0; i < nprob; ++i) {
+    rnmf_status r = check_problem(probs[i], i);
+    if (r != RNMF_OK) return r;
+  }
+  const BatchLayout L = batch_layout(ws, nprob);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  int table[4];
+  {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    std::memcpy(table, g_batch_tc, sizeof(table));
+  }
+  if ((r = upload_plan(probs, nprob, L, table, nullptr, d.stream)) != RNMF_OK) return r;
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_batch_run(int32_t nprob, int32_t q, int32_t nsweeps, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (nprob < 1) return fail(RNMF_ERR_ARG, "nprob must be >= 1");
+  if (q < 0 || q > 32) return fail(RNMF_ERR_ARG, "q must be in [0, 32]");
+  if (nsweeps < 0) return fail(RNMF_ERR_ARG, "nsweeps < 0");
+  const BatchLayout L = batch_layout(ws, nprob);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const int grid = nprob < d.cus ? nprob : d.cus;
+  HIPCHK(launch_batch(L.descs, nprob, q, nsweeps, L.counter, L.err, L.status, grid, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_batch_results(int32_t nprob, void* ws, size_t ws_bytes, double* rel_err, int32_t* status,
+                               void* stream) {
+  g_err.clear();
+  if (nprob < 1) return fail(RNMF_ERR_ARG, "nprob must be >= 1");
+  const BatchLayout L = batch_layout(ws, nprob);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  std::vector<double> e(2 * (size_t)nprob);
+  std::vector<unsigned> st((size_t)nprob);
+  HIPCHK(hipMemcpyAsync(e.data(), L.err, e.size() * sizeof(double), hipMemcpyDeviceToHost, d.stream));
+  HIPCHK(hipMemcpyAsync(st.data(), L.status, st.size() * sizeof(unsigned), hipMemcpyDeviceToHost, d.stream));
+  HIPCHK(hipStreamSynchronize(d.stream));
+  for (int i = 0; i < nprob; ++i) {
+    if (rel_err) rel_err[i] = (e[2 * i + 1] > 0.0 && !(st[i] & ST_NOT_SPD)) ? std::sqrt(e[2 * i] / e[2 * i + 1]) : NAN;
+    if (status) status[i] = (st[i] & ST_NOT_SPD) ? RNMF_ERR_NOT_SPD : RNMF_OK;
+  }
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_t q, void* ws, size_t ws_bytes,
+                                int32_t* tiling_out, void* stream) {
+  g_err.clear();
+  if (!probs || nprob < 1) return fail(RNMF_ERR_ARG, "need a host array of nprob >= 1 problems");
+  if (q < 0 || q > 32) return fail(RNMF_ERR_ARG, "q must be in [0, 32]");
+  for (int i = 0; i < nprob; ++i) {
+    rnmf_status r = check_problem(probs[i], i);
+    if (r != RNMF_OK) return r;
+  }
+  const BatchLayout L = batch_layout(ws, nprob);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  int table[4];
+  {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    std::memcpy(table, g_batch_tc, sizeof(table));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct EvGuard {
+    hipEvent_t* a;
+    hipEvent_t* b;
+    ~EvGuard() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } guard{&e0, &e1};
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // each sketch-width class separately: its problems only, every tiling that
+  // covers the class's widest sketch, the range finder and compression only
+  for (int cls = 0; cls < 4; ++cls) {
+    std::vector<rnmf_problem> sub;
+    int lmax = 0;
+    for (int i = 0; i < nprob; ++i)
+      if (l_class(probs[i].l) == cls) {
+        sub.push_back(probs[i]);
+        lmax = probs[i].l > lmax ? probs[i].l : lmax;
+      }
+    if (sub.empty()) continue;
+    float best_ms = 0.f;
+    int best = table[cls];
+    for (int tc : {4, 8, 16}) {
+      if (4 * tc < lmax) continue;
+      int forced[4] = {tc, tc, tc, tc};
+      const int ns = (int)sub.size();
+      const BatchLayout S = batch_layout(ws, ns);
+      if ((r = upload_plan(sub.data(), ns, S, forced, nullptr, d.stream)) != RNMF_OK) return r;
+      const int grid = ns < d.cus ? ns : d.cus;
+      HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));  // warm-up
+      HIPCHK(hipEventRecord(e0, d.stream));
+      HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));
+      HIPCHK(hipEventRecord(e1, d.stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = tc;
+      }
+    }
+    table[cls] = best;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    std::memcpy(g_batch_tc, table, sizeof(table));
+  }
+  if (tiling_out) std::memcpy(tiling_out, table, sizeof(table));
+  return upload_plan(probs, nprob, L, table, nullptr, d.stream);
 }
 
 rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, void* W, void* H, int32_t nsweeps,

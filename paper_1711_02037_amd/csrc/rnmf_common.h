@@ -8,6 +8,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct rnmf_problem;
+
 namespace rnmf {
 
 typedef unsigned long long u64;
@@ -124,6 +126,13 @@ hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, h
 struct SvdBufs {
   double *gpart, *C, *Ub, *sv, *upart, *vpart, *coef;
 };
+// Batched randomized HALS (batch.hip).
+size_t batch_desc_bytes();
+size_t batch_lds_bytes();
+void batch_fill_desc(void* dst, const ::rnmf_problem& p, int idx, int tc);
+hipError_t launch_batch(const void* descs, int nprob, int q, int nsweeps, unsigned* counter, double* err,
+                        unsigned* status, int grid, hipStream_t s);
+
 int svd_row_blocks(int64_t m);
 int svd_col_blocks(int64_t n);
 hipError_t launch_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int l, int k, void* W, void* H,

@@ -11,12 +11,16 @@ a large matrix can be regenerated on its own:
 
     0 W* (per row chunk)   1 H*          2 noise (per row chunk)
     3 Omega                4 W0          5 H0
-    6 sparsity mask of H*  8 row-chunk subsample
+    6 sparsity mask of H*  7 batch shapes          8 row-chunk subsample
+
+The batched workload (many independent NMFs of uneven shapes) draws its shapes
+from stream 7 of its own seed; problem i is then an ordinary low-rank product
+with seed ``batch_seed(seed, i)``.
 """
 
 import numpy as np
 
-S_WSTAR, S_HSTAR, S_NOISE, S_OMEGA, S_W0, S_H0, S_MASK, S_SUB = 0, 1, 2, 3, 4, 5, 6, 8
+S_WSTAR, S_HSTAR, S_NOISE, S_OMEGA, S_W0, S_H0, S_MASK, S_BATCH, S_SUB = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 CHUNK_ROWS = 1000
 
@@ -107,6 +111,42 @@ def low_rank_rows(m, n, rank, seed, noise_abs=0.0, noise_rel=0.0, density=1.0,
         for i in range(len(sel)):
             fill(i)
     return X
+
+
+# Batched workload: independent problems with m ~ U[256, 4096], n ~ U[128, 2048],
+# k ~ U{4..32}; each X is a rank-k uniform product plus 1% relative noise,
+# clipped; p = 10, q = 2, 100 sweeps.
+BATCH = dict(count=512, m=(256, 4096), n=(128, 2048), k=(4, 32), p=10, q=2, sweeps=100,
+             noise_rel=0.01, seed=104)
+
+
+def batch_seed(seed, i):
+    return int(seed) * 1_000_003 + int(i)
+
+
+def batch_shapes(count=None, seed=None, m=None, n=None, k=None):
+    """(m, n, k) of each problem of the batched workload, drawn from stream 7."""
+    b = BATCH
+    count = b["count"] if count is None else count
+    seed = b["seed"] if seed is None else seed
+    m, n, k = m or b["m"], n or b["n"], k or b["k"]
+    g = stream(seed, S_BATCH)
+    ms = g.integers(m[0], m[1] + 1, count)
+    ns = g.integers(n[0], n[1] + 1, count)
+    ks = g.integers(k[0], k[1] + 1, count)
+    return [(int(a), int(c), int(d)) for a, c, d in zip(ms, ns, ks)]
+
+
+def batch_problem(i, m, n, k, p=None, seed=None, dtype=np.float32):
+    """Problem i of a batch: (X, Omega, W0, H0) with l = min(k + p, m, n)."""
+    b = BATCH
+    p = b["p"] if p is None else p
+    s = batch_seed(b["seed"] if seed is None else seed, i)
+    X = low_rank_rows(m, n, k, s, noise_rel=b["noise_rel"])
+    l = sketch_cols(k, p, m, n)
+    Om = omega(n, l, s)
+    W0, H0 = init_factors(m, n, k, s)
+    return X.astype(dtype), Om.astype(dtype), W0.astype(dtype), H0.astype(dtype)
 
 
 def workload(name):

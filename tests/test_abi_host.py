@@ -199,3 +199,32 @@ def test_svd_init_validation():
     assert L.rnmf_factorize(p, rn.F32, 5000, 700, 700, ctypes.byref(f), None, p, None, p, p, ctypes.byref(rep),
                             p, 1 << 40, None) == rn.ERR_ARG
     assert b"W0" in L.rnmf_last_error()
+
+
+def test_batch_problem_layout_and_validation():
+    assert ctypes.sizeof(rn.Problem) == 104
+    L = rn.lib()
+    assert L.rnmf_batch_workspace_bytes(512) > 512 * 104
+    assert L.rnmf_batch_workspace_bytes(0) == 0
+    good = dict(X=4096, Omega=4096, W0=4096, H0=4096, W=4096, H=4096, Q=4096, B=4096, Z=4096,
+                m=1000, n=500, ldx=500, k=10, l=20)
+
+    def plan(**kw):
+        d = dict(good, **kw)
+        arr = (rn.Problem * 2)()
+        for key, v in good.items():
+            setattr(arr[0], key, v)
+        for key, v in d.items():
+            setattr(arr[1], key, v)
+        return L.rnmf_batch_plan(arr, 2, ctypes.c_void_p(256), 1 << 30, None)
+
+    assert plan(l=65) == rn.ERR_SHAPE
+    assert b"problem 1" in L.rnmf_last_error()
+    assert plan(l=600, m=500, n=500) == rn.ERR_SHAPE
+    assert plan(k=33, l=40) == rn.ERR_ARG
+    assert plan(k=21) == rn.ERR_ARG
+    assert plan(ldx=499) == rn.ERR_SHAPE
+    assert plan(Z=0) == rn.ERR_ARG
+    assert L.rnmf_batch_run(4, 33, 10, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
+    assert L.rnmf_batch_run(4, 2, -1, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
+    assert L.rnmf_batch_run(4, 2, 10, ctypes.c_void_p(256), 16, None) == rn.ERR_WORKSPACE
