@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
 import argparse
+import numpy as np
 import hashlib
 import json
 import os
@@ -77,6 +78,7 @@ def main():
     ap.add_argument("--no-target", action="store_true", help="skip the time-to-target protocol")
     ap.add_argument("--no-hals", action="store_true", help="skip the deterministic HALS comparison")
     ap.add_argument("--no-svd-init", action="store_true", help="skip the SVD-based initialization comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (512 uneven problems)")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -201,6 +203,13 @@ def main():
         log(f"SVD init: {svd['ms']:.3f} ms; error after {sweeps} sweeps {svd['rel_err']:.6f} "
             f"(uniform init {svd['rel_err_uniform_init']:.6f})")
 
+    # ---- batched workload: 512 uneven problems in one persistent launch ------
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(rn, torch, synth, dev)
+        log(f"batch: {batch['problems']} problems in {batch['ms_per_run']:.2f} ms per run "
+            f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X)")
+
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -229,6 +238,7 @@ def main():
         "time_to_target": ttt,
         "hals_vs_rhals": hals,
         "svd_init": svd,
+        "batched": batch,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -326,6 +336,51 @@ def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=
     return {"ms": round(ms, 4), "rel_err": info["rel_err"], "rel_err_uniform_init": reps_f[-1]["rel_err"],
             "sweeps": sweeps, "precision": "fp32",
             "note": "nonnegative double SVD of the randomized SVD Q B (FP64 Jacobi on B B^T)"}
+
+
+def batch_bench(rn, torch, synth, dev, reps=3):
+    """The batched workload: 512 independent problems, m ~ U[256, 4096],
+    n ~ U[128, 2048], k ~ U{4..32}, p = 10, q = 2, 100 sweeps each, run as one
+    persistent launch captured in a HIP graph (after autotuning the X-pass
+    tiling); wall time of `reps` replays by events on the replay stream."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = synth.BATCH
+    shapes = synth.batch_shapes()
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        host = list(ex.map(lambda i: synth.batch_problem(i, *shapes[i]), range(len(shapes))))
+    log(f"batch: generated {len(host)} problems in {time.time() - t0:.1f}s")
+    probs = [tuple(torch.from_numpy(a).to(dev) for a in p) for p in host]
+    del host
+    b = rn.Batch(probs, autotune=True, q=w["q"])
+    g = b.capture(w["q"], w["sweeps"])
+    st = torch.cuda.current_stream(dev)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        g.replay()
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rel, status = b.results()
+    xbytes = sum(m * n * 4 for m, n, k in shapes)
+    passes = 2 * w["q"] + 2 + 1  # range finder and compression, plus the error pass
+    out = {"problems": len(shapes), "sweeps": w["sweeps"], "q": w["q"], "p": w["p"],
+           "ms_per_run": round(ms, 3), "problems_per_s": round(len(shapes) / (ms * 1e-3), 1),
+           "sweeps_per_s": round(len(shapes) * w["sweeps"] / (ms * 1e-3), 1),
+           "x_bytes": xbytes, "x_passes": passes,
+           "x_GBps": round(passes * xbytes / (ms * 1e-3) / 1e9, 1),
+           "frac_of_8TBps": round(passes * xbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+           "tiling": b.tiling, "all_ok": all(x == 0 for x in status),
+           "rel_err_mean": float(np.mean(rel)), "rel_err_max": float(np.max(rel)),
+           "arithmetic": "fp32 (FP64 Grams, Cholesky and error sums)",
+           "note": "one persistent launch per run, captured in a HIP graph; per-problem range finder, "
+                   "compression, sweeps and error run inside one workgroup"}
+    del b, probs, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def speedup_series(rn, torch, X, ks, p, q, nsw=20):

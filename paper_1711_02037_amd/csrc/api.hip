@@ -793,7 +793,8 @@ rnmf_status rnmf_batch_run(int32_t nprob, int32_t q, int32_t nsweeps, void* ws, 
   if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
-  const int grid = nprob < d.cus ? nprob : d.cus;
+  // two workgroups per compute unit (the kernel's LDS and registers allow it)
+  const int grid = nprob < 2 * d.cus ? nprob : 2 * d.cus;
   HIPCHK(launch_batch(L.descs, nprob, q, nsweeps, L.counter, L.err, L.status, grid, d.stream));
   return RNMF_OK;
 }
@@ -868,7 +869,7 @@ rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_
       const int ns = (int)sub.size();
       const BatchLayout S = batch_layout(ws, ns);
       if ((r = upload_plan(sub.data(), ns, S, forced, nullptr, d.stream)) != RNMF_OK) return r;
-      const int grid = ns < d.cus ? ns : d.cus;
+      const int grid = ns < 2 * d.cus ? ns : 2 * d.cus;
       HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));  // warm-up
       HIPCHK(hipEventRecord(e0, d.stream));
       HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));

@@ -25,7 +25,6 @@ constexpr int BKM = 32;   // largest rank
 constexpr int NCX = 32;   // X columns per chunk (X A pass)
 constexpr int MTZ = 32;   // X rows per chunk (X^T Q pass)
 constexpr int GT = 64;    // rows per tile (Grams, init, error)
-constexpr int RQT = 256;  // Q rows per tile (W phase)
 constexpr int P1 = BLM + 1;
 
 // LDS carving (floats): sweep state, then a scratch region reused by phases.
@@ -34,20 +33,24 @@ constexpr int OFF_T = OFF_WT + BLM * BKM;        // T: BLM x BKM
 constexpr int OFF_V = OFF_T + BLM * BKM;         // V: BKM x BKM
 constexpr int OFF_S = OFF_V + BKM * BKM;         // S: BKM x BKM
 constexpr int OFF_VEC = OFF_S + BKM * BKM;       // update vector: BLM
-constexpr int OFF_WS = OFF_VEC + BLM;            // lifted column tile: RQT
-constexpr int OFF_RED = OFF_WS + RQT;            // doubles: 2 x BT (2 floats each)
+constexpr int RQW = 128;                         // Q rows per tile (W phase)
+constexpr int OFF_WS = OFF_VEC + BLM;            // lifted column tile: RQW
+constexpr int OFF_RED = OFF_WS + RQW;            // doubles: 2 x BT (2 floats each)
 constexpr int OFF_SCR = OFF_RED + 2 * 2 * BT;    // scratch
-// scratch users (floats from OFF_SCR)
-constexpr int SCR_CHOL_A = 2 * BLM * P1 + 64;    // after G (doubles) and padding
-constexpr int SCR_CHOL_D = SCR_CHOL_A + 2 * BLM * P1;
-constexpr int SCR_AT = SCR_CHOL_D + 2 * 2 * BLM + 64;  // L^{-T} as floats: BLM x BLM
+// scratch users (floats from OFF_SCR): the Cholesky works in place on the
+// Gram (A, FP64, BLM x P1), then dL, dX, then L^{-T} as floats (BLM x BLM);
+// the tiles of the other phases reuse the region from its start.
+constexpr int SCR_CHOL_D = 2 * BLM * P1;
+constexpr int SCR_AT = SCR_CHOL_D + 2 * 2 * BLM;
 constexpr int SCR_FLOATS = SCR_AT + BLM * BLM;
 constexpr int LDS_FLOATS = OFF_SCR + SCR_FLOATS;
-static_assert(RQT * P1 <= SCR_AT, "Q tile overlaps the factor");
+static_assert(RQW * P1 <= SCR_FLOATS, "W-phase Q tile");
+static_assert(256 * 17 <= SCR_AT, "Cholesky QR apply tile below the factor");
 static_assert(4 * BLM <= 2 * BT, "map-back partials fit the reduction buffer");
-static_assert(OFF_RED % 2 == 0 && OFF_SCR % 2 == 0 && SCR_CHOL_A % 2 == 0 && SCR_CHOL_D % 2 == 0, "FP64 alignment");
-static_assert(NCX * 0 + 256 * (NCX + 1) + NCX * BLM <= SCR_FLOATS, "X A tiles");
+static_assert(OFF_RED % 2 == 0 && OFF_SCR % 2 == 0 && SCR_CHOL_D % 2 == 0, "FP64 alignment");
+static_assert(256 * (NCX + 1) + NCX * BLM <= SCR_FLOATS, "X A tiles");
 static_assert(MTZ * (4 * 64 + 1) + MTZ * BLM <= SCR_FLOATS, "X^T Q tiles");
+static_assert(LDS_FLOATS * 4 <= 80 * 1024 - 256, "two workgroups per compute unit");
 
 struct BDesc {
   rnmf_problem p;
@@ -66,318 +69,494 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 }
 __device__ __forceinline__ float clipf(float x) { return x > 0.f ? x : 0.f; }
 
-// Y (m x l) = X (m x n) A (n x l).  Thread (ti, tj): rows ti + tr * i,
-// columns 4 tj + u.
-__device__ void xa_pass(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, const float* __restrict__ A,
-                        int l, float* __restrict__ Y, int tc, float* scr) {
+// Global memory is addressed through address-space-1 pointers: the phases
+// are separate functions, and generic pointers would turn every access into a
+// flat instruction (which also counts against the LDS wait counter).
+typedef __attribute__((address_space(1))) const float gcf;
+typedef __attribute__((address_space(1))) float gf;
+template <typename T>
+__device__ __forceinline__ gcf* G(const T* p) { return (gcf*)p; }
+__device__ __forceinline__ gf* GW(float* p) { return (gf*)p; }
+
+// Tile loads: every load of a thread is issued before the first one is
+// waited for, so a tile costs one memory round trip, not one per element.
+// Element e = t + s * BT (s < CNT) of the tile, so a tile holds at most
+// CNT * BT elements (every caller sizes its tile to that); elements outside the tile
+// read a valid address (the tile's first element) and are replaced by zero,
+// so the loads carry no branches.
+//   flat: a contiguous block of a packed matrix, base[e] for e < valid;
+//         stored as rows of C at pitch dp;
+//   pow2: an R x 2^lg tile of a row-major matrix with row pitch sp (2^lg <=
+//         BT: a thread keeps its column and steps down BT >> lg rows).
+template <int CNT>
+__device__ __forceinline__ void flat_fetch(float (&v)[CNT], gcf* base, int valid) {
   const int t = threadIdx.x;
-  const int tr = BT / tc, RT = 4 * tr, LC = 4 * tc;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    const int e = t + s * BT;
+    const bool ok = e < valid;
+    const float x = base[ok ? e : 0];
+    v[s] = ok ? x : 0.f;
+  }
+}
+template <int CNT>
+__device__ __forceinline__ void flat_store(const float (&v)[CNT], float* dst, int dp, int C, int total) {
+  const int t = threadIdx.x;
+  // element t + s * BT: row i, column c; each step adds BT = qs * C + rs
+  int i = t / C, c = t - (t / C) * C;
+  const int qs = BT / C, rs = BT - (BT / C) * C;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    if (t + s * BT < total) dst[i * dp + c] = v[s];
+    c += rs;
+    i += qs;
+    if (c >= C) {
+      c -= C;
+      ++i;
+    }
+  }
+}
+// rows r0 .. r0 + R - 1 of a packed (rows x C) matrix into dst (pitch dp)
+template <int CNT>
+__device__ __forceinline__ void rows_load(float* dst, int dp, gcf* src, int64_t r0, int64_t rows, int R, int C) {
+  float v[CNT];
+  const int64_t left = rows - r0;
+  flat_fetch<CNT>(v, src + r0 * C, (int)((left < R ? left : R) * C));
+  flat_store<CNT>(v, dst, dp, C, R * C);
+}
+template <int CNT>
+__device__ __forceinline__ void pow2_fetch(float (&v)[CNT], gcf* src, int64_t sp, int64_t r0, int64_t rows,
+                                           int64_t c0, int64_t cols, int R, int lg) {
+  const int t = threadIdx.x;
+  const int C = 1 << lg;
+  const int c = t & (C - 1), i0 = t >> lg, di = BT >> lg;
+  const int64_t rl = rows - r0;
+  const int rmax = (int)(rl < R ? rl : R);
+  const bool colok = c0 + c < cols;
+  gcf* base = src + r0 * sp + c0;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    const int i = i0 + s * di;
+    const bool ok = colok && i < rmax;
+    const float x = base[ok ? (int64_t)i * sp + c : 0];
+    v[s] = ok ? x : 0.f;
+  }
+}
+template <int CNT>
+__device__ __forceinline__ void pow2_store(const float (&v)[CNT], float* dst, int dp, int R, int lg) {
+  const int t = threadIdx.x;
+  const int C = 1 << lg;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    const int e = t + s * BT;
+    if (e < R * C) dst[(e >> lg) * dp + (e & (C - 1))] = v[s];
+  }
+}
+__device__ __forceinline__ int ilog2(int x) { return 31 - __builtin_clz(x); }
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// (lgkmcnt) but leaves global loads and stores in flight, which a full
+// __syncthreads() would drain.  Used where only LDS data is handed between
+// threads; a full barrier follows wherever global data written by one thread
+// is read by another.
+__device__ __forceinline__ void lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = 63, expcnt = 7, lgkmcnt = 0
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// dst[0 .. count) = src[0 .. count), eight loads in flight per thread.
+__device__ __forceinline__ void copy_f(float* dst_, const float* src_, int64_t count) {
+  gf* dst = GW(dst_);
+  gcf* src = G(src_);
+  const int t = threadIdx.x;
+  for (int64_t b = 0; b < count; b += 8 * BT) {
+    float v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int64_t e = b + t + (int64_t)s * BT;
+      v[s] = e < count ? src[e] : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int64_t e = b + t + (int64_t)s * BT;
+      if (e < count) dst[e] = v[s];
+    }
+  }
+}
+
+// Y (m x l) = X (m x n) A (n x l).  Thread (ti, tj): rows ti + tr * i,
+// columns 4 tj + u.  Chunks (RT rows x NCX columns of X) run as one sequence;
+// the next chunk's loads are in flight while the current one is multiplied.
+template <int TC>
+__device__ __noinline__ void xa_pass_t(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                       const float* __restrict__ A, int l, float* __restrict__ Y_, float* scr) {
+  const int t = threadIdx.x;
+  constexpr int tr = BT / TC, RT = 4 * tr, LC = 4 * TC;
+  constexpr int XCNT = RT * NCX / BT, ACNT = NCX * LC / BT;
+  gf* Y = GW(Y_);
   float* Xs = scr;                      // RT x (NCX + 1)
   float* As = scr + RT * (NCX + 1);     // NCX x LC
   const int ti = t % tr, tj = t / tr;
-  for (int64_t r0 = 0; r0 < m; r0 += RT) {
-    double acc[4][4];
+  for (int e = t; e < NCX * LC; e += BT)
+    if (e % LC >= l) As[e] = 0.f;       // padding columns, never written below
+  const int nr = (int)((m + RT - 1) / RT), nc = (int)((n + NCX - 1) / NCX);
+  float xv[XCNT], av[ACNT];
+#define XA_FETCH(qq)                                                                     \
+  do {                                                                                   \
+    const int64_t r0_ = (int64_t)((qq) / nc) * RT, c0_ = (int64_t)((qq) % nc) * NCX;   \
+    const int64_t left_ = n - c0_;                                                       \
+    pow2_fetch<XCNT>(xv, G(X), ldx, r0_, m, c0_, n, RT, 5);                              \
+    flat_fetch<ACNT>(av, G(A + c0_ * l), (int)((left_ < NCX ? left_ : NCX) * l));       \
+  } while (0)
+  XA_FETCH(0);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
+  for (int qq = 0; qq < nr * nc; ++qq) {
+    pow2_store<XCNT>(xv, Xs, NCX + 1, RT, 5);
+    flat_store<ACNT>(av, As, LC, l, NCX * l);
+    lds_sync();
+    if (qq + 1 < nr * nc) XA_FETCH(qq + 1);
+    float s[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
-    for (int64_t c0 = 0; c0 < n; c0 += NCX) {
-      for (int e = t; e < RT * NCX; e += BT) {
-        const int i = e / NCX, c = e - (e / NCX) * NCX;
-        const int64_t r = r0 + i, cc = c0 + c;
-        Xs[i * (NCX + 1) + c] = (r < m && cc < n) ? X[r * ldx + cc] : 0.f;
-      }
-      for (int e = t; e < NCX * LC; e += BT) {
-        const int a = e / LC, j = e - (e / LC) * LC;
-        As[a * LC + j] = (c0 + a < n && j < l) ? A[(c0 + a) * l + j] : 0.f;
-      }
-      __syncthreads();
-      float s[4][4];
+      for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
+#pragma unroll 2
+    for (int c = 0; c < NCX; ++c) {
+      float xr[4], ar[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xr[i] = Xs[(ti + tr * i) * (NCX + 1) + c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ar[u] = As[c * LC + tj * 4 + u];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
-      for (int c = 0; c < NCX; ++c) {
-        float xv[4], av[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xv[i] = Xs[(ti + tr * i) * (NCX + 1) + c];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = As[c * LC + tj * 4 + u];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) s[i][u] = fmaf(xv[i], av[u], s[i][u]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[i][u] += (double)s[i][u];
-      __syncthreads();
+        for (int u = 0; u < 4; ++u) s[i][u] = fmaf(xr[i], ar[u], s[i][u]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + ti + tr * i;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = tj * 4 + u;
-        if (r < m && j < l) Y[r * l + j] = (float)acc[i][u];
+      for (int u = 0; u < 4; ++u) acc[i][u] += (double)s[i][u];
+    lds_sync();
+    if (qq % nc == nc - 1) {
+      const int64_t r0 = (int64_t)(qq / nc) * RT;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + ti + tr * i;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = tj * 4 + u;
+          if (r < m && j < l) Y[r * l + j] = (float)acc[i][u];
+          acc[i][u] = 0.0;
+        }
       }
     }
   }
   __syncthreads();  // Y is read next by other threads of the workgroup
+#undef XA_FETCH
+}
+
+__device__ __noinline__ void xa_pass(const float* X, int64_t ldx, int64_t m, int64_t n, const float* A, int l,
+                                     float* Y, int tc, float* scr) {
+  if (tc == 4) xa_pass_t<4>(X, ldx, m, n, A, l, Y, scr);
+  else if (tc == 8) xa_pass_t<8>(X, ldx, m, n, A, l, Y, scr);
+  else xa_pass_t<16>(X, ldx, m, n, A, l, Y, scr);
 }
 
 // Z (n x l) = X^T Q, and optionally B = Z^T (l x n).  Thread (ti, tj): Z rows
-// (X columns) c0 + ti + tz * i, columns 4 tj + u.
-__device__ void xtq_pass(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, const float* __restrict__ Q,
-                         int l, float* __restrict__ Z, float* __restrict__ Bout, int tc, float* scr) {
+// (X columns) c0 + ti + tz * i, columns 4 tj + u.  Chunks (MTZ rows x NZ
+// columns of X) run as one sequence, the next one's loads in flight.
+template <int TC>
+__device__ __noinline__ void xtq_pass_t(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                        const float* __restrict__ Q, int l, float* __restrict__ Z_,
+                                        float* __restrict__ Bout_, float* scr) {
   const int t = threadIdx.x;
-  const int tz = BT / tc, NZ = 4 * tz, LC = 4 * tc;
+  constexpr int tz = BT / TC, NZ = 4 * tz, LC = 4 * TC;
+  constexpr int XCNT = MTZ * NZ / BT, QCNT = MTZ * LC / BT;
+  gf* Z = GW(Z_);
+  gf* Bout = Bout_ ? GW(Bout_) : nullptr;
   float* Xs = scr;                    // MTZ x (NZ + 1)
   float* Qs = scr + MTZ * (NZ + 1);   // MTZ x LC
   const int ti = t % tz, tj = t / tz;
-  for (int64_t c0 = 0; c0 < n; c0 += NZ) {
-    double acc[4][4];
+  const int lgz = ilog2(NZ);
+  for (int e = t; e < MTZ * LC; e += BT)
+    if (e % LC >= l) Qs[e] = 0.f;     // padding columns, never written below
+  const int ncb = (int)((n + NZ - 1) / NZ), nrb = (int)((m + MTZ - 1) / MTZ);
+  float xv[XCNT], qv[QCNT];
+#define XTQ_FETCH(qq)                                                                    \
+  do {                                                                                   \
+    const int64_t c0_ = (int64_t)((qq) / nrb) * NZ, r0_ = (int64_t)((qq) % nrb) * MTZ;  \
+    const int64_t left_ = m - r0_;                                                       \
+    pow2_fetch<XCNT>(xv, G(X), ldx, r0_, m, c0_, n, MTZ, lgz);                           \
+    flat_fetch<QCNT>(qv, G(Q + r0_ * l), (int)((left_ < MTZ ? left_ : MTZ) * l));       \
+  } while (0)
+  XTQ_FETCH(0);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
+  for (int qq = 0; qq < ncb * nrb; ++qq) {
+    pow2_store<XCNT>(xv, Xs, NZ + 1, MTZ, lgz);
+    flat_store<QCNT>(qv, Qs, LC, l, MTZ * l);
+    lds_sync();
+    if (qq + 1 < ncb * nrb) XTQ_FETCH(qq + 1);
+    float s[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
-    for (int64_t r0 = 0; r0 < m; r0 += MTZ) {
-      for (int e = t; e < MTZ * NZ; e += BT) {
-        const int i = e / NZ, c = e - (e / NZ) * NZ;
-        const int64_t r = r0 + i, cc = c0 + c;
-        Xs[i * (NZ + 1) + c] = (r < m && cc < n) ? X[r * ldx + cc] : 0.f;
-      }
-      for (int e = t; e < MTZ * LC; e += BT) {
-        const int i = e / LC, j = e - (e / LC) * LC;
-        Qs[i * LC + j] = (r0 + i < m && j < l) ? Q[(r0 + i) * l + j] : 0.f;
-      }
-      __syncthreads();
-      float s[4][4];
+      for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
+#pragma unroll 2
+    for (int rr = 0; rr < MTZ; ++rr) {
+      float xr[4], qr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xr[i] = Xs[rr * (NZ + 1) + ti + tz * i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) qr[u] = Qs[rr * LC + tj * 4 + u];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
-      for (int rr = 0; rr < MTZ; ++rr) {
-        float xv[4], qv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xv[i] = Xs[rr * (NZ + 1) + ti + tz * i];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) qv[u] = Qs[rr * LC + tj * 4 + u];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) s[i][u] = fmaf(xv[i], qv[u], s[i][u]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[i][u] += (double)s[i][u];
-      __syncthreads();
+        for (int u = 0; u < 4; ++u) s[i][u] = fmaf(xr[i], qr[u], s[i][u]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t c = c0 + ti + tz * i;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = tj * 4 + u;
-        if (c < n && j < l) {
-          Z[c * l + j] = (float)acc[i][u];
-          if (Bout) Bout[(int64_t)j * n + c] = (float)acc[i][u];
+      for (int u = 0; u < 4; ++u) acc[i][u] += (double)s[i][u];
+    lds_sync();
+    if (qq % nrb == nrb - 1) {
+      const int64_t c0 = (int64_t)(qq / nrb) * NZ;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t c = c0 + ti + tz * i;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = tj * 4 + u;
+          if (c < n && j < l) {
+            Z[c * l + j] = (float)acc[i][u];
+            if (Bout) Bout[(int64_t)j * n + c] = (float)acc[i][u];
+          }
+          acc[i][u] = 0.0;
         }
       }
     }
   }
   __syncthreads();  // Z is read next by other threads of the workgroup
+#undef XTQ_FETCH
 }
 
-// Cholesky of G (l x l, in LDS, pitch P1) with the inverse fused, in blocks
-// of 8 columns (the scheme of the single-problem factorisation).  A holds L
-// in its strict lower triangle and X = L^{-1} transposed in its strict upper
-// triangle; dL, dX the diagonals.  Returns 0 (plain), 1 (after the shift) or
-// 2 (not positive definite).
-__device__ int chol_lds(const double* G, double* A, double* dL, double* dX, int* flag, int l, int64_t rows) {
+__device__ __noinline__ void xtq_pass(const float* X, int64_t ldx, int64_t m, int64_t n, const float* Q, int l,
+                                      float* Z, float* Bout, int tc, float* scr) {
+  if (tc == 4) xtq_pass_t<4>(X, ldx, m, n, Q, l, Z, Bout, scr);
+  else if (tc == 8) xtq_pass_t<8>(X, ldx, m, n, Q, l, Z, Bout, scr);
+  else xtq_pass_t<16>(X, ldx, m, n, Q, l, Z, Bout, scr);
+}
+
+// Cholesky of the Gram in A (l x l, lower triangle and diagonal, in LDS,
+// pitch P1; the strict upper triangle zero) in place, with the inverse fused,
+// in blocks of 8 columns (the scheme of the single-problem factorisation).
+// On exit A holds L in its strict lower triangle and X = L^{-1} transposed in
+// its strict upper triangle; dL, dX the diagonals.  Returns false if a pivot
+// is not positive and finite.
+__device__ __noinline__ bool chol_lds(double* A, double* dL, double* dX, int* flag, int l) {
   constexpr int CB = 8;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    for (int e = t; e < l * l; e += BT) {
-      const int i = e / l, j = e - (e / l) * l;
-      A[i * P1 + j] = (j <= i) ? G[i * P1 + j] : 0.0;
+  for (int i = t; i < l; i += BT) dX[i] = 1.0;
+  if (t == 0) *flag = 0;
+  lds_sync();
+  for (int jb = 0; jb < l; jb += CB) {
+    const int je = (l - jb < CB) ? l : jb + CB;
+    if (wave == 0) {
+      for (int jj = jb; jj < je; ++jj) {
+        const double d = A[jj * P1 + jj];
+        if (!(d > 0.0) || !(d < INFINITY)) {
+          if (lane == 0) *flag = 1;
+          break;
+        }
+        const double r = sqrt(d), ri = 1.0 / r;
+        const int ii = jj + 1 + lane;
+        if (ii < je) A[ii * P1 + jj] *= ri;
+        if (lane == 0) dL[jj] = r;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int w = je - jj - 1;
+        for (int q = lane; q < w * w; q += 64) {
+          const int a = jj + 1 + q / w, b = jj + 1 + q - (q / w) * w;
+          if (b <= a) A[a * P1 + b] -= A[a * P1 + jj] * A[b * P1 + jj];
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
     }
-    for (int i = t; i < l; i += BT) dX[i] = 1.0;
-    if (t == 0) *flag = 0;
-    __syncthreads();
-    if (attempt == 1) {
-      double trace = 0.0;
-      for (int i = 0; i < l; ++i) trace += A[i * P1 + i];
-      const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace;
-      __syncthreads();
-      for (int i = t; i < l; i += BT) A[i * P1 + i] += shift;
-      __syncthreads();
-    }
-    bool fail = false;
-    for (int jb = 0; jb < l; jb += CB) {
-      const int je = (l - jb < CB) ? l : jb + CB;
-      if (wave == 0) {
+    lds_sync();
+    if (*flag) return false;  // the same value in every thread
+    if (t < 128) {
+      const int i = je + t;
+      if (i < l) {
         for (int jj = jb; jj < je; ++jj) {
-          const double d = A[jj * P1 + jj];
-          if (!(d > 0.0) || !(d < INFINITY)) {
-            if (lane == 0) *flag = 1;
-            break;
-          }
-          const double r = sqrt(d), ri = 1.0 / r;
-          const int ii = jj + 1 + lane;
-          if (ii < je) A[ii * P1 + jj] *= ri;
-          if (lane == 0) dL[jj] = r;
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-          __builtin_amdgcn_s_waitcnt(0xC07F);
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-          const int w = je - jj - 1;
-          for (int q = lane; q < w * w; q += 64) {
-            const int a = jj + 1 + q / w, b = jj + 1 + q - (q / w) * w;
-            if (b <= a) A[a * P1 + b] -= A[a * P1 + jj] * A[b * P1 + jj];
-          }
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-          __builtin_amdgcn_s_waitcnt(0xC07F);
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          double x = A[i * P1 + jj];
+          for (int p = jb; p < jj; ++p) x -= A[i * P1 + p] * A[jj * P1 + p];
+          A[i * P1 + jj] = x / dL[jj];
         }
       }
-      __syncthreads();
-      if (*flag) { fail = true; break; }
-      if (t < 128) {
-        const int i = je + t;
-        if (i < l) {
-          for (int jj = jb; jj < je; ++jj) {
-            double x = A[i * P1 + jj];
-            for (int p = jb; p < jj; ++p) x -= A[i * P1 + p] * A[jj * P1 + p];
-            A[i * P1 + jj] = x / dL[jj];
-          }
-        }
-      } else {
-        const int c = t - 128;
-        if (c < je) {
-          const int s0 = c > jb ? c : jb;
-          for (int jj = s0; jj < je; ++jj) {
-            double x = (jj == c) ? dX[jj] : A[c * P1 + jj];
-            for (int p = s0; p < jj; ++p) x -= A[jj * P1 + p] * ((p == c) ? dX[p] : A[c * P1 + p]);
-            x /= dL[jj];
-            if (jj == c) dX[jj] = x;
-            else A[c * P1 + jj] = x;
-          }
+    } else {
+      const int c = t - 128;
+      if (c < je) {
+        const int s0 = c > jb ? c : jb;
+        for (int jj = s0; jj < je; ++jj) {
+          double x = (jj == c) ? dX[jj] : A[c * P1 + jj];
+          for (int p = s0; p < jj; ++p) x -= A[jj * P1 + p] * ((p == c) ? dX[p] : A[c * P1 + p]);
+          x /= dL[jj];
+          if (jj == c) dX[jj] = x;
+          else A[c * P1 + jj] = x;
         }
       }
-      __syncthreads();
-      const int w = l - je, na = w * (w + 1) / 2, nx = w * je;
-      for (int q = t; q < na + nx; q += BT) {
-        if (q < na) {
-          int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-          while ((i + 1) * (i + 2) / 2 <= q) ++i;
-          while (i * (i + 1) / 2 > q) --i;
-          const int pp = q - i * (i + 1) / 2;
-          const int ri = je + i, rp = je + pp;
-          double acc = A[ri * P1 + rp];
-          for (int cc = jb; cc < je; ++cc) acc -= A[ri * P1 + cc] * A[rp * P1 + cc];
-          A[ri * P1 + rp] = acc;
-        } else {
-          const int e = q - na;
-          const int i = je + e / je, c = e - (e / je) * je;
-          double acc = A[c * P1 + i];
-          for (int qq = (c > jb ? c : jb); qq < je; ++qq) acc -= A[i * P1 + qq] * ((qq == c) ? dX[qq] : A[c * P1 + qq]);
-          A[c * P1 + i] = acc;
-        }
-      }
-      __syncthreads();
     }
-    if (!fail) return attempt;
-    __syncthreads();
+    lds_sync();
+    const int w = l - je, na = w * (w + 1) / 2, nx = w * je;
+    for (int q = t; q < na + nx; q += BT) {
+      if (q < na) {
+        int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= q) ++i;
+        while (i * (i + 1) / 2 > q) --i;
+        const int pp = q - i * (i + 1) / 2;
+        const int ri = je + i, rp = je + pp;
+        double acc = A[ri * P1 + rp];
+        for (int cc = jb; cc < je; ++cc) acc -= A[ri * P1 + cc] * A[rp * P1 + cc];
+        A[ri * P1 + rp] = acc;
+      } else {
+        const int e = q - na;
+        const int i = je + e / je, c = e - (e / je) * je;
+        double acc = A[c * P1 + i];
+        for (int qq = (c > jb ? c : jb); qq < je; ++qq) acc -= A[i * P1 + qq] * ((qq == c) ? dX[qq] : A[c * P1 + qq]);
+        A[c * P1 + i] = acc;
+      }
+    }
+    lds_sync();
   }
-  return 2;
+  return true;
 }
 
-// One Cholesky QR pass on Y (rows x l, global, in place).  Returns chol_lds's code.
-__device__ int cholqr_pass(float* __restrict__ Y, int64_t rows, int l, int tc, float* scr, int* flag) {
+// FP64 Gram Y^T Y of Y (rows x l, global) into A (lower triangle and
+// diagonal; strict upper triangle zero; pitch P1).  The row tiles are staged
+// in the same LDS region, which A overwrites only after the last tile.
+__device__ __noinline__ void gram_y(const float* __restrict__ Y, int64_t rows, int l, double* A, float* scr) {
   const int t = threadIdx.x;
-  double* G = (double*)scr;
-  double* A = (double*)(scr + SCR_CHOL_A);
+  float* Ys = scr;  // GT x P1
+  const int ga = t % 16, gb = t / 16;
+  double g[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[i][u] = 0.0;
+  const int ntile = (int)((rows + GT - 1) / GT);
+  float yv[16];
+  flat_fetch<16>(yv, G(Y), (int)((rows < GT ? rows : GT) * l));
+  for (int it = 0; it < ntile; ++it) {
+    const int64_t r0 = (int64_t)it * GT;
+    flat_store<16>(yv, Ys, P1, l, GT * l);
+    lds_sync();
+    if (it + 1 < ntile) {
+      const int64_t left = rows - (r0 + GT);
+      flat_fetch<16>(yv, G(Y + (r0 + GT) * l), (int)((left < GT ? left : GT) * l));
+    }
+    for (int rr = 0; rr < GT; ++rr) {
+      double ya[4], yb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = ga + 16 * i, b = gb + 16 * i;
+        ya[i] = a < l ? (double)Ys[rr * P1 + a] : 0.0;
+        yb[i] = b < l ? (double)Ys[rr * P1 + b] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[i][u] = fma(ya[i], yb[u], g[i][u]);
+    }
+    lds_sync();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = ga + 16 * i, b = gb + 16 * u;
+      if (a < l && b < l) A[a * P1 + b] = (b <= a) ? g[i][u] : 0.0;
+    }
+  lds_sync();
+}
+
+// One Cholesky QR pass on Y (rows x l, global, in place): FP64 Gram, Cholesky
+// with the inverse fused (when it breaks down, the Gram is recomputed and the
+// diagonal shifted by 11 (rows l + l (l + 1)) u tr(G), Fukaya et al.), then
+// Y <- Y L^{-T}.  Returns 0 (plain), 1 (after the shift) or 2 (failed).
+__device__ __noinline__ int cholqr_pass(float* __restrict__ Y_, int64_t rows, int l, int tc, float* scr, int* flag) {
+  const int t = threadIdx.x;
+  float* Y = Y_;
+  gf* Yw = GW(Y_);
+  double* A = (double*)scr;
   double* dL = (double*)(scr + SCR_CHOL_D);
   double* dX = dL + BLM;
   float* At = scr + SCR_AT;
-  // Gram in FP64: thread (ga, gb) owns entries (ga + 16 i, gb + 16 u)
-  {
-    float* Ys = scr + SCR_CHOL_A;  // GT x P1 floats; G is written only after the loop
-    const int ga = t % 16, gb = t / 16;
-    double g[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) g[i][u] = 0.0;
-    for (int64_t r0 = 0; r0 < rows; r0 += GT) {
-      for (int e = t; e < GT * l; e += BT) {
-        const int i = e / l, a = e - (e / l) * l;
-        Ys[i * P1 + a] = (r0 + i < rows) ? Y[(r0 + i) * l + a] : 0.f;
-      }
-      __syncthreads();
-      for (int rr = 0; rr < GT; ++rr) {
-        double ya[4], yb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int a = ga + 16 * i, b = gb + 16 * i;
-          ya[i] = a < l ? (double)Ys[rr * P1 + a] : 0.0;
-          yb[i] = b < l ? (double)Ys[rr * P1 + b] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) g[i][u] = fma(ya[i], yb[u], g[i][u]);
-      }
-      __syncthreads();
+  int code = -1;
+  for (int attempt = 0; attempt < 2 && code < 0; ++attempt) {
+    gram_y(Y, rows, l, A, scr);
+    if (attempt == 1) {
+      double trace = 0.0;
+      for (int i = 0; i < l; ++i) trace += A[i * P1 + i];  // same order in every thread
+      const double shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace;
+      lds_sync();
+      for (int i = t; i < l; i += BT) A[i * P1 + i] += shift;
+      lds_sync();
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int a = ga + 16 * i, b = gb + 16 * u;
-        if (a < l && b < l) G[a * P1 + b] = g[i][u];
-      }
-    __syncthreads();
+    if (chol_lds(A, dL, dX, flag, l)) code = attempt;
   }
-  const int code = chol_lds(G, A, dL, dX, flag, l, rows);
-  if (code == 2) return 2;
+  if (code < 0) return 2;
   // At(a, c) = X(c, a) = L^{-1}(c, a) for a <= c, so Q = Y At
   for (int e = t; e < l * l; e += BT) {
     const int a = e / l, c = e - (e / l) * l;
     At[a * BLM + c] = (float)((a == c) ? dX[c] : (a < c ? A[a * P1 + c] : 0.0));
   }
-  __syncthreads();
-  // Q = Y At in place, RT rows per tile
+  lds_sync();
+  // Q = Y At in place, RT rows per tile (pitch l + 1, below At)
   {
-    const int tr = BT / tc, RT = 4 * tr;
-    float* Ys = scr;  // RT x P1 floats, below At
+    const int tr = BT / tc, RT = 4 * tr, pa = l + 1;
+    float* Ys = scr;
     const int ti = t % tr, tj = t / tr;
-    for (int64_t r0 = 0; r0 < rows; r0 += RT) {
-      for (int e = t; e < RT * l; e += BT) {
-        const int i = e / l, a = e - (e / l) * l;
-        Ys[i * P1 + a] = (r0 + i < rows) ? Y[(r0 + i) * l + a] : 0.f;
+    const int ntile = (int)((rows + RT - 1) / RT);
+    float yv[16];
+    flat_fetch<16>(yv, G(Y), (int)((rows < RT ? rows : RT) * l));
+    for (int it = 0; it < ntile; ++it) {
+      const int64_t r0 = (int64_t)it * RT;
+      flat_store<16>(yv, Ys, pa, l, RT * l);
+      lds_sync();
+      if (it + 1 < ntile) {  // rows of the next tile are not written before they are loaded
+        const int64_t left = rows - (r0 + RT);
+        flat_fetch<16>(yv, G(Y + (r0 + RT) * l), (int)((left < RT ? left : RT) * l));
       }
-      __syncthreads();
       float s[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
       for (int a = 0; a < l; ++a) {
-        float yv[4], av[4];
+        float yr[4], ar[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) yv[i] = Ys[(ti + tr * i) * P1 + a];
+        for (int i = 0; i < 4; ++i) yr[i] = Ys[(ti + tr * i) * pa + a];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = tj * 4 + u;
-          av[u] = c < l ? At[a * BLM + c] : 0.f;
+          ar[u] = c < l ? At[a * BLM + c] : 0.f;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) s[i][u] = fmaf(yv[i], av[u], s[i][u]);
+          for (int u = 0; u < 4; ++u) s[i][u] = fmaf(yr[i], ar[u], s[i][u]);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -385,17 +564,18 @@ __device__ int cholqr_pass(float* __restrict__ Y, int64_t rows, int l, int tc, f
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = tj * 4 + u;
-          if (r < rows && c < l) Y[r * l + c] = s[i][u];
+          if (r < rows && c < l) Yw[r * l + c] = s[i][u];
         }
       }
-      __syncthreads();
+      lds_sync();
     }
   }
+  __syncthreads();  // Y is read next by other threads of the workgroup
   return code;
 }
 
 // Cholesky QR2 (a third pass after a shifted one).  Returns status bits.
-__device__ unsigned cholqr2(float* Y, int64_t rows, int l, int tc, float* scr, int* flag) {
+__device__ __noinline__ unsigned cholqr2(float* Y, int64_t rows, int l, int tc, float* scr, int* flag) {
   unsigned st = 0;
   bool shifted = false;
   for (int pass = 0; pass < 3; ++pass) {
@@ -408,17 +588,14 @@ __device__ unsigned cholqr2(float* Y, int64_t rows, int l, int tc, float* scr, i
 }
 
 // S = W^T W (k x k, FP64 sums) into Ss (pitch BKM).
-__device__ void gram_w(const float* __restrict__ W, int64_t m, int k, float* Ss, float* scr) {
+__device__ __noinline__ void gram_w(const float* __restrict__ W, int64_t m, int k, float* Ss, float* scr) {
   const int t = threadIdx.x;
   float* Wsh = scr;  // GT x (BKM + 1)
   const int gi = t % 16, gj = t / 16;
   double s[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int64_t r0 = 0; r0 < m; r0 += GT) {
-    for (int e = t; e < GT * k; e += BT) {
-      const int i = e / k, j = e - (e / k) * k;
-      Wsh[i * (BKM + 1) + j] = (r0 + i < m) ? W[(r0 + i) * k + j] : 0.f;
-    }
-    __syncthreads();
+    rows_load<8>(Wsh, BKM + 1, G(W), r0, m, GT, k);
+    lds_sync();
     for (int rr = 0; rr < GT; ++rr) {
       double a[2], b[2];
 #pragma unroll
@@ -432,7 +609,7 @@ __device__ void gram_w(const float* __restrict__ W, int64_t m, int k, float* Ss,
 #pragma unroll
         for (int v = 0; v < 2; ++v) s[u][v] = fma(a[u], b[v], s[u][v]);
     }
-    __syncthreads();
+    lds_sync();
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -441,11 +618,11 @@ __device__ void gram_w(const float* __restrict__ W, int64_t m, int k, float* Ss,
       const int i = gi + 16 * u, j = gj + 16 * v;
       if (i < k && j < k) Ss[i * BKM + j] = (float)s[u][v];
     }
-  __syncthreads();
+  lds_sync();
 }
 
 // W~ = Q^T W (l x k, FP64 sums) into Wts (pitch BKM).
-__device__ void init_wt(const float* __restrict__ Q, const float* __restrict__ W, int64_t m, int l, int k, float* Wts,
+__device__ __noinline__ void init_wt(const float* __restrict__ Q, const float* __restrict__ W, int64_t m, int l, int k, float* Wts,
                         float* scr) {
   const int t = threadIdx.x;
   float* Qsh = scr;                  // GT x P1
@@ -455,15 +632,9 @@ __device__ void init_wt(const float* __restrict__ Q, const float* __restrict__ W
 #pragma unroll
   for (int i = 0; i < 4; ++i) s[i][0] = s[i][1] = 0.0;
   for (int64_t r0 = 0; r0 < m; r0 += GT) {
-    for (int e = t; e < GT * l; e += BT) {
-      const int i = e / l, a = e - (e / l) * l;
-      Qsh[i * P1 + a] = (r0 + i < m) ? Q[(r0 + i) * l + a] : 0.f;
-    }
-    for (int e = t; e < GT * k; e += BT) {
-      const int i = e / k, j = e - (e / k) * k;
-      Wsh[i * (BKM + 1) + j] = (r0 + i < m) ? W[(r0 + i) * k + j] : 0.f;
-    }
-    __syncthreads();
+    rows_load<16>(Qsh, P1, G(Q), r0, m, GT, l);
+    rows_load<8>(Wsh, BKM + 1, G(W), r0, m, GT, k);
+    lds_sync();
     for (int rr = 0; rr < GT; ++rr) {
       double qa[4], wj[2];
 #pragma unroll
@@ -481,7 +652,7 @@ __device__ void init_wt(const float* __restrict__ Q, const float* __restrict__ W
 #pragma unroll
         for (int u = 0; u < 2; ++u) s[i][u] = fma(qa[i], wj[u], s[i][u]);
     }
-    __syncthreads();
+    lds_sync();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -490,43 +661,95 @@ __device__ void init_wt(const float* __restrict__ Q, const float* __restrict__ W
       const int a = ga + 16 * i, j = gj + 16 * u;
       if (a < l && j < k) Wts[a * BKM + j] = (float)s[i][u];
     }
-  __syncthreads();
+  lds_sync();
 }
 
-// Rows of H (Algorithm 1, H rule with S = W^T W), one wavefront per column of
-// H: lane j holds H(j, c) and the running gradient (FP64), Gauss-Seidel over j.
-__device__ void h_phase(const float* __restrict__ Bt, float* __restrict__ H, int64_t n, int l, int k,
-                        const float* Wts, const float* Ss) {
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int jj = lane < k ? lane : 0;
-  double rinv = 0.0;
-  if (lane < k) {
-    const double d = (double)Ss[lane * BKM + lane];
-    rinv = d > 0.0 ? 1.0 / d : 0.0;
+// Rows of H (Algorithm 1, H rule with S = W^T W), one lane per column c of H:
+// the lane holds H(:, c) and the gradient g = R(c, :) - H(:, c)^T S in
+// registers and runs the Gauss-Seidel chain over j on its own (the columns of
+// H are independent); W~, S and the reciprocal scales are LDS broadcasts.
+// KB >= k: W~ and S are zero beyond k, so the extra rows have scale zero and
+// are skipped like any zero-scale row.  B^T is staged through LDS in tiles of
+// NCT columns (256 when l <= 32, else 128).  FP64 gradient; H entries are
+// FP32 values (every update is rounded to FP32 before it is used).
+template <int KB>
+__device__ __noinline__ void h_phase_t(const float* __restrict__ Bt, float* __restrict__ H, int64_t n, int l, int k,
+                                       const float* Wts, const float* Ss, double* rinv, float* scr) {
+  const int t = threadIdx.x;
+  gcf* Hg = G(H);
+  gf* Hw = GW(H);
+  const int NCT = (l <= 32) ? 256 : 128;  // NCT * l <= 32 * BT: the tile fits the 32 loads per thread
+  const int pz = l + 1;
+  float* Zs = scr;  // NCT x (l + 1)
+  if (t < KB) {
+    const double d = (double)Ss[t * BKM + t];
+    rinv[t] = (t < k && d > 0.0) ? 1.0 / d : 0.0;
   }
-  for (int64_t c = wave; c < n; c += BT / 64) {
-    double h = lane < k ? (double)H[(int64_t)lane * n + c] : 0.0;
-    const float bcol = lane < l ? Bt[c * l + lane] : 0.f;
-    double g = 0.0;
-    for (int a = 0; a < l; ++a) g = fma((double)readlane_f(bcol, a), (double)Wts[a * BKM + jj], g);
-    for (int p = 0; p < k; ++p) g = fma(-(double)Ss[p * BKM + jj], readlane_d(h, p), g);
-    for (int i = 0; i < k; ++i) {
-      const double rd = readlane_d(rinv, i);
-      const double hi = readlane_d(h, i), gi = readlane_d(g, i);
-      const double hn = (rd > 0.0) ? (double)clipf((float)fma(gi, rd, hi)) : hi;
-      const double delta = hn - hi;
-      if (lane == i) h = hn;
-      g = fma(-(double)Ss[i * BKM + jj], delta, g);
+  for (int64_t c0 = 0; c0 < n; c0 += NCT) {
+    {
+      float zv[32];
+      const int64_t left = n - c0;
+      flat_fetch<32>(zv, G(Bt + c0 * l), (int)((left < NCT ? left : NCT) * l));
+      flat_store<32>(zv, Zs, pz, l, NCT * l);
     }
-    if (lane < k) H[(int64_t)lane * n + c] = (float)h;
+    lds_sync();
+    const int64_t c = c0 + t;
+    if (t < NCT && c < n) {
+      float h[KB];
+      double g[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        h[j] = j < k ? Hg[(int64_t)j * n + c] : 0.f;
+        g[j] = 0.0;
+      }
+      for (int a = 0; a < l; ++a) {  // R(c, j) = sum_a B(a, c) W~(a, j)
+        const double bz = (double)Zs[t * pz + a];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) g[j] = fma(bz, (double)Wts[a * BKM + j], g[j]);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
+      // (the compiler fences keep each step's LDS broadcasts inside the step,
+      // so the unrolled loops do not hoist KB x KB values into registers)
+#pragma unroll
+      for (int p = 0; p < KB; ++p) {  // g(j) -= sum_p S(p, j) H(p, c)
+        const double hp = (double)h[p];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) g[j] = fma(-(double)Ss[p * BKM + j], hp, g[j]);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {  // Gauss-Seidel over the rows
+        const double rd = rinv[j];
+        if (rd > 0.0) {
+          const float hn = clipf((float)fma(g[j], rd, (double)h[j]));
+          const double delta = (double)hn - (double)h[j];
+          h[j] = hn;
+#pragma unroll
+          for (int p = 0; p < KB; ++p) g[p] = fma(-(double)Ss[j * BKM + p], delta, g[p]);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
+#pragma unroll
+      for (int j = 0; j < KB; ++j)
+        if (j < k) Hw[(int64_t)j * n + c] = h[j];
+    }
+    lds_sync();
   }
-  __syncthreads();
+  __syncthreads();  // H is read next by other threads of the workgroup
+}
+
+__device__ __noinline__ void h_phase(const float* Bt, float* H, int64_t n, int l, int k, const float* Wts,
+                                     const float* Ss, double* rinv, float* scr) {
+  if (k <= 8) h_phase_t<8>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
+  else if (k <= 16) h_phase_t<16>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
+  else if (k <= 24) h_phase_t<24>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
+  else h_phase_t<32>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
 }
 
 // T = B H^T (l x k) and V = H H^T (k x k) over 64-column tiles: FP32 within a
 // tile, FP64 across tiles.  Threads 0..127: T entries (ga + 16 i, gj + 8 u);
 // threads 128..191: V entries (vi + 8 p, vj + 8 q).
-__device__ void tv_phase(const float* __restrict__ Bt, const float* __restrict__ H, int64_t n, int l, int k, float* Ts,
+__device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float* __restrict__ H, int64_t n, int l, int k, float* Ts,
                          float* Vs, float* scr) {
   const int t = threadIdx.x;
   float* Zs = scr;                // 64 (columns) x P1
@@ -537,15 +760,15 @@ __device__ void tv_phase(const float* __restrict__ Bt, const float* __restrict__
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
   for (int64_t c0 = 0; c0 < n; c0 += 64) {
-    for (int e = t; e < 64 * l; e += BT) {
-      const int c = e / l, a = e - (e / l) * l;
-      Zs[c * P1 + a] = (c0 + c < n) ? Bt[(c0 + c) * l + a] : 0.f;
+    {
+      float zv[16], hv[8];
+      const int64_t left = n - c0;
+      flat_fetch<16>(zv, G(Bt + c0 * l), (int)((left < 64 ? left : 64) * l));
+      pow2_fetch<8>(hv, G(H), n, 0, k, c0, n, k, 6);
+      flat_store<16>(zv, Zs, P1, l, 64 * l);
+      pow2_store<8>(hv, Hs, 65, k, 6);
     }
-    for (int e = t; e < k * 64; e += BT) {
-      const int j = e / 64, c = e - (e / 64) * 64;
-      Hs[j * 65 + c] = (c0 + c < n) ? H[(int64_t)j * n + c0 + c] : 0.f;
-    }
-    __syncthreads();
+    lds_sync();
     float s[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -590,7 +813,7 @@ __device__ void tv_phase(const float* __restrict__ Bt, const float* __restrict__
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[i][u] += (double)s[i][u];
-    __syncthreads();
+    lds_sync();
   }
   if (t < 128) {
     const int ga = t % 16, gj = t / 16;
@@ -611,16 +834,19 @@ __device__ void tv_phase(const float* __restrict__ Bt, const float* __restrict__
         if (a < k && b < k) Vs[a * BKM + b] = (float)acc[i][u];
       }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Columns of W (Algorithm 1): update vector in the compressed space, lift and
-// clip on all rows (Q streamed in RQT-row tiles), map back with FP64 sums.
-__device__ void w_phase(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k, float* Wts,
+// clip on all rows (Q streamed in RQW-row tiles; the next tile's loads are in
+// flight while the current one is used), map back with FP64 sums.
+__device__ __noinline__ void w_phase(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k, float* Wts,
                         const float* Ts, const float* Vs, float* vec, float* ws, double* red, float* scr) {
+  constexpr int RQW = 128;  // rows per tile; RQW * BLM / BT = 32 loads per thread
   const int t = threadIdx.x;
-  float* Qs = scr;  // RQT x P1
+  float* Qs = scr;  // RQW x P1
   const int a = t & 63, g = t >> 6;
+  const int ntile = (int)((m + RQW - 1) / RQW);
   for (int j = 0; j < k; ++j) {
     const float d = Vs[j * BKM + j];
     if (!(d > 0.f)) continue;
@@ -638,15 +864,18 @@ __device__ void w_phase(const float* __restrict__ Q, float* __restrict__ W, int6
       }
       vec[t] = v;
     }
-    __syncthreads();
+    float qv[32];
+    flat_fetch<32>(qv, G(Q), (int)((m < RQW ? m : RQW) * l));
     double macc = 0.0;
-    for (int64_t r0 = 0; r0 < m; r0 += RQT) {
-      for (int e = t; e < RQT * l; e += BT) {
-        const int i = e / l, c = e - (e / l) * l;
-        Qs[i * P1 + c] = (r0 + i < m) ? Q[(r0 + i) * l + c] : 0.f;
+    for (int ti = 0; ti < ntile; ++ti) {
+      const int64_t r0 = (int64_t)ti * RQW;
+      flat_store<32>(qv, Qs, P1, l, RQW * l);
+      lds_sync();  // Qs (and, the first time, vec) visible
+      if (ti + 1 < ntile) {
+        const int64_t left = m - (r0 + RQW);
+        flat_fetch<32>(qv, G(Q + (r0 + RQW) * l), (int)((left < RQW ? left : RQW) * l));
       }
-      __syncthreads();
-      {
+      if (t < RQW) {
         float u0 = 0.f, u1 = 0.f;
         int c = 0;
         for (; c + 2 <= l; c += 2) {
@@ -656,25 +885,26 @@ __device__ void w_phase(const float* __restrict__ Q, float* __restrict__ W, int6
         for (; c < l; ++c) u0 = fmaf(Qs[t * P1 + c], vec[c], u0);
         const float w = (r0 + t < m) ? clipf(u0 + u1) : 0.f;
         ws[t] = w;
-        if (r0 + t < m) W[(r0 + t) * k + j] = w;
+        if (r0 + t < m) GW(W)[(r0 + t) * k + j] = w;
       }
-      __syncthreads();
+      lds_sync();
       if (a < l) {
         float p = 0.f;
-        for (int rr = g; rr < RQT; rr += 4) p = fmaf(Qs[rr * P1 + a], ws[rr], p);
+        for (int rr = g; rr < RQW; rr += 4) p = fmaf(Qs[rr * P1 + a], ws[rr], p);
         macc += (double)p;
       }
-      __syncthreads();
+      lds_sync();  // Qs and ws are overwritten next
     }
     red[g * BLM + a] = macc;
-    __syncthreads();
+    lds_sync();
     if (t < l) Wts[t * BKM + j] = (float)((red[t] + red[BLM + t]) + (red[2 * BLM + t] + red[3 * BLM + t]));
-    __syncthreads();
+    lds_sync();
   }
+  __syncthreads();  // W is read next by other threads of the workgroup
 }
 
 // ||X - W H||_F^2 and ||X||_F^2 (FP64 sums, fixed order) for thread 0.
-__device__ void rel_err(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, const float* __restrict__ W,
+__device__ __noinline__ void rel_err(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, const float* __restrict__ W,
                         const float* __restrict__ H, int k, float* scr, double* red, double* out) {
   const int t = threadIdx.x;
   float* Xs = scr;                      // 64 x 65
@@ -683,20 +913,16 @@ __device__ void rel_err(const float* __restrict__ X, int64_t ldx, int64_t m, int
   const int ti = t % 16, tj = t / 16;
   double e2 = 0.0, x2 = 0.0;
   for (int64_t r0 = 0; r0 < m; r0 += 64) {
-    for (int e = t; e < 64 * k; e += BT) {
-      const int i = e / k, j = e - (e / k) * k;
-      Wsh[i * (BKM + 1) + j] = (r0 + i < m) ? W[(r0 + i) * k + j] : 0.f;
-    }
+    rows_load<8>(Wsh, BKM + 1, G(W), r0, m, 64, k);
     for (int64_t c0 = 0; c0 < n; c0 += 64) {
-      for (int e = t; e < 64 * 64; e += BT) {
-        const int i = e / 64, c = e - (e / 64) * 64;
-        Xs[i * 65 + c] = (r0 + i < m && c0 + c < n) ? X[(r0 + i) * ldx + c0 + c] : 0.f;
+      {
+        float xv[16], hv[8];
+        pow2_fetch<16>(xv, G(X), ldx, r0, m, c0, n, 64, 6);
+        pow2_fetch<8>(hv, G(H), n, 0, k, c0, n, k, 6);
+        pow2_store<16>(xv, Xs, 65, 64, 6);
+        pow2_store<8>(hv, Hs, 65, k, 6);
       }
-      for (int e = t; e < k * 64; e += BT) {
-        const int j = e / 64, c = e - (e / 64) * 64;
-        Hs[j * 65 + c] = (c0 + c < n) ? H[(int64_t)j * n + c0 + c] : 0.f;
-      }
-      __syncthreads();
+      lds_sync();
       float s[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -722,27 +948,27 @@ __device__ void rel_err(const float* __restrict__ X, int64_t ldx, int64_t m, int
           e2 += d * d;
           x2 += x * x;
         }
-      __syncthreads();
+      lds_sync();
     }
   }
   red[t] = e2;
   red[BT + t] = x2;
-  __syncthreads();
+  lds_sync();
   for (int o = BT / 2; o > 0; o >>= 1) {
     if (t < o) {
       red[t] += red[t + o];
       red[BT + t] += red[BT + t + o];
     }
-    __syncthreads();
+    lds_sync();
   }
   if (t == 0) {
     out[0] = red[0];
     out[1] = red[BT];
   }
-  __syncthreads();
+  lds_sync();
 }
 
-__global__ __launch_bounds__(BT) void batch_kernel(const BDesc* __restrict__ descs, int nprob, int q, int nsweeps,
+__global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ descs, int nprob, int q, int nsweeps,
                                                    unsigned* counter, double* err, unsigned* status) {
   extern __shared__ float lds[];
   __shared__ int cur, flag;
@@ -780,14 +1006,15 @@ __global__ __launch_bounds__(BT) void batch_kernel(const BDesc* __restrict__ des
       // compression (step 9): B^T into Z for the sweeps, B for the caller
       xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, p.B, tc, scr);
       // initialisation (step 10)
-      for (int64_t e = t; e < m * k; e += BT) p.W[e] = p.W0[e];
-      for (int64_t e = t; e < (int64_t)k * n; e += BT) p.H[e] = p.H0[e];
+      for (int e = t; e < OFF_VEC; e += BT) lds[e] = 0.f;  // W~, T, V, S zero beyond k
+      copy_f(p.W, p.W0, m * k);
+      copy_f(p.H, p.H0, (int64_t)k * n);
       __syncthreads();
       init_wt(p.Q, p.W, m, l, k, Wts, scr);
       // sweeps (steps 11-22): H rows, then W columns
       for (int s = 0; s < nsweeps; ++s) {
         gram_w(p.W, m, k, Ss, scr);
-        h_phase(p.Z, p.H, n, l, k, Wts, Ss);
+        h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr);
         tv_phase(p.Z, p.H, n, l, k, Ts, Vs, scr);
         w_phase(p.Q, p.W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
       }
