@@ -208,7 +208,8 @@ def main():
     if not args.no_batch:
         batch = batch_bench(rn, torch, synth, dev)
         log(f"batch: {batch['problems']} problems in {batch['ms_per_run']:.2f} ms per run "
-            f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X)")
+            f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X); one at a time "
+            f"~{batch['one_at_a_time_ms_estimate']:.0f} ms ({batch['speedup_vs_one_at_a_time']:.1f}x)")
 
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
@@ -365,6 +366,19 @@ def batch_bench(rn, torch, synth, dev, reps=3):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     rel, status = b.results()
+    # the same problems one at a time through the single-problem path
+    # (rnmf_factorize per problem), on a seeded sample, scaled to the batch
+    pick = synth.stream(w["seed"], 98).choice(len(shapes), size=24, replace=False)
+    for i in pick[:2]:
+        X, Om, W0, H0 = probs[i]
+        rn.factorize(X, W0.shape[1], w["p"], w["q"], max_iter=w["sweeps"], omega=Om, W0=W0, H0=H0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in pick:
+        X, Om, W0, H0 = probs[i]
+        rn.factorize(X, W0.shape[1], w["p"], w["q"], max_iter=w["sweeps"], omega=Om, W0=W0, H0=H0)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t1) * 1e3 / len(pick) * len(shapes)
     xbytes = sum(m * n * 4 for m, n, k in shapes)
     passes = 2 * w["q"] + 2 + 1  # range finder and compression, plus the error pass
     out = {"problems": len(shapes), "sweeps": w["sweeps"], "q": w["q"], "p": w["p"],
@@ -374,6 +388,8 @@ def batch_bench(rn, torch, synth, dev, reps=3):
            "x_GBps": round(passes * xbytes / (ms * 1e-3) / 1e9, 1),
            "frac_of_8TBps": round(passes * xbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
            "tiling": b.tiling, "all_ok": all(x == 0 for x in status),
+           "one_at_a_time_ms_estimate": round(loop_ms, 1),
+           "speedup_vs_one_at_a_time": round(loop_ms / ms, 2),
            "rel_err_mean": float(np.mean(rel)), "rel_err_max": float(np.max(rel)),
            "arithmetic": "fp32 (FP64 Grams, Cholesky and error sums)",
            "note": "one persistent launch per run, captured in a HIP graph; per-problem range finder, "
