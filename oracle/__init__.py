@@ -15,6 +15,10 @@ algorithm of the paper written out in its own order and notation.
 Readings of passages that are silent, ambiguous or misprinted are listed in the
 module docstring of :mod:`oracle.rhals` and in the design document.
 
+:mod:`oracle.adjoint` holds the reference gradients of unrolled sweeps: a
+literal torch float64 transcription of the sweep differentiated by autograd
+(readings R21-R23), pinned by central finite differences.
+
 Parity status: every public function here is pinned by ``tests/test_oracle_pins.py``
 against facts other than its own formula (closed forms, textbook routines,
 brute-force minimisers, an independent library implementation of
