@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-hals", action="store_true", help="skip the deterministic HALS comparison")
     ap.add_argument("--no-svd-init", action="store_true", help="skip the SVD-based initialization comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (512 uneven problems)")
+    ap.add_argument("--no-backward", action="store_true", help="skip the reverse pass through unrolled sweeps")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -211,6 +212,13 @@ def main():
             f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X); one at a time "
             f"~{batch['one_at_a_time_ms_estimate']:.0f} ms ({batch['speedup_vs_one_at_a_time']:.1f}x)")
 
+    # ---- reverse pass through 20 unrolled FP32 sweeps ------------------------
+    back = None
+    if not args.no_backward:
+        back = backward_bench(rn, torch, X, Q32, W0, H0, dev)
+        log(f"backward: {back['ms_backward']:.2f} ms for {back['T']} sweeps (forward {back['ms_forward']:.2f} ms, "
+            f"{back['ratio_to_forward']:.1f}x)")
+
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -240,6 +248,7 @@ def main():
         "hals_vs_rhals": hals,
         "svd_init": svd,
         "batched": batch,
+        "backward": back,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -337,6 +346,44 @@ def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=
     return {"ms": round(ms, 4), "rel_err": info["rel_err"], "rel_err_uniform_init": reps_f[-1]["rel_err"],
             "sweeps": sweeps, "precision": "fp32",
             "note": "nonnegative double SVD of the randomized SVD Q B (FP64 Jacobi on B B^T)"}
+
+
+def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, ckpt=20, reps=3):
+    """rnmf_backward through T FP32 sweeps of this workload against one launch
+    of the same T forward sweeps; events on the current stream, mean of `reps`
+    calls after one warm-up.  With ckpt = T every state of the unrolled map is
+    kept (T + 1 states of 21 MB here), so the call recomputes the forward once;
+    the recomputation is inside the timed call."""
+    m, n = X.shape
+    k, l = H0.shape[0], Q.shape[1]
+    B = rn.compress(X, Q)
+    Wt0 = rn.compress(W0.contiguous(), Q)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1711)
+    gW = torch.randn((m, k), dtype=torch.float64, device=dev, generator=g)
+    gH = torch.randn((k, n), dtype=torch.float64, device=dev, generator=g)
+    bws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, ckpt, "fp32"), dev)
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt, ws=bws)
+    e0.record(st)
+    for _ in range(reps):
+        rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt, ws=bws)
+    e1.record(st)
+    e1.synchronize()
+    ms_b = e0.elapsed_time(e1) / reps
+    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+    rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
+    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+    e0.record(st)
+    rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
+    e1.record(st)
+    e1.synchronize()
+    ms_f = e0.elapsed_time(e1)
+    return {"T": T, "ckpt_every": ckpt, "precision": "fp32 states, fp64 adjoints", "ms_backward": round(ms_b, 3),
+            "ms_forward": round(ms_f, 3), "ratio_to_forward": round(ms_b / ms_f, 2),
+            "note": "gradients of (W_T, H_T) with respect to B, W0, H0 with Q fixed; the call recomputes "
+                    "the T forward sweeps (one launch each) and runs T reverse sweeps"}
 
 
 def batch_bench(rn, torch, synth, dev, reps=3):

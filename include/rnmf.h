@@ -242,6 +242,32 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
                           void* W, void* H, const rnmf_opts* opts, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* ---- Reverse mode through unrolled sweeps ---------------------------------
+ * Gradients through T compressed-HALS sweeps (Algorithm 1's sweep, Sec. 3.2,
+ * S = W^T W, rows of H first, plain rules) with the basis Q held fixed.  The
+ * derivative of max(0, x) is taken as 0 at 0; a block whose scale is zero is
+ * skipped, as in the forward.  Given the upstream gradients gW_T, gH_T of the
+ * sweeps' outputs (W_T, H_T), returns the gradients of
+ * <gW_T, W_T> + <gH_T, H_T> with respect to B, W0 (including the path through
+ * Wt0 = Q^T W0) and H0, and optionally gX = Q gB (the path of X through
+ * B = Q^T X).  The forward is recomputed inside with the sweep kernel, one
+ * sweep per launch, from Wt0 (as the caller's forward must run it for the
+ * gradients to describe that forward), keeping a checkpoint every ckpt_every
+ * sweeps and recomputing one segment at a time.
+ * Q (m x l), B (l x n), W0 (m x k), Wt0 (l x k), H0 (k x n): packed, in the
+ * factor dtype of opts->prec (RNMF_F64 for RNMF_PREC_F64, else RNMF_F32).
+ * gW_T (m x k), gH_T (k x n) in; gB (l x n), gW0 (m x k), gH0 (k x n) and gX
+ * (m x n, may be NULL) out; all FP64, packed, device memory.  Requires
+ * gram_mode RNMF_GRAM_FULL, order RNMF_ORDER_H_FIRST and zero regularization
+ * weights; 1 <= k <= min(64, l), l <= min(128, m); T >= 0, ckpt_every >= 1.
+ * Workspace: rnmf_backward_workspace_bytes.  Asynchronous. */
+size_t rnmf_backward_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k, int32_t T, int32_t ckpt_every,
+                                     const rnmf_opts* opts);
+rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k,
+                          const void* W0, const void* Wt0, const void* H0, int32_t T, int32_t ckpt_every,
+                          const double* gW_T, const double* gH_T, double* gB, double* gW0, double* gH0,
+                          double* gX, const rnmf_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Batched randomized HALS ------------------------------------------------
  * Many independent problems of uneven shapes (Algorithm 1 for each, with the
  * plain FP32 rules, Gram mode RNMF_GRAM_FULL and order RNMF_ORDER_H_FIRST) in

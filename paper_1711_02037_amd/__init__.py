@@ -18,7 +18,8 @@ import os
 __all__ = [
     "RnmfError", "lib", "available", "make_opts", "sketch_width", "workspace_bytes",
     "sketch", "compress", "hals_step", "rel_error", "factorize", "cast_bf16",
-    "status_string", "read_status",
+    "status_string", "read_status", "hals", "svd_init", "Batch", "backward", "backward_workspace_bytes",
+    "unrolled_forward", "rand_hals_fn",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,7 +42,7 @@ EXPORTS = [
     "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
     "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
-    "rnmf_batch_autotune",
+    "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward",
 ]
 
 
@@ -127,6 +128,11 @@ def lib():
         L.rnmf_batch_results.restype = ctypes.c_int
         L.rnmf_batch_autotune.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, sz, ctypes.POINTER(i32), vp]
         L.rnmf_batch_autotune.restype = ctypes.c_int
+        L.rnmf_backward_workspace_bytes.argtypes = [i64, i64, i32, i32, i32, i32, ctypes.POINTER(Opts)]
+        L.rnmf_backward_workspace_bytes.restype = sz
+        L.rnmf_backward.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_backward.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
         L.rnmf_cast_bf16.restype = ctypes.c_int
         L.rnmf_read_status.argtypes = [vp, sz, vp]
@@ -355,6 +361,110 @@ def svd_init(Q, B, k, ws=None):
     _check(lib().rnmf_svd_init(_ptr(Q), _ptr(B), m, n, l, int(k), _ptr(W), _ptr(H), ctypes.byref(o), _ptr(w),
                                w.numel(), _stream(Q.device)))
     return W, H
+
+
+def backward_workspace_bytes(m, n, l, k, T, ckpt_every, precision="fp32"):
+    o = make_opts(k, l - k, 0, precision=precision)
+    b = lib().rnmf_backward_workspace_bytes(int(m), int(n), int(l), int(k), int(T), int(ckpt_every),
+                                            ctypes.byref(o))
+    if b == 0:
+        raise RnmfError(ERR_ARG, lib().rnmf_last_error().decode())
+    return int(b)
+
+
+def backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=None, want_gX=False, ws=None):
+    """Gradients through T unrolled compressed sweeps with Q fixed
+    (rnmf_backward).  Q, B, W0, Wt0, H0 in the factor dtype (FP32 or FP64),
+    gW (m x k) and gH (k x n) FP64: the upstream gradients of (W_T, H_T).
+    Returns FP64 (gB, gW0, gH0, gX), gX = Q gB or None."""
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B"), (W0, "W0"), (Wt0, "Wt0"), (H0, "H0"), (gW, "gW"), (gH, "gH")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    k, n = H0.shape
+    if B.shape != (l, n) or W0.shape != (m, k) or Wt0.shape != (l, k):
+        raise ValueError("need B (l x n), W0 (m x k), Wt0 (l x k) for Q (m x l), H0 (k x n)")
+    for t, nm in ((B, "B"), (W0, "W0"), (Wt0, "Wt0"), (H0, "H0")):
+        if t.dtype != Q.dtype:
+            raise ValueError(f"{nm} must have the dtype of Q")
+    if gW.shape != (m, k) or gH.shape != (k, n) or gW.dtype != torch.float64 or gH.dtype != torch.float64:
+        raise ValueError("gW (m x k) and gH (k x n) must be float64")
+    prec = "fp64" if Q.dtype == torch.float64 else "fp32"
+    ckpt = int(ckpt_every) if ckpt_every else max(1, int(T))
+    o = make_opts(k, l - k, 0, precision=prec)
+    nb = backward_workspace_bytes(m, n, l, k, T, ckpt, prec)
+    keep, w = ws if ws is not None else _workspace(nb, Q.device)
+    dev = Q.device
+    gB = torch.empty((l, n), dtype=torch.float64, device=dev)
+    gW0 = torch.empty((m, k), dtype=torch.float64, device=dev)
+    gH0 = torch.empty((k, n), dtype=torch.float64, device=dev)
+    gX = torch.empty((m, n), dtype=torch.float64, device=dev) if want_gX else None
+    _check(lib().rnmf_backward(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W0), _ptr(Wt0), _ptr(H0), int(T), ckpt,
+                               _ptr(gW), _ptr(gH), _ptr(gB), _ptr(gW0), _ptr(gH0), _ptr(gX), ctypes.byref(o),
+                               _ptr(w), w.numel(), _stream(dev)))
+    _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(dev)))
+    return gB, gW0, gH0, gX
+
+
+def unrolled_forward(Q, B, W0, Wt0, H0, T, ws=None):
+    """(W_T, Wt_T, H_T) after T compressed sweeps from copies of (W0, Wt0, H0),
+    one sweep per launch: the states rnmf_backward recomputes."""
+    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+    for _ in range(int(T)):
+        hals_step(Q, B, W, Wt, H, nsweeps=1, ws=ws)
+    return W, Wt, H
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class RandHALS(torch.autograd.Function):
+        """(W_T, H_T) = T compressed HALS sweeps from (W0, H0) on B = Q^T X with
+        the basis Q held fixed (no gradient flows into Q).  Both passes run in
+        librnmf: the forward through rnmf_compress and rnmf_hals_step, the
+        backward through rnmf_backward (checkpoints every ckpt_every sweeps).
+        Call as RandHALS.apply(X, Q, W0, H0, T, ckpt_every)."""
+
+        @staticmethod
+        def forward(ctx, X, Q, W0, H0, T, ckpt_every=None):
+            Q = Q.contiguous()
+            prec = "fp64" if Q.dtype == torch.float64 else "fp32"
+            B = compress(X, Q, precision=prec)
+            W0c = W0.detach().to(Q.dtype).contiguous()
+            H0c = H0.detach().to(Q.dtype).contiguous()
+            Wt0 = compress(W0c, Q, precision=prec)
+            W, _, H = unrolled_forward(Q, B, W0c, Wt0, H0c, T)
+            ctx.save_for_backward(Q, B, W0c, Wt0, H0c)
+            ctx.T, ctx.ckpt = int(T), ckpt_every
+            ctx.dtypes = (X.dtype, W0.dtype, H0.dtype)
+            return W, H
+
+        @staticmethod
+        def backward(ctx, gW, gH):
+            Q, B, W0, Wt0, H0 = ctx.saved_tensors
+            m, k = W0.shape
+            n = H0.shape[1]
+            gW = (torch.zeros((m, k), dtype=torch.float64, device=Q.device) if gW is None
+                  else gW.to(torch.float64).contiguous())
+            gH = (torch.zeros((k, n), dtype=torch.float64, device=Q.device) if gH is None
+                  else gH.to(torch.float64).contiguous())
+            want_x = ctx.needs_input_grad[0]
+            gB, gW0, gH0, gX = backward(Q, B, W0, Wt0, H0, ctx.T, gW, gH, ctx.ckpt, want_gX=want_x)
+            xd, wd, hd = ctx.dtypes
+            return (gX.to(xd) if want_x else None, None, gW0.to(wd), gH0.to(hd), None, None)
+
+    return RandHALS
+
+
+_rand_hals = None
+
+
+def rand_hals_fn():
+    """The torch.autograd.Function over T unrolled sweeps (see RandHALS)."""
+    global _rand_hals
+    if _rand_hals is None:
+        _rand_hals = _make_autograd()
+    return _rand_hals
 
 
 class Batch:

@@ -554,6 +554,113 @@ rnmf_status prepare_x(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, 
   return RNMF_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Reverse mode through unrolled sweeps
+// ---------------------------------------------------------------------------
+struct State {
+  void* W;   // m x k
+  void* Wt;  // l x k
+  void* H;   // k x n
+};
+State take_state(Arena& a, int64_t m, int64_t n, int l, int k, size_t es) {
+  State st;
+  st.W = a.take<char>((size_t)m * k * es);
+  st.Wt = a.take<char>((size_t)l * k * es);
+  st.H = a.take<char>((size_t)k * n * es);
+  return st;
+}
+
+struct BackBufs {
+  SweepBufs sw;
+  std::vector<State> ckpt;  // states at the start of segments 1..nseg-1
+  std::vector<State> seg;   // the states of one segment, len + 1 of them
+  double *gWt, *gA, *gT, *gV, *gS, *Msym, *S, *Tm, *V, *part;
+  double *gpart, *hpart;  // Gram partials of W^T W and of H H^T
+  int gsplits, hsplits;
+  int nseg, len;
+};
+BackBufs plan_backward(Arena& a, int64_t m, int64_t n, int l, int k, int T, int ckpt, const Mode& md,
+                       const Dev& d) {
+  BackBufs b;
+  b.sw = plan_hals(a, m, n, l, k, md, d, false);
+  b.len = T < ckpt ? T : ckpt;
+  b.nseg = T == 0 ? 0 : (T + ckpt - 1) / ckpt;
+  for (int c = 1; c < b.nseg; ++c) b.ckpt.push_back(take_state(a, m, n, l, k, md.es));
+  for (int i = 0; i <= b.len && T > 0; ++i) b.seg.push_back(take_state(a, m, n, l, k, md.es));
+  b.gWt = a.take<double>((size_t)l * k);
+  b.gA = a.take<double>((size_t)k * n);
+  b.gT = a.take<double>((size_t)l * k);
+  b.gV = a.take<double>((size_t)k * k);
+  b.gS = a.take<double>((size_t)k * k);
+  b.Msym = a.take<double>((size_t)k * k);
+  b.S = a.take<double>((size_t)k * k);
+  b.Tm = a.take<double>((size_t)l * k);
+  b.V = a.take<double>((size_t)k * k);
+  b.part = a.take<double>((size_t)ad_wcol_parts(m) * l);
+  b.gsplits = gram_splits(m, d.cus);
+  b.gpart = a.take<double>((size_t)b.gsplits * LMAX * LMAX);
+  b.hsplits = hgram_splits(n);
+  b.hpart = a.take<double>((size_t)b.hsplits * LMAX * LMAX);
+  return b;
+}
+
+rnmf_status check_backward(int64_t m, int64_t n, int l, int k, int T, int ckpt, const rnmf_opts* o) {
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (T < 0) return fail(RNMF_ERR_ARG, "T < 0");
+  if (ckpt < 1) return fail(RNMF_ERR_ARG, "ckpt_every must be >= 1");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  if (o->gram_mode != RNMF_GRAM_FULL) return fail(RNMF_ERR_ARG, "the reverse pass needs gram_mode RNMF_GRAM_FULL");
+  if (o->order != RNMF_ORDER_H_FIRST) return fail(RNMF_ERR_ARG, "the reverse pass needs order RNMF_ORDER_H_FIRST");
+  if (o->alpha_w != 0.0 || o->alpha_h != 0.0 || o->beta_w != 0.0 || o->beta_h != 0.0)
+    return fail(RNMF_ERR_ARG, "the reverse pass covers the plain rules (zero regularization weights)");
+  return RNMF_OK;
+}
+
+hipError_t copy_state(const State& dst, const void* W, const void* Wt, const void* H, int64_t m, int64_t n, int l,
+                      int k, size_t es, hipStream_t s) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(dst.W, W, (size_t)m * k * es, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(dst.Wt, Wt, (size_t)l * k * es, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(dst.H, H, (size_t)k * n * es, hipMemcpyDeviceToDevice, s);
+}
+
+// The reverse of one sweep from (Wo, Wto, Ho) to (Wn, Wtn, Hn).  On entry gW,
+// gWt, gH hold the adjoints of the sweep's outputs; on return those of its
+// inputs, and gB has been accumulated.
+rnmf_status reverse_sweep(const void* Q, const void* B, const State& o_, const State& n_, int64_t m, int64_t n,
+                          int l, int k, double* gB, double* gW, double* gH, const BackBufs& b, int dt, hipStream_t s) {
+  const int sd = dt;  // dtype code of the states, Q and B
+  // T = B H'^T (l x k), V = H' H'^T (k x k)
+  HIPCHK(ad_gemm_sd(l, k, n, B, sd, n, 0, n_.H, sd, n, 1, b.Tm, k, 1.0, 0, s));
+  HIPCHK(launch_hgram(n_.H, k, n, b.hpart, dt, s));
+  HIPCHK(launch_gram_sum(b.hpart, b.hsplits, k, b.V, s));
+  HIPCHK(ad_fill_run(b.gT, (int64_t)l * k, 0.0, s));
+  HIPCHK(ad_fill_run(b.gV, (int64_t)k * k, 0.0, s));
+  // W columns in reverse
+  for (int j = k - 1; j >= 0; --j)
+    HIPCHK(ad_wcol(Q, n_.W, o_.Wt, n_.Wt, m, l, k, j, b.Tm, b.V, gW, b.gWt, b.gT, b.gV, b.part, dt, s));
+  // T and V to H' and B: gB += gT H', gH += gT^T B + (gV + gV^T) H'
+  HIPCHK(ad_gemm_sd(l, n, k, b.gT, 0, k, 0, n_.H, sd, n, 0, gB, n, 1.0, 1, s));
+  HIPCHK(ad_gemm_sd(k, n, l, b.gT, 0, k, 1, B, sd, n, 0, gH, n, 1.0, 1, s));
+  HIPCHK(ad_symm_run(b.gV, k, b.Msym, s));
+  HIPCHK(ad_gemm_sd(k, n, k, b.Msym, 0, k, 0, n_.H, sd, n, 0, gH, n, 1.0, 1, s));
+  // H rows in reverse with S = W^T W of the sweep's input
+  HIPCHK(launch_gram(o_.W, dt, m, k, b.gpart, b.gsplits, b.S, s));
+  HIPCHK(ad_hrows_run(n_.H, b.S, n, k, gH, b.gA, dt, s));
+  HIPCHK(ad_gs_run(n_.H, o_.H, b.gA, b.S, n, k, b.gS, dt, s));
+  HIPCHK(ad_scale_rows_run(b.gA, b.S, n, k, s));
+  // R = B^T W~: gB += W~ gA, gW~ += B gA^T; S: gW += W (gS + gS^T)
+  HIPCHK(ad_gemm_sd(l, n, k, o_.Wt, sd, k, 0, b.gA, 0, n, 0, gB, n, 1.0, 1, s));
+  HIPCHK(ad_gemm_sd(l, k, n, B, sd, n, 0, b.gA, 0, n, 1, b.gWt, k, 1.0, 1, s));
+  HIPCHK(ad_symm_run(b.gS, k, b.Msym, s));
+  HIPCHK(ad_gemm_sd(m, k, k, o_.W, sd, k, 0, b.Msym, 0, k, 0, gW, k, 1.0, 1, s));
+  return RNMF_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -755,6 +862,78 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
   HIPCHK(launch_svd_init(Q, B, m, n, l, k, W, H, md.dt, b, d.stream));
   return RNMF_OK;
 }
+
+size_t rnmf_backward_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k, int32_t T, int32_t ckpt_every,
+                                     const rnmf_opts* o) {
+  g_err.clear();
+  if (check_backward(m, n, l, k, T, ckpt_every, o) != RNMF_OK) return 0;
+  Dev d = default_dev();
+  Dev q;
+  if (get_dev(q, nullptr)) d = q;
+  Arena a(nullptr);
+  a.take<char>(HDR_BYTES);
+  plan_backward(a, m, n, l, k, T, ckpt_every, mode_of(o), d);
+  return a.used;
+}
+
+rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, const void* W0,
+                          const void* Wt0, const void* H0, int32_t T, int32_t ckpt_every, const double* gW_T,
+                          const double* gH_T, double* gB, double* gW0, double* gH0, double* gX, const rnmf_opts* o,
+                          void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rnmf_status r;
+  if ((r = check_backward(m, n, l, k, T, ckpt_every, o)) != RNMF_OK) return r;
+  if (!Q || !B || !W0 || !Wt0 || !H0 || !gW_T || !gH_T || !gB || !gW0 || !gH0)
+    return fail(RNMF_ERR_ARG, "only gX may be NULL");
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  hipStream_t s = d.stream;
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  BackBufs b = plan_backward(a, m, n, l, k, T, ckpt_every, md, d);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, s));
+  const Reg none{0.0, 0.0, 0.0, 0.0};
+  auto sweep = [&](const State& st) {
+    return launch_sweep(b.sw.sh, md.dt, Q, B, st.W, st.Wt, st.H, m, n, l, k, 1, 0.0, RNMF_GRAM_FULL,
+                        RNMF_ORDER_H_FIRST, none, b.sw.xbuf, h.stats, h.status, nullptr, s);
+  };
+  // adjoint accumulators: gW0 and gH0 carry gW and gH through the sweeps
+  if (gW0 != gW_T) HIPCHK(hipMemcpyAsync(gW0, gW_T, (size_t)m * k * 8, hipMemcpyDeviceToDevice, s));
+  if (gH0 != gH_T) HIPCHK(hipMemcpyAsync(gH0, gH_T, (size_t)k * n * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(ad_fill_run(b.gWt, (int64_t)l * k, 0.0, s));
+  HIPCHK(ad_fill_run(gB, (int64_t)l * n, 0.0, s));
+  // forward: the state at the start of every segment after the first, each
+  // from the one before by one-sweep launches
+  for (int c = 1; c < b.nseg; ++c) {
+    const State& dst = b.ckpt[c - 1];
+    if (c == 1) HIPCHK(copy_state(dst, W0, Wt0, H0, m, n, l, k, md.es, s));
+    else HIPCHK(copy_state(dst, b.ckpt[c - 2].W, b.ckpt[c - 2].Wt, b.ckpt[c - 2].H, m, n, l, k, md.es, s));
+    for (int i = 0; i < ckpt_every; ++i) HIPCHK(sweep(dst));
+  }
+  // reverse, segment by segment: recompute the segment's states, then undo
+  // its sweeps last to first
+  for (int c = b.nseg - 1; c >= 0; --c) {
+    const int t0 = c * ckpt_every;
+    const int len = (T - t0) < ckpt_every ? (T - t0) : ckpt_every;
+    if (c == 0) HIPCHK(copy_state(b.seg[0], W0, Wt0, H0, m, n, l, k, md.es, s));
+    else HIPCHK(copy_state(b.seg[0], b.ckpt[c - 1].W, b.ckpt[c - 1].Wt, b.ckpt[c - 1].H, m, n, l, k, md.es, s));
+    for (int i = 1; i <= len; ++i) {
+      HIPCHK(copy_state(b.seg[i], b.seg[i - 1].W, b.seg[i - 1].Wt, b.seg[i - 1].H, m, n, l, k, md.es, s));
+      HIPCHK(sweep(b.seg[i]));
+    }
+    for (int i = len - 1; i >= 0; --i)
+      if ((r = reverse_sweep(Q, B, b.seg[i], b.seg[i + 1], m, n, l, k, gB, gW0, gH0, b, md.dt, s)) != RNMF_OK)
+        return r;
+  }
+  // W~0 = Q^T W0: gW0 += Q gW~0; X enters through B = Q^T X: gX = Q gB
+  HIPCHK(ad_gemm_sd(m, k, l, Q, md.dt, l, 0, b.gWt, 0, k, 0, gW0, k, 1.0, 1, s));
+  if (gX) HIPCHK(ad_gemm_sd(m, n, l, Q, md.dt, l, 0, gB, 0, n, 0, gX, n, 1.0, 0, s));
+  return RNMF_OK;
+}
+
 
 size_t rnmf_batch_workspace_bytes(int32_t nprob) {
   g_err.clear();

@@ -119,6 +119,22 @@ hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void
 int hgram_splits(int64_t n);
 hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, hipStream_t s);
 
+// Reverse mode through unrolled sweeps (adjoint.hip).  dt: 0 = double
+// states, 1 = float states; adjoints are FP64.
+hipError_t ad_gemm_sd(int64_t M, int64_t N, int64_t K, const void* A, int adt, int64_t lda, int ta, const void* B,
+                      int bdt, int64_t ldb, int tb, double* C, int64_t ldc, double alpha, int acc, hipStream_t s);
+hipError_t ad_wcol(const void* Q, const void* Wn, const void* Wto, const void* Wtn, int64_t m, int l, int k, int j,
+                   const double* Tm, const double* V, double* gW, double* gWt, double* gT, double* gV, double* part,
+                   int dt, hipStream_t s);
+int ad_wcol_parts(int64_t m);
+hipError_t ad_hrows_run(const void* Hn, const double* S, int64_t n, int k, double* gH, double* gA, int dt,
+                        hipStream_t s);
+hipError_t ad_gs_run(const void* Hn, const void* Ho, const double* gA, const double* S, int64_t n, int k,
+                     double* gS, int dt, hipStream_t s);
+hipError_t ad_scale_rows_run(double* gA, const double* S, int64_t n, int k, hipStream_t s);
+hipError_t ad_symm_run(const double* G, int k, double* M, hipStream_t s);
+hipError_t ad_fill_run(double* p, int64_t count, double v, hipStream_t s);
+
 // SVD-based initialization (svdinit.hip).  Workspace pieces, all FP64:
 // gpart (hgram_splits(n) x LMAX x LMAX), C (l x l), Ub (l x k), sv (k),
 // upart (svd_row_blocks(m) x k x 2), vpart (svd_col_blocks(n) x k x 2),

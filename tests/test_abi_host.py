@@ -228,3 +228,33 @@ def test_batch_problem_layout_and_validation():
     assert L.rnmf_batch_run(4, 33, 10, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
     assert L.rnmf_batch_run(4, 2, -1, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
     assert L.rnmf_batch_run(4, 2, 10, ctypes.c_void_p(256), 16, None) == rn.ERR_WORKSPACE
+
+
+def test_backward_validation():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    o = rn.make_opts(8, 8, 0, precision="fp64")
+    n1 = rn.backward_workspace_bytes(3000, 500, 16, 8, 10, 10, "fp64")
+    n2 = rn.backward_workspace_bytes(3000, 500, 16, 8, 10, 3, "fp64")
+    n3 = rn.backward_workspace_bytes(3000, 500, 16, 8, 10, 3, "fp32")
+    assert n1 > n2 > n3 > 0     # more states per segment; FP32 states are half the size
+    assert rn.backward_workspace_bytes(3000, 500, 16, 8, 0, 1, "fp64") > 0
+    qb = lambda T=10, c=3, l=16, k=8, m=3000, oo=o: L.rnmf_backward_workspace_bytes(m, 500, l, k, T, c,
+                                                                                   ctypes.byref(oo))
+    assert qb(T=-1) == 0 and qb(c=0) == 0 and qb(k=0) == 0 and qb(k=65, l=100) == 0
+    assert qb(l=7) == 0 and qb(l=129) == 0 and qb(m=10) == 0
+
+    def call(T=10, c=3, gX=None, gW=p, oo=o, l=16, ws_bytes=1 << 40):
+        return L.rnmf_backward(p, p, 3000, 500, l, 8, p, p, p, T, c, gW, p, p, p, p, gX, ctypes.byref(oo), p,
+                               ws_bytes, None)
+    assert call(T=-1) == rn.ERR_ARG
+    assert call(c=0) == rn.ERR_ARG
+    assert call(gW=None) == rn.ERR_ARG
+    assert call(l=4) == rn.ERR_SHAPE
+    for field, value in (("gram_mode", 1), ("order", 1), ("alpha_h", 0.5), ("beta_w", 0.1)):
+        bad = rn.make_opts(8, 8, 0, precision="fp64")
+        setattr(bad, field, value)
+        assert call(oo=bad) == rn.ERR_ARG, field
+        assert qb(oo=bad) == 0, field
+    # arguments check out: the missing device is reported, not a crash
+    assert call(gX=p) == rn.ERR_HIP
