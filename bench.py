@@ -216,8 +216,9 @@ def main():
     back = None
     if not args.no_backward:
         back = backward_bench(rn, torch, X, Q32, W0, H0, dev)
-        log(f"backward: {back['ms_backward']:.2f} ms for {back['T']} sweeps (forward {back['ms_forward']:.2f} ms, "
-            f"{back['ratio_to_forward']:.1f}x)")
+        log(f"backward: {back['ms_backward']:.2f} ms for {back['T']} sweeps from recorded states "
+            f"(recording forward {back['ms_forward_recorded']:.2f} ms, one-launch forward {back['ms_forward']:.2f} ms, "
+            f"recomputing backward {back['ms_backward_recompute']:.2f} ms)")
 
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
@@ -348,12 +349,13 @@ def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=
             "note": "nonnegative double SVD of the randomized SVD Q B (FP64 Jacobi on B B^T)"}
 
 
-def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, ckpt=20, reps=3):
-    """rnmf_backward through T FP32 sweeps of this workload against one launch
-    of the same T forward sweeps; events on the current stream, mean of `reps`
-    calls after one warm-up.  With ckpt = T every state of the unrolled map is
-    kept (T + 1 states of 21 MB here), so the call recomputes the forward once;
-    the recomputation is inside the timed call."""
+def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, reps=3):
+    """Reverse pass through T FP32 sweeps of this workload: rnmf_unroll with
+    every state recorded (T one-sweep launches, 21 MB per state here) and
+    rnmf_backward reading that record, against one launch of the same T
+    forward sweeps; also rnmf_backward recomputing the forward itself
+    (ckpt_every = T).  Events on the current stream, mean of `reps` calls
+    after one warm-up."""
     m, n = X.shape
     k, l = H0.shape[0], Q.shape[1]
     B = rn.compress(X, Q)
@@ -362,28 +364,44 @@ def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, ckpt=20, reps=3):
     g.manual_seed(1711)
     gW = torch.randn((m, k), dtype=torch.float64, device=dev, generator=g)
     gH = torch.randn((k, n), dtype=torch.float64, device=dev, generator=g)
-    bws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, ckpt, "fp32"), dev)
     st = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt, ws=bws)
-    e0.record(st)
-    for _ in range(reps):
-        rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt, ws=bws)
-    e1.record(st)
-    e1.synchronize()
-    ms_b = e0.elapsed_time(e1) / reps
+
+    def timed(fn):
+        fn()
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    uws = rn._workspace(rn.workspace_bytes(rn.OP_HALS_STEP, m, n, rn.make_opts(k, l - k, 0)), dev)
     W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
-    rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
-    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
-    e0.record(st)
-    rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
-    e1.record(st)
-    e1.synchronize()
-    ms_f = e0.elapsed_time(e1)
-    return {"T": T, "ckpt_every": ckpt, "precision": "fp32 states, fp64 adjoints", "ms_backward": round(ms_b, 3),
-            "ms_forward": round(ms_f, 3), "ratio_to_forward": round(ms_b / ms_f, 2),
-            "note": "gradients of (W_T, H_T) with respect to B, W0, H0 with Q fixed; the call recomputes "
-                    "the T forward sweeps (one launch each) and runs T reverse sweeps"}
+    states = rn.unroll(Q, B, W, Wt, H, T, ws=uws)
+
+    def fwd_rec():
+        W.copy_(W0); Wt.copy_(Wt0); H.copy_(H0)
+        rn.unroll(Q, B, W, Wt, H, T, ws=uws)
+
+    ms_fr = timed(fwd_rec)
+    bws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, 0, "fp32"), dev)
+    ms_b = timed(lambda: rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, states=states, ws=bws))
+    cws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, T, "fp32"), dev)
+    ms_bc = timed(lambda: rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=T, ws=cws))
+
+    def fwd_one():
+        W.copy_(W0); Wt.copy_(Wt0); H.copy_(H0)
+        rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
+
+    ms_f = timed(fwd_one)
+    return {"T": T, "precision": "fp32 states, fp64 adjoints", "ms_backward": round(ms_b, 3),
+            "ms_forward_recorded": round(ms_fr, 3), "ms_backward_recompute": round(ms_bc, 3),
+            "ms_forward": round(ms_f, 3), "ratio_to_forward": round((ms_fr + ms_b) / ms_f, 2),
+            "note": "gradients of (W_T, H_T) with respect to B, W0, H0 with Q fixed. ms_backward reads the "
+                    "states that rnmf_unroll recorded (ms_forward_recorded: T one-sweep launches plus the "
+                    "copies); ms_backward_recompute reruns those T launches itself; ms_forward is one launch "
+                    "of T sweeps; the ratio is (recorded forward + backward) / ms_forward"}
 
 
 def batch_bench(rn, torch, synth, dev, reps=3):

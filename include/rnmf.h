@@ -243,30 +243,49 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
                           void* stream);
 
 /* ---- Reverse mode through unrolled sweeps ---------------------------------
- * Gradients through T compressed-HALS sweeps (Algorithm 1's sweep, Sec. 3.2,
+ * T sweeps, one launch each, with every state recorded: the forward that
+ * rnmf_backward differentiates without recomputation.  Runs T sweeps of
+ * Algorithm 1's sweep (Sec. 3.2) on W, Wt, H in place, exactly as T calls of
+ * rnmf_hals_step with nsweeps = 1 (one launch of T sweeps carries sums across
+ * sweeps and matches this to rounding only).  If states is not NULL, the
+ * state after sweep i (i = 0..T-1) is written at
+ *   states + i * (m*k + l*k + k*n) * es,  es = 8 (RNMF_PREC_F64) or 4,
+ * as W (m x k), then Wt (l x k), then H (k x n), packed.  Arguments as for
+ * rnmf_hals_step; workspace: RNMF_OP_HALS_STEP.  Asynchronous. */
+rnmf_status rnmf_unroll(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W, void* Wt,
+                        void* H, int32_t T, void* states, const rnmf_opts* opts, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Gradients through T compressed-HALS sweeps (Algorithm 1's sweep, Sec. 3.2,
  * S = W^T W, rows of H first, plain rules) with the basis Q held fixed.  The
  * derivative of max(0, x) is taken as 0 at 0; a block whose scale is zero is
  * skipped, as in the forward.  Given the upstream gradients gW_T, gH_T of the
  * sweeps' outputs (W_T, H_T), returns the gradients of
  * <gW_T, W_T> + <gH_T, H_T> with respect to B, W0 (including the path through
  * Wt0 = Q^T W0) and H0, and optionally gX = Q gB (the path of X through
- * B = Q^T X).  The forward is recomputed inside with the sweep kernel, one
- * sweep per launch, from Wt0 (as the caller's forward must run it for the
- * gradients to describe that forward), keeping a checkpoint every ckpt_every
- * sweeps and recomputing one segment at a time.
+ * B = Q^T X).
+ * The states of the forward come either from rnmf_unroll's record (states
+ * not NULL, ckpt_every = 0: nothing is recomputed) or are recomputed inside
+ * the call (states NULL, ckpt_every >= 1): the sweep kernel runs one sweep
+ * per launch from Wt0, a checkpoint is kept every ckpt_every sweeps, and one
+ * segment is recomputed at a time.  Either way the gradients describe the
+ * one-sweep-per-launch forward of rnmf_unroll.
  * Q (m x l), B (l x n), W0 (m x k), Wt0 (l x k), H0 (k x n): packed, in the
  * factor dtype of opts->prec (RNMF_F64 for RNMF_PREC_F64, else RNMF_F32).
  * gW_T (m x k), gH_T (k x n) in; gB (l x n), gW0 (m x k), gH0 (k x n) and gX
- * (m x n, may be NULL) out; all FP64, packed, device memory.  Requires
- * gram_mode RNMF_GRAM_FULL, order RNMF_ORDER_H_FIRST and zero regularization
- * weights; 1 <= k <= min(64, l), l <= min(128, m); T >= 0, ckpt_every >= 1.
- * Workspace: rnmf_backward_workspace_bytes.  Asynchronous. */
+ * (m x n, may be NULL) out; all FP64, packed, device memory.  gW0 may be
+ * gW_T and gH0 may be gH_T (updated in place).  Requires gram_mode
+ * RNMF_GRAM_FULL, order RNMF_ORDER_H_FIRST and zero regularization weights;
+ * 1 <= k <= min(64, l), l <= min(128, m); T >= 0.
+ * Workspace: rnmf_backward_workspace_bytes with the same ckpt_every.  A
+ * device-wide wait that passes its spin limit sets RNMF_ERR_DEVICE_TIMEOUT in
+ * the status word (rnmf_read_status).  Asynchronous. */
 size_t rnmf_backward_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k, int32_t T, int32_t ckpt_every,
                                      const rnmf_opts* opts);
 rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k,
                           const void* W0, const void* Wt0, const void* H0, int32_t T, int32_t ckpt_every,
-                          const double* gW_T, const double* gH_T, double* gB, double* gW0, double* gH0,
-                          double* gX, const rnmf_opts* opts, void* ws, size_t ws_bytes, void* stream);
+                          const void* states, const double* gW_T, const double* gH_T, double* gB, double* gW0,
+                          double* gH0, double* gX, const rnmf_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Batched randomized HALS ------------------------------------------------
  * Many independent problems of uneven shapes (Algorithm 1 for each, with the

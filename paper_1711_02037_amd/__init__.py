@@ -19,7 +19,7 @@ __all__ = [
     "RnmfError", "lib", "available", "make_opts", "sketch_width", "workspace_bytes",
     "sketch", "compress", "hals_step", "rel_error", "factorize", "cast_bf16",
     "status_string", "read_status", "hals", "svd_init", "Batch", "backward", "backward_workspace_bytes",
-    "unrolled_forward", "rand_hals_fn",
+    "unrolled_forward", "unroll", "rand_hals_fn",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,7 +42,7 @@ EXPORTS = [
     "rnmf_sketch_width", "rnmf_sketch", "rnmf_compress", "rnmf_hals_step", "rnmf_rel_error",
     "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
-    "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward",
+    "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
 ]
 
 
@@ -130,8 +130,10 @@ def lib():
         L.rnmf_batch_autotune.restype = ctypes.c_int
         L.rnmf_backward_workspace_bytes.argtypes = [i64, i64, i32, i32, i32, i32, ctypes.POINTER(Opts)]
         L.rnmf_backward_workspace_bytes.restype = sz
-        L.rnmf_backward.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp,
+        L.rnmf_backward.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_unroll.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, vp, ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_unroll.restype = ctypes.c_int
         L.rnmf_backward.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
         L.rnmf_cast_bf16.restype = ctypes.c_int
@@ -372,11 +374,14 @@ def backward_workspace_bytes(m, n, l, k, T, ckpt_every, precision="fp32"):
     return int(b)
 
 
-def backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=None, want_gX=False, ws=None):
+def backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=None, states=None, want_gX=False, ws=None):
     """Gradients through T unrolled compressed sweeps with Q fixed
     (rnmf_backward).  Q, B, W0, Wt0, H0 in the factor dtype (FP32 or FP64),
     gW (m x k) and gH (k x n) FP64: the upstream gradients of (W_T, H_T).
-    Returns FP64 (gB, gW0, gH0, gX), gX = Q gB or None."""
+    With `states` (the record of unroll) nothing is recomputed; otherwise the
+    forward is recomputed from checkpoints every `ckpt_every` sweeps (default
+    T: all states of one pass kept).  Returns FP64 (gB, gW0, gH0, gX), gX =
+    Q gB or None."""
     torch = _torch()
     for t, nm in ((Q, "Q"), (B, "B"), (W0, "W0"), (Wt0, "Wt0"), (H0, "H0"), (gW, "gW"), (gH, "gH")):
         _need_dev(t, nm); _packed(t, nm)
@@ -389,8 +394,14 @@ def backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=None, want_gX=False, ws=No
             raise ValueError(f"{nm} must have the dtype of Q")
     if gW.shape != (m, k) or gH.shape != (k, n) or gW.dtype != torch.float64 or gH.dtype != torch.float64:
         raise ValueError("gW (m x k) and gH (k x n) must be float64")
+    if states is not None:
+        _need_dev(states, "states"); _packed(states, "states")
+        if states.dtype != Q.dtype or states.numel() < int(T) * (m * k + l * k + k * n):
+            raise ValueError("states must hold T recorded states in the dtype of Q")
+        ckpt = 0
+    else:
+        ckpt = int(ckpt_every) if ckpt_every else max(1, int(T))
     prec = "fp64" if Q.dtype == torch.float64 else "fp32"
-    ckpt = int(ckpt_every) if ckpt_every else max(1, int(T))
     o = make_opts(k, l - k, 0, precision=prec)
     nb = backward_workspace_bytes(m, n, l, k, T, ckpt, prec)
     keep, w = ws if ws is not None else _workspace(nb, Q.device)
@@ -400,18 +411,43 @@ def backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=None, want_gX=False, ws=No
     gH0 = torch.empty((k, n), dtype=torch.float64, device=dev)
     gX = torch.empty((m, n), dtype=torch.float64, device=dev) if want_gX else None
     _check(lib().rnmf_backward(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W0), _ptr(Wt0), _ptr(H0), int(T), ckpt,
-                               _ptr(gW), _ptr(gH), _ptr(gB), _ptr(gW0), _ptr(gH0), _ptr(gX), ctypes.byref(o),
-                               _ptr(w), w.numel(), _stream(dev)))
+                               _ptr(states), _ptr(gW), _ptr(gH), _ptr(gB), _ptr(gW0), _ptr(gH0), _ptr(gX),
+                               ctypes.byref(o), _ptr(w), w.numel(), _stream(dev)))
     _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(dev)))
     return gB, gW0, gH0, gX
 
 
+def state_elems(m, n, l, k):
+    """Elements of one recorded state: W (m x k), Wt (l x k), H (k x n)."""
+    return m * k + l * k + k * n
+
+
+def unroll(Q, B, W, Wt, H, T, record=True, ws=None):
+    """T sweeps, one launch each, in place on W, Wt, H (rnmf_unroll).  With
+    `record`, returns the T states after each sweep in one flat tensor of the
+    factor dtype (the layout rnmf_backward reads), else None."""
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B"), (W, "W"), (Wt, "Wt"), (H, "H")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    k, n = H.shape
+    prec = "fp64" if Q.dtype == torch.float64 else "fp32"
+    o = make_opts(k, l - k, 0, precision=prec)
+    nb = workspace_bytes(OP_HALS_STEP, m, n, o)
+    keep, w = ws if ws is not None else _workspace(nb, Q.device)
+    states = (torch.empty(max(1, int(T)) * state_elems(m, n, l, k), dtype=Q.dtype, device=Q.device)
+              if record else None)
+    _check(lib().rnmf_unroll(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W), _ptr(Wt), _ptr(H), int(T), _ptr(states),
+                             ctypes.byref(o), _ptr(w), w.numel(), _stream(Q.device)))
+    _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(Q.device)))
+    return states
+
+
 def unrolled_forward(Q, B, W0, Wt0, H0, T, ws=None):
     """(W_T, Wt_T, H_T) after T compressed sweeps from copies of (W0, Wt0, H0),
-    one sweep per launch: the states rnmf_backward recomputes."""
+    one sweep per launch: the states rnmf_backward reads or recomputes."""
     W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
-    for _ in range(int(T)):
-        hals_step(Q, B, W, Wt, H, nsweeps=1, ws=ws)
+    unroll(Q, B, W, Wt, H, T, record=False, ws=ws)
     return W, Wt, H
 
 
@@ -421,9 +457,12 @@ def _make_autograd():
     class RandHALS(torch.autograd.Function):
         """(W_T, H_T) = T compressed HALS sweeps from (W0, H0) on B = Q^T X with
         the basis Q held fixed (no gradient flows into Q).  Both passes run in
-        librnmf: the forward through rnmf_compress and rnmf_hals_step, the
-        backward through rnmf_backward (checkpoints every ckpt_every sweeps).
-        Call as RandHALS.apply(X, Q, W0, H0, T, ckpt_every)."""
+        librnmf: the forward through rnmf_compress and rnmf_unroll, the
+        backward through rnmf_backward.
+        Call as RandHALS.apply(X, Q, W0, H0, T, ckpt_every): with ckpt_every
+        None the forward records all T states (rnmf_unroll) and the backward
+        reads them; with a number it records nothing and the backward
+        recomputes from checkpoints."""
 
         @staticmethod
         def forward(ctx, X, Q, W0, H0, T, ckpt_every=None):
@@ -433,15 +472,18 @@ def _make_autograd():
             W0c = W0.detach().to(Q.dtype).contiguous()
             H0c = H0.detach().to(Q.dtype).contiguous()
             Wt0 = compress(W0c, Q, precision=prec)
-            W, _, H = unrolled_forward(Q, B, W0c, Wt0, H0c, T)
-            ctx.save_for_backward(Q, B, W0c, Wt0, H0c)
+            W, Wt, H = W0c.clone(), Wt0.clone(), H0c.clone()
+            # without ckpt_every every state is recorded and the backward
+            # recomputes nothing; with it, nothing is recorded
+            states = unroll(Q, B, W, Wt, H, T, record=ckpt_every is None)
+            ctx.save_for_backward(Q, B, W0c, Wt0, H0c, states)
             ctx.T, ctx.ckpt = int(T), ckpt_every
             ctx.dtypes = (X.dtype, W0.dtype, H0.dtype)
             return W, H
 
         @staticmethod
         def backward(ctx, gW, gH):
-            Q, B, W0, Wt0, H0 = ctx.saved_tensors
+            Q, B, W0, Wt0, H0, states = ctx.saved_tensors
             m, k = W0.shape
             n = H0.shape[1]
             gW = (torch.zeros((m, k), dtype=torch.float64, device=Q.device) if gW is None
@@ -449,7 +491,7 @@ def _make_autograd():
             gH = (torch.zeros((k, n), dtype=torch.float64, device=Q.device) if gH is None
                   else gH.to(torch.float64).contiguous())
             want_x = ctx.needs_input_grad[0]
-            gB, gW0, gH0, gX = backward(Q, B, W0, Wt0, H0, ctx.T, gW, gH, ctx.ckpt, want_gX=want_x)
+            gB, gW0, gH0, gX = backward(Q, B, W0, Wt0, H0, ctx.T, gW, gH, ctx.ckpt, states=states, want_gX=want_x)
             xd, wd, hd = ctx.dtypes
             return (gX.to(xd) if want_x else None, None, gW0.to(wd), gH0.to(hd), None, None)
 

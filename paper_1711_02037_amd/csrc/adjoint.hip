@@ -70,111 +70,290 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// W column j in reverse, part 1 (rows r of a 256-row block):
-//   g = gW(r, j) + Q(r, :) gWt(:, j);  gz = g if W'(r, j) > 0 else 0;
-//   gW(r, j) <- 0 (the old column has no derivative here);
-//   part(blk, a) = sum over the block's rows of Q(r, a) gz(r).  For the
-//   partial the workgroup splits into 256 / l groups of l threads; thread a
-//   of group g adds rows g, g + groups, ... (reads of a row are contiguous
-//   across the group), then the groups' sums are added in order.
-template <typename T>
-__global__ __launch_bounds__(256) void ad_wcol_a(const T* __restrict__ Q, const T* __restrict__ Wn, int64_t m,
-                                                 int l, int k, int j, const double* __restrict__ V,
-                                                 double* __restrict__ gW, const double* __restrict__ gWt,
-                                                 double* __restrict__ part) {
-  if (!(V[j * k + j] > 0.0)) return;  // skipped in the forward: adjoints pass through
-  __shared__ double gwt[LMAX];
-  __shared__ double gz[256];
-  __shared__ double red[256];
-  const int t = threadIdx.x;
-  for (int a = t; a < l; a += 256) gwt[a] = gWt[(int64_t)a * k + j];
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * 256;
-  const int64_t r = r0 + t;
-  double z = 0.0;
-  if (r < m) {
-    const T* q = Q + r * l;
-    double g = gW[r * k + j];
-    for (int a = 0; a < l; ++a) g = fma((double)q[a], gwt[a], g);
-    z = ((double)Wn[r * k + j] > 0.0) ? g : 0.0;
-    gW[r * k + j] = 0.0;
-  }
-  gz[t] = z;
-  __syncthreads();
-  const int groups = 256 / l;
-  const int grp = t / l, a = t - (t / l) * l;
-  const int rows = (int)((m - r0) < 256 ? (m - r0) : 256);
-  double s = 0.0;
-  if (grp < groups) {
-    const T* q = Q + r0 * l + a;
-#pragma unroll 8
-    for (int i = grp; i < rows; i += groups) s = fma((double)q[(int64_t)i * l], gz[i], s);
-  }
-  red[t] = s;
-  __syncthreads();
-  for (int e = t; e < l; e += 256) {
-    double v = 0.0;
-    for (int g2 = 0; g2 < groups; ++g2) v += red[g2 * l + e];
-    part[(int64_t)blockIdx.x * l + e] = v;
-  }
+// ---- W columns in reverse: one persistent, cooperative launch per sweep ----
+//
+// The k column steps form a chain: step j needs gWt(:, j) after the updates of
+// the steps j' > j.  Per step, with the W column's adjoint g = gW(:, j) +
+// Q gWt(:, j) masked by W'(:, j) > 0:
+//   gu = Q^T (masked g)                               (a sum over the m rows)
+//   gWt(:, p) -= V_pj / V_jj gu  (p != j),  gWt(:, j) <- 0,  gW(:, j) <- 0.
+// Workgroup g owns a slab of rows of Q and W and a replicated copy of gWt and V
+// in LDS.  The l-vector gu is all-reduced in two levels over a GR x GC grid of
+// workgroups: workgroup (i, c) adds the slab partials of its row i (GC
+// sources), publishes that row sum, and adds the row sums of the workgroups
+// (0..GR-1, c).  Every sum runs in a fixed order, so every workgroup holds the
+// same gu to the last bit.  Exchange words are 64 bits, a 32-bit half of a
+// double and the 32-bit epoch of the step, written and read with agent-scope
+// relaxed atomics: each word carries its own readiness.  Slots alternate
+// between two buffers by the parity of the step: a workgroup can run at most
+// one step ahead of a reader of its slot, because its next-but-one partial
+// needs that reader's next partial.  gu of every step goes to GU(:, j); the
+// adjoints of T and V follow from GU in ad_wpost.  Every wait is bounded:
+// past the spin limit the workgroup records ST_TIMEOUT and leaves the chain.
+constexpr int WR_NT = 512;
+constexpr long WR_SPIN = 1L << 22;
+
+__device__ __forceinline__ u64 xld(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xst(u64* p, unsigned payload, unsigned e) {
+  __hip_atomic_store(p, ((u64)e << 32) | (u64)payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish(u64* slot, int a, double v, unsigned e) {
+  const u64 b = (u64)__double_as_longlong(v);
+  xst(slot + 2 * a, (unsigned)b, e);
+  xst(slot + 2 * a + 1, (unsigned)(b >> 32), e);
 }
 
-// W column j in reverse, part 2 (one workgroup of 16 wavefronts):
-// gu = sum of the parts (wavefront w adds blocks w, w + 16, ..., then the 16
-// sums in order); the update vector u_j; then gT(:, j) += gu / V_jj,
-// gWt(:, p) -= V_pj / V_jj gu (p != j), gV(p, j) -= Wtc_p . gu / V_jj,
-// gV(j, j) -= u . gu / V_jj, and gWt(:, j) <- 0.
-// Wtc_p = Wt'(:, p) for p < j, Wt(:, p) for p > j.
-template <typename T>
-__global__ __launch_bounds__(1024) void ad_wcol_b(const T* __restrict__ Wto, const T* __restrict__ Wtn,
-                                                  const double* __restrict__ Tm, const double* __restrict__ V,
-                                                  int l, int k, int j, const double* __restrict__ part, int nblk,
-                                                  double* __restrict__ gT, double* __restrict__ gWt,
-                                                  double* __restrict__ gV) {
-  const double d = V[j * k + j];
-  if (!(d > 0.0)) return;
-  __shared__ double sred[16][LMAX];
-  __shared__ double gu[LMAX], u[LMAX], vj[KMAX];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (int a = lane; a < l; a += 64) {
-    double s = 0.0;
-    for (int b = wv; b < nblk; b += 16) s += part[(int64_t)b * l + a];
-    sred[wv][a] = s;
-  }
-  if (t < k) vj[t] = V[t * k + j];
-  __syncthreads();
-  if (t < l) {
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += sred[w][t];
-    gu[t] = s;
-  }
-  // u(a) = (T(a, j) - sum_{p != j} V_pj Wtc(a, p)) / V_jj: one wavefront per a, lanes over p
-  for (int a = wv; a < l; a += 16) {
-    double v = 0.0;
-    if (lane < k && lane != j)
-      v = vj[lane] * (lane < j ? (double)Wtn[a * k + lane] : (double)Wto[a * k + lane]);
-    v = wave_sum(v);
-    if (lane == 0) u[a] = (Tm[a * k + j] - v) / d;
-  }
-  __syncthreads();
-  for (int e = t; e < l * k; e += 1024) {
-    const int a = e / k, p = e - (e / k) * k;
-    if (p == j) {
-      gT[a * k + j] += gu[a] / d;
-      gWt[e] = 0.0;
-    } else {
-      gWt[e] -= vj[p] / d * gu[a];
+// Sum, in source order, of element a over nsrc slots (slot s at base + s *
+// stride), waiting for epoch e.  Sixteen sources are loaded together and
+// only their stale words are polled again.
+__device__ double gather(const u64* base, size_t stride, int nsrc, int a, unsigned e, bool& ok) {
+  constexpr int WIN = 16;
+  double sum = 0.0;
+  for (int s0 = 0; s0 < nsrc; s0 += WIN) {
+    const int cnt = (nsrc - s0) < WIN ? (nsrc - s0) : WIN;
+    u64 w[WIN][2];
+#pragma unroll
+    for (int q = 0; q < WIN; ++q)
+      if (q < cnt) {
+        w[q][0] = xld(base + (size_t)(s0 + q) * stride + 2 * a);
+        w[q][1] = xld(base + (size_t)(s0 + q) * stride + 2 * a + 1);
+      }
+    long spins = 0;
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int q = 0; q < WIN; ++q)
+        if (q < cnt) all = all && (unsigned)(w[q][0] >> 32) == e && (unsigned)(w[q][1] >> 32) == e;
+      if (all) break;
+      if (!ok || ++spins > WR_SPIN) { ok = false; break; }
+#pragma unroll
+      for (int q = 0; q < WIN; ++q)
+        if (q < cnt) {
+          if ((unsigned)(w[q][0] >> 32) != e) w[q][0] = xld(base + (size_t)(s0 + q) * stride + 2 * a);
+          if ((unsigned)(w[q][1] >> 32) != e) w[q][1] = xld(base + (size_t)(s0 + q) * stride + 2 * a + 1);
+        }
     }
+#pragma unroll
+    for (int q = 0; q < WIN; ++q)
+      if (q < cnt) sum += __longlong_as_double((long long)(((u64)(unsigned)w[q][1] << 32) | (u64)(unsigned)w[q][0]));
   }
-  // gV(p, j): one wavefront per p, lanes over a
-  for (int p = wv; p < k; p += 16) {
+  return sum;
+}
+
+// Workgroup barrier for LDS data only: waits for this wavefront's LDS
+// operations but not for its outstanding global stores and exchange words,
+// which __syncthreads() would drain.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = 63, expcnt = 7, lgkmcnt = 0
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// q . w over l entries with four partial sums, added pairwise.
+template <typename T>
+__device__ __forceinline__ double row_dot(const T* q, const double* w, int l) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int a = 0;
+  for (; a + 4 <= l; a += 4) {
+    s0 = fma((double)q[a], w[a], s0);
+    s1 = fma((double)q[a + 1], w[a + 1], s1);
+    s2 = fma((double)q[a + 2], w[a + 2], s2);
+    s3 = fma((double)q[a + 3], w[a + 3], s3);
+  }
+  for (; a < l; ++a) s0 = fma((double)q[a], w[a], s0);
+  return (s0 + s1) + (s2 + s3);
+}
+
+// sum over rows i = first, first + step, ... < count of q[i * ld] z[i], with
+// two partial sums (rows taken alternately), added at the end.
+template <typename T>
+__device__ __forceinline__ double col_dot(const T* q, int64_t ld, const double* z, int first, int count, int step) {
+  double s0 = 0.0, s1 = 0.0;
+  int i = first;
+#pragma unroll 2
+  for (; i + step < count; i += 2 * step) {
+    s0 = fma((double)q[(int64_t)i * ld], z[i], s0);
+    s1 = fma((double)q[(int64_t)(i + step) * ld], z[i + step], s1);
+  }
+  if (i < count) s0 = fma((double)q[(int64_t)i * ld], z[i], s0);
+  return s0 + s1;
+}
+
+template <typename T>
+struct WrevArgs {
+  const T* Q; const T* Wn; const double* V;
+  double* gW; double* gWt; double* GU;
+  int64_t m; int l, k;
+  int G, GR, GC; int64_t rows_per;
+  u64* part; u64* rows;  // exchange slots: [2][G][2 * LMAX] words each
+  unsigned* status;
+};
+
+// RES: the workgroup's slab of Q stays in LDS for the whole launch (row
+// stride l | 1, odd, so that a wavefront reading one entry per row hits
+// distinct banks); otherwise the slab is read from global memory at every
+// step, WR_NT rows at a time.  Dot products keep four partial sums (two in
+// the transposed product) so that their loads overlap.
+template <typename T, bool RES>
+__global__ __launch_bounds__(WR_NT) void ad_wrev_kernel(WrevArgs<T> A) {
+  extern __shared__ double lds[];
+  const int l = A.l, k = A.k, t = threadIdx.x, g = blockIdx.x;
+  const int lq = l | 1;
+  const int64_t r0 = (int64_t)g * A.rows_per;
+  const int64_t r1 = (r0 + A.rows_per) < A.m ? (r0 + A.rows_per) : A.m;
+  const int nrows = r1 > r0 ? (int)(r1 - r0) : 0;
+  const int zn = RES ? (int)A.rows_per : WR_NT;
+  double* sgwt = lds;               // l x k
+  double* gu = sgwt + l * k;        // LMAX
+  double* vj = gu + LMAX;           // KMAX: V(:, j) / V_jj
+  double* wj = vj + KMAX;           // LMAX: gWt(:, j)
+  double* red = wj + LMAX;          // WR_NT
+  double* zs = red + WR_NT;         // zn
+  T* tile = (T*)(zs + zn);          // RES: nrows x lq
+  __shared__ int sok;
+  for (int e = t; e < l * k; e += WR_NT) sgwt[e] = A.gWt[e];
+  if (RES)
+    for (int64_t e = t; e < (int64_t)nrows * l; e += WR_NT) {
+      const int i = (int)(e / l), a = (int)(e - (e / l) * l);
+      tile[i * lq + a] = A.Q[(r0 + i) * l + a];
+    }
+  if (t == 0) sok = 1;
+  // one slab row per thread: the next step's gW and W' entries are loaded
+  // ahead, while the exchange of the current step is in flight
+  const bool one = RES && nrows <= WR_NT;
+  const bool own = one && t < nrows;
+  const int64_t rt = r0 + t;
+  int pj = k - 1;
+  double pg = own ? A.gW[rt * k + pj] : 0.0;
+  T pw = own ? A.Wn[rt * k + pj] : (T)0;
+  // the update of gWt: thread t takes column up = t % k of rows ua, ua + ur, ...
+  const int ur = WR_NT / k, ua0 = t / k, up = t - (t / k) * k;
+  __syncthreads();
+  const int gi = g / A.GC, gc = g - (g / A.GC) * A.GC;
+  const int groups = WR_NT / l, grp = t / l, ta = t - (t / l) * l;
+  const size_t slotw = 2 * LMAX;
+  bool ok = true;
+  unsigned step = 0;
+  for (int j = k - 1; j >= 0; --j) {
+    const double d = A.V[j * k + j];
+    if (!(d > 0.0)) continue;  // skipped in the forward: adjoints pass through
+    const unsigned e = ++step;
+    const int par = (int)(e & 1u);
+    if (t < k) vj[t] = A.V[t * k + j] / d;
+    if (t < l) wj[t] = sgwt[t * k + j];
+    lds_barrier();
+    // slab partial of Q^T (masked g)
+    double s = 0.0;
+    if (one) {
+      if (own) {
+        if (pj != j) {
+          pg = A.gW[rt * k + j];
+          pw = A.Wn[rt * k + j];
+        }
+        const double gg = pg + row_dot(tile + t * lq, wj, l);
+        zs[t] = ((double)pw > 0.0) ? gg : 0.0;
+        A.gW[rt * k + j] = 0.0;
+        if (j > 0) {
+          pj = j - 1;
+          pg = A.gW[rt * k + pj];
+          pw = A.Wn[rt * k + pj];
+        }
+      }
+      lds_barrier();
+      if (grp < groups) s = col_dot(tile + ta, (int64_t)lq, zs, grp, nrows, groups);
+    } else if (RES) {
+      for (int i = t; i < nrows; i += WR_NT) {
+        const int64_t r = r0 + i;
+        const double gg = A.gW[r * k + j] + row_dot(tile + i * lq, wj, l);
+        zs[i] = ((double)A.Wn[r * k + j] > 0.0) ? gg : 0.0;
+        A.gW[r * k + j] = 0.0;
+      }
+      lds_barrier();
+      if (grp < groups) s = col_dot(tile + ta, (int64_t)lq, zs, grp, nrows, groups);
+    } else {
+      for (int64_t c0 = r0; c0 < r1; c0 += WR_NT) {
+        const int64_t r = c0 + t;
+        double z = 0.0;
+        if (r < r1) {
+          const double gg = A.gW[r * k + j] + row_dot(A.Q + r * l, wj, l);
+          z = ((double)A.Wn[r * k + j] > 0.0) ? gg : 0.0;
+          A.gW[r * k + j] = 0.0;
+        }
+        zs[t] = z;
+        lds_barrier();
+        const int cnt = (int)((r1 - c0) < WR_NT ? (r1 - c0) : WR_NT);
+        if (grp < groups) s += col_dot(A.Q + c0 * l + ta, (int64_t)l, zs, grp, cnt, groups);
+        lds_barrier();
+      }
+    }
+    red[t] = s;
+    lds_barrier();
+    if (t < l) {
+      double v = 0.0;
+      for (int g2 = 0; g2 < groups; ++g2) v += red[g2 * l + t];
+      publish(A.part + ((size_t)par * A.G + g) * slotw, t, v, e);
+      const double rs = gather(A.part + ((size_t)par * A.G + (size_t)gi * A.GC) * slotw, slotw, A.GC, t, e, ok);
+      publish(A.rows + ((size_t)par * A.G + g) * slotw, t, rs, e);
+      gu[t] = gather(A.rows + ((size_t)par * A.G + gc) * slotw, (size_t)A.GC * slotw, A.GR, t, e, ok);
+      if (!ok) sok = 0;
+    }
+    lds_barrier();
+    if (!sok) break;
+    if (g == 0 && t < l) A.GU[t * k + j] = gu[t];
+    if (ua0 < ur) {
+      const double f = vj[up];
+      for (int a = ua0; a < l; a += ur) {
+        if (up == j) sgwt[a * k + up] = 0.0;
+        else sgwt[a * k + up] -= f * gu[a];
+      }
+    }
+    lds_barrier();
+  }
+  if (!sok) {
+    if (t == 0) atomicOr(A.status, ST_TIMEOUT);
+    return;
+  }
+  if (g == 0)
+    for (int e2 = t; e2 < l * k; e2 += WR_NT) A.gWt[e2] = sgwt[e2];
+}
+
+// Adjoints of T and V from the steps' gu (one workgroup per column j):
+// gT(:, j) = gu_j / V_jj;  gV(p, j) = -Wtc_p . gu_j / V_jj (p != j) and
+// gV(j, j) = -u_j . gu_j / V_jj, with the update vector
+// u_j = (T(:, j) - sum_{p != j} V_pj Wtc_p) / V_jj and Wtc_p = Wt'(:, p) for
+// p < j, Wt(:, p) for p > j.  All zero for a skipped column.
+template <typename T>
+__global__ __launch_bounds__(256) void ad_wpost(const T* __restrict__ Wto, const T* __restrict__ Wtn,
+                                                const double* __restrict__ Tm, const double* __restrict__ V,
+                                                const double* __restrict__ GU, int l, int k, double* __restrict__ gT,
+                                                double* __restrict__ gV) {
+  const int j = blockIdx.x, t = threadIdx.x;
+  const double d = V[j * k + j];
+  __shared__ double gu[LMAX], u[LMAX];
+  if (!(d > 0.0)) {
+    if (t < l) gT[t * k + j] = 0.0;
+    if (t < k) gV[t * k + j] = 0.0;
+    return;
+  }
+  if (t < l) {
+    gu[t] = GU[t * k + j];
+    double num = Tm[t * k + j];
+    for (int p = 0; p < k; ++p)
+      if (p != j) num -= V[p * k + j] * (p < j ? (double)Wtn[t * k + p] : (double)Wto[t * k + p]);
+    u[t] = num / d;
+    gT[t * k + j] = gu[t] / d;
+  }
+  __syncthreads();
+  if (t < k) {
     double v = 0.0;
-    for (int a = lane; a < l; a += 64) {
-      const double w = (p == j) ? u[a] : (p < j ? (double)Wtn[a * k + p] : (double)Wto[a * k + p]);
+    for (int a = 0; a < l; ++a) {
+      const double w = (t == j) ? u[a] : (t < j ? (double)Wtn[a * k + t] : (double)Wto[a * k + t]);
       v = fma(w, gu[a], v);
     }
-    v = wave_sum(v);
-    if (lane == 0) gV[p * k + j] -= v / d;
+    gV[t * k + j] = -v / d;
   }
 }
 
@@ -314,25 +493,59 @@ hipError_t ad_gemm_sd(int64_t M, int64_t N, int64_t K, const void* A, int adt, i
   return gemm_t(M, N, K, (const float*)A, lda, ta, (const float*)B, ldb, tb, C, ldc, alpha, acc, s);
 }
 
-hipError_t ad_wcol(const void* Q, const void* Wn, const void* Wto, const void* Wtn, int64_t m, int l, int k, int j,
-                   const double* Tm, const double* V, double* gW, double* gWt, double* gT, double* gV, double* part,
-                   int dt, hipStream_t s) {
-  const int nblk = (int)((m + 255) / 256);
-  if (dt == 0) {
-    hipLaunchKernelGGL(ad_wcol_a<double>, dim3(nblk), dim3(256), 0, s, (const double*)Q, (const double*)Wn, m, l, k,
-                       j, V, gW, gWt, part);
-    hipLaunchKernelGGL(ad_wcol_b<double>, dim3(1), dim3(1024), 0, s, (const double*)Wto, (const double*)Wtn, Tm, V, l,
-                       k, j, part, nblk, gT, gWt, gV);
-  } else {
-    hipLaunchKernelGGL(ad_wcol_a<float>, dim3(nblk), dim3(256), 0, s, (const float*)Q, (const float*)Wn, m, l, k, j,
-                       V, gW, gWt, part);
-    hipLaunchKernelGGL(ad_wcol_b<float>, dim3(1), dim3(1024), 0, s, (const float*)Wto, (const float*)Wtn, Tm, V, l, k,
-                       j, part, nblk, gT, gWt, gV);
-  }
-  return hipGetLastError();
+WrevShape plan_wrev(int64_t m, int l, int k, int dt, int cus, int max_lds) {
+  WrevShape sh;
+  int64_t target = (m + 63) / 64;
+  if (target > cus) target = cus;
+  if (target < 1) target = 1;
+  sh.GC = target < 16 ? (int)target : 16;
+  sh.GR = (int)(target / sh.GC);
+  sh.G = sh.GR * sh.GC;
+  sh.rows_per = (m + sh.G - 1) / sh.G;
+  const size_t fixed = ((size_t)l * k + 2 * LMAX + KMAX + WR_NT) * sizeof(double);
+  const size_t res = fixed + (size_t)sh.rows_per * sizeof(double) +
+                     (size_t)sh.rows_per * (size_t)(l | 1) * (dt == 0 ? 8 : 4);
+  sh.res = res + 256 <= (size_t)max_lds;  // 256 bytes left for the static flag
+  sh.lds_bytes = sh.res ? res : fixed + (size_t)WR_NT * sizeof(double);
+  return sh;
 }
 
-int ad_wcol_parts(int64_t m) { return (int)((m + 255) / 256); }
+size_t wrev_ws_words(const WrevShape& sh) { return (size_t)2 * 2 * sh.G * 2 * LMAX; }
+
+hipError_t ad_wrev(const WrevShape& sh, const void* Q, const void* Wn, const double* V, int64_t m, int l, int k,
+                   double* gW, double* gWt, double* GU, u64* xbuf, unsigned* status, int dt, hipStream_t s) {
+  if (l < 1 || l > LMAX || k < 1 || k > KMAX) return hipErrorInvalidValue;
+  const size_t words = wrev_ws_words(sh);
+  hipError_t e = launch_fill_u32((unsigned*)xbuf, words * 2, 0u, s);
+  if (e != hipSuccess) return e;
+  u64* part = xbuf;
+  u64* rows = xbuf + words / 2;
+#define WREV(TT)                                                                                       \
+  {                                                                                                    \
+    WrevArgs<TT> a;                                                                                    \
+    a.Q = (const TT*)Q; a.Wn = (const TT*)Wn; a.V = V; a.gW = gW; a.gWt = gWt; a.GU = GU;              \
+    a.m = m; a.l = l; a.k = k; a.G = sh.G; a.GR = sh.GR; a.GC = sh.GC; a.rows_per = sh.rows_per;      \
+    a.part = part; a.rows = rows; a.status = status;                                                   \
+    void* args[] = {&a};                                                                               \
+    const void* fn = sh.res ? (const void*)ad_wrev_kernel<TT, true> : (const void*)ad_wrev_kernel<TT, false>; \
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);        \
+    if (e != hipSuccess) return e;                                                                     \
+    return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(WR_NT), args, (unsigned)sh.lds_bytes, s);   \
+  }
+  if (dt == 0) WREV(double) else WREV(float)
+#undef WREV
+}
+
+hipError_t ad_wpost_run(const void* Wto, const void* Wtn, const double* Tm, const double* V, const double* GU,
+                        int l, int k, double* gT, double* gV, int dt, hipStream_t s) {
+  if (dt == 0)
+    hipLaunchKernelGGL(ad_wpost<double>, dim3(k), dim3(256), 0, s, (const double*)Wto, (const double*)Wtn, Tm, V,
+                       GU, l, k, gT, gV);
+  else
+    hipLaunchKernelGGL(ad_wpost<float>, dim3(k), dim3(256), 0, s, (const float*)Wto, (const float*)Wtn, Tm, V, GU,
+                       l, k, gT, gV);
+  return hipGetLastError();
+}
 
 template <typename T>
 static hipError_t hrows_t(const T* Hn, const double* S, int64_t n, int k, double* gH, double* gA, hipStream_t s) {

@@ -575,8 +575,10 @@ struct BackBufs {
   SweepBufs sw;
   std::vector<State> ckpt;  // states at the start of segments 1..nseg-1
   std::vector<State> seg;   // the states of one segment, len + 1 of them
-  double *gWt, *gA, *gT, *gV, *gS, *Msym, *S, *Tm, *V, *part;
+  double *gWt, *gA, *gT, *gV, *gS, *Msym, *S, *Tm, *V, *GU;
   double *gpart, *hpart;  // Gram partials of W^T W and of H H^T
+  WrevShape wsh;          // the persistent reverse W phase
+  u64* wx;                // its exchange slots
   int gsplits, hsplits;
   int nseg, len;
 };
@@ -584,8 +586,9 @@ BackBufs plan_backward(Arena& a, int64_t m, int64_t n, int l, int k, int T, int 
                        const Dev& d) {
   BackBufs b;
   b.sw = plan_hals(a, m, n, l, k, md, d, false);
-  b.len = T < ckpt ? T : ckpt;
-  b.nseg = T == 0 ? 0 : (T + ckpt - 1) / ckpt;
+  // ckpt == 0: the caller recorded every state; nothing is recomputed
+  b.len = ckpt == 0 ? 0 : (T < ckpt ? T : ckpt);
+  b.nseg = (T == 0 || ckpt == 0) ? 0 : (T + ckpt - 1) / ckpt;
   for (int c = 1; c < b.nseg; ++c) b.ckpt.push_back(take_state(a, m, n, l, k, md.es));
   for (int i = 0; i <= b.len && T > 0; ++i) b.seg.push_back(take_state(a, m, n, l, k, md.es));
   b.gWt = a.take<double>((size_t)l * k);
@@ -597,7 +600,9 @@ BackBufs plan_backward(Arena& a, int64_t m, int64_t n, int l, int k, int T, int 
   b.S = a.take<double>((size_t)k * k);
   b.Tm = a.take<double>((size_t)l * k);
   b.V = a.take<double>((size_t)k * k);
-  b.part = a.take<double>((size_t)ad_wcol_parts(m) * l);
+  b.GU = a.take<double>((size_t)l * k);
+  b.wsh = plan_wrev(m, l, k, md.dt, d.cus, d.max_lds);
+  b.wx = a.take<u64>(wrev_ws_words(b.wsh));
   b.gsplits = gram_splits(m, d.cus);
   b.gpart = a.take<double>((size_t)b.gsplits * LMAX * LMAX);
   b.hsplits = hgram_splits(n);
@@ -611,7 +616,7 @@ rnmf_status check_backward(int64_t m, int64_t n, int l, int k, int T, int ckpt, 
   if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
   if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
   if (T < 0) return fail(RNMF_ERR_ARG, "T < 0");
-  if (ckpt < 1) return fail(RNMF_ERR_ARG, "ckpt_every must be >= 1");
+  if (ckpt < 0) return fail(RNMF_ERR_ARG, "ckpt_every must be >= 0");
   if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
   if (o->gram_mode != RNMF_GRAM_FULL) return fail(RNMF_ERR_ARG, "the reverse pass needs gram_mode RNMF_GRAM_FULL");
   if (o->order != RNMF_ORDER_H_FIRST) return fail(RNMF_ERR_ARG, "the reverse pass needs order RNMF_ORDER_H_FIRST");
@@ -632,17 +637,16 @@ hipError_t copy_state(const State& dst, const void* W, const void* Wt, const voi
 // gWt, gH hold the adjoints of the sweep's outputs; on return those of its
 // inputs, and gB has been accumulated.
 rnmf_status reverse_sweep(const void* Q, const void* B, const State& o_, const State& n_, int64_t m, int64_t n,
-                          int l, int k, double* gB, double* gW, double* gH, const BackBufs& b, int dt, hipStream_t s) {
+                          int l, int k, double* gB, double* gW, double* gH, const BackBufs& b, unsigned* status,
+                          int dt, hipStream_t s) {
   const int sd = dt;  // dtype code of the states, Q and B
   // T = B H'^T (l x k), V = H' H'^T (k x k)
   HIPCHK(ad_gemm_sd(l, k, n, B, sd, n, 0, n_.H, sd, n, 1, b.Tm, k, 1.0, 0, s));
   HIPCHK(launch_hgram(n_.H, k, n, b.hpart, dt, s));
   HIPCHK(launch_gram_sum(b.hpart, b.hsplits, k, b.V, s));
-  HIPCHK(ad_fill_run(b.gT, (int64_t)l * k, 0.0, s));
-  HIPCHK(ad_fill_run(b.gV, (int64_t)k * k, 0.0, s));
-  // W columns in reverse
-  for (int j = k - 1; j >= 0; --j)
-    HIPCHK(ad_wcol(Q, n_.W, o_.Wt, n_.Wt, m, l, k, j, b.Tm, b.V, gW, b.gWt, b.gT, b.gV, b.part, dt, s));
+  // W columns in reverse (one persistent launch), then the T and V adjoints
+  HIPCHK(ad_wrev(b.wsh, Q, n_.W, b.V, m, l, k, gW, b.gWt, b.GU, b.wx, status, dt, s));
+  HIPCHK(ad_wpost_run(o_.Wt, n_.Wt, b.Tm, b.V, b.GU, l, k, b.gT, b.gV, dt, s));
   // T and V to H' and B: gB += gT H', gH += gT^T B + (gV + gV^T) H'
   HIPCHK(ad_gemm_sd(l, n, k, b.gT, 0, k, 0, n_.H, sd, n, 0, gB, n, 1.0, 1, s));
   HIPCHK(ad_gemm_sd(k, n, l, b.gT, 0, k, 1, B, sd, n, 0, gH, n, 1.0, 1, s));
@@ -842,6 +846,43 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   return RNMF_OK;
 }
 
+rnmf_status rnmf_unroll(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W, void* Wt,
+                        void* H, int32_t T, void* states, const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!Q || !B || !W || !Wt || !H) return fail(RNMF_ERR_ARG, "Q, B, W, Wt and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (T < 0) return fail(RNMF_ERR_ARG, "T < 0");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode");
+  if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
+  if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  rnmf_status r;
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  SweepBufs b = plan_hals(a, m, n, l, k, md, d, false);
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
+  const size_t wsz = (size_t)m * k * md.es, wtsz = (size_t)l * k * md.es, hsz = (size_t)k * n * md.es;
+  for (int i = 0; i < T; ++i) {
+    HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, 1, 0.0, o->gram_mode, o->order, reg_of(o), b.xbuf,
+                        h.stats, h.status, nullptr, d.stream));
+    if (states) {
+      char* p = (char*)states + (size_t)i * (wsz + wtsz + hsz);
+      HIPCHK(hipMemcpyAsync(p, W, wsz, hipMemcpyDeviceToDevice, d.stream));
+      HIPCHK(hipMemcpyAsync(p + wsz, Wt, wtsz, hipMemcpyDeviceToDevice, d.stream));
+      HIPCHK(hipMemcpyAsync(p + wsz + wtsz, H, hsz, hipMemcpyDeviceToDevice, d.stream));
+    }
+  }
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
                           void* H, const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -877,14 +918,16 @@ size_t rnmf_backward_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k,
 }
 
 rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, const void* W0,
-                          const void* Wt0, const void* H0, int32_t T, int32_t ckpt_every, const double* gW_T,
-                          const double* gH_T, double* gB, double* gW0, double* gH0, double* gX, const rnmf_opts* o,
-                          void* ws, size_t ws_bytes, void* stream) {
+                          const void* Wt0, const void* H0, int32_t T, int32_t ckpt_every, const void* states,
+                          const double* gW_T, const double* gH_T, double* gB, double* gW0, double* gH0, double* gX,
+                          const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   rnmf_status r;
   if ((r = check_backward(m, n, l, k, T, ckpt_every, o)) != RNMF_OK) return r;
   if (!Q || !B || !W0 || !Wt0 || !H0 || !gW_T || !gH_T || !gB || !gW0 || !gH0)
-    return fail(RNMF_ERR_ARG, "only gX may be NULL");
+    return fail(RNMF_ERR_ARG, "only gX (and states, with ckpt_every >= 1) may be NULL");
+  if ((ckpt_every == 0) != (states != nullptr))
+    return fail(RNMF_ERR_ARG, "recorded states go with ckpt_every = 0, and ckpt_every = 0 needs them");
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
   const Mode md = mode_of(o);
@@ -913,6 +956,20 @@ rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, in
     else HIPCHK(copy_state(dst, b.ckpt[c - 2].W, b.ckpt[c - 2].Wt, b.ckpt[c - 2].H, m, n, l, k, md.es, s));
     for (int i = 0; i < ckpt_every; ++i) HIPCHK(sweep(dst));
   }
+  // recorded states: sweep i maps state i - 1 (the inputs for i = 0) to state i
+  if (states) {
+    const size_t wsz = (size_t)m * k * md.es, wtsz = (size_t)l * k * md.es, hsz = (size_t)k * n * md.es;
+    char* base = (char*)states;
+    auto rec = [&](int i) {
+      char* p = base + (size_t)i * (wsz + wtsz + hsz);
+      return State{p, p + wsz, p + wsz + wtsz};
+    };
+    const State in{(void*)W0, (void*)Wt0, (void*)H0};
+    for (int i = T - 1; i >= 0; --i)
+      if ((r = reverse_sweep(Q, B, i == 0 ? in : rec(i - 1), rec(i), m, n, l, k, gB, gW0, gH0, b, h.status, md.dt,
+                             s)) != RNMF_OK)
+        return r;
+  }
   // reverse, segment by segment: recompute the segment's states, then undo
   // its sweeps last to first
   for (int c = b.nseg - 1; c >= 0; --c) {
@@ -925,7 +982,8 @@ rnmf_status rnmf_backward(const void* Q, const void* B, int64_t m, int64_t n, in
       HIPCHK(sweep(b.seg[i]));
     }
     for (int i = len - 1; i >= 0; --i)
-      if ((r = reverse_sweep(Q, B, b.seg[i], b.seg[i + 1], m, n, l, k, gB, gW0, gH0, b, md.dt, s)) != RNMF_OK)
+      if ((r = reverse_sweep(Q, B, b.seg[i], b.seg[i + 1], m, n, l, k, gB, gW0, gH0, b, h.status, md.dt, s)) !=
+          RNMF_OK)
         return r;
   }
   // W~0 = Q^T W0: gW0 += Q gW~0; X enters through B = Q^T X: gX = Q gB

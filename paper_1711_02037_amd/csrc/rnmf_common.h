@@ -123,10 +123,18 @@ hipError_t launch_hgram(const void* H, int k, int64_t n, double* part, int dt, h
 // states, 1 = float states; adjoints are FP64.
 hipError_t ad_gemm_sd(int64_t M, int64_t N, int64_t K, const void* A, int adt, int64_t lda, int ta, const void* B,
                       int bdt, int64_t ldb, int tb, double* C, int64_t ldc, double alpha, int acc, hipStream_t s);
-hipError_t ad_wcol(const void* Q, const void* Wn, const void* Wto, const void* Wtn, int64_t m, int l, int k, int j,
-                   const double* Tm, const double* V, double* gW, double* gWt, double* gT, double* gV, double* part,
-                   int dt, hipStream_t s);
-int ad_wcol_parts(int64_t m);
+struct WrevShape {
+  int G, GR, GC;
+  int64_t rows_per;
+  bool res;  // the Q slab stays in LDS
+  size_t lds_bytes;
+};
+WrevShape plan_wrev(int64_t m, int l, int k, int dt, int cus, int max_lds);
+size_t wrev_ws_words(const WrevShape& sh);
+hipError_t ad_wrev(const WrevShape& sh, const void* Q, const void* Wn, const double* V, int64_t m, int l, int k,
+                   double* gW, double* gWt, double* GU, u64* xbuf, unsigned* status, int dt, hipStream_t s);
+hipError_t ad_wpost_run(const void* Wto, const void* Wtn, const double* Tm, const double* V, const double* GU,
+                        int l, int k, double* gT, double* gV, int dt, hipStream_t s);
 hipError_t ad_hrows_run(const void* Hn, const double* S, int64_t n, int k, double* gH, double* gA, int dt,
                         hipStream_t s);
 hipError_t ad_gs_run(const void* Hn, const void* Ho, const double* gA, const double* S, int64_t n, int k,

@@ -241,14 +241,19 @@ def test_backward_validation():
     assert rn.backward_workspace_bytes(3000, 500, 16, 8, 0, 1, "fp64") > 0
     qb = lambda T=10, c=3, l=16, k=8, m=3000, oo=o: L.rnmf_backward_workspace_bytes(m, 500, l, k, T, c,
                                                                                    ctypes.byref(oo))
-    assert qb(T=-1) == 0 and qb(c=0) == 0 and qb(k=0) == 0 and qb(k=65, l=100) == 0
+    assert qb(T=-1) == 0 and qb(c=-1) == 0 and qb(k=0) == 0 and qb(k=65, l=100) == 0
     assert qb(l=7) == 0 and qb(l=129) == 0 and qb(m=10) == 0
 
-    def call(T=10, c=3, gX=None, gW=p, oo=o, l=16, ws_bytes=1 << 40):
-        return L.rnmf_backward(p, p, 3000, 500, l, 8, p, p, p, T, c, gW, p, p, p, p, gX, ctypes.byref(oo), p,
+    def call(T=10, c=3, gX=None, gW=p, oo=o, l=16, ws_bytes=1 << 40, st=None):
+        return L.rnmf_backward(p, p, 3000, 500, l, 8, p, p, p, T, c, st, gW, p, p, p, p, gX, ctypes.byref(oo), p,
                                ws_bytes, None)
     assert call(T=-1) == rn.ERR_ARG
-    assert call(c=0) == rn.ERR_ARG
+    assert call(c=-1) == rn.ERR_ARG
+    assert call(c=0) == rn.ERR_ARG              # ckpt_every = 0 needs recorded states
+    assert call(c=3, st=p) == rn.ERR_ARG        # recorded states go with ckpt_every = 0
+    assert call(c=0, st=p) == rn.ERR_HIP        # consistent: the missing device is reported
+    # recorded states: no checkpoint or segment buffers
+    assert rn.backward_workspace_bytes(3000, 500, 16, 8, 10, 0, "fp64") < n2
     assert call(gW=None) == rn.ERR_ARG
     assert call(l=4) == rn.ERR_SHAPE
     for field, value in (("gram_mode", 1), ("order", 1), ("alpha_h", 0.5), ("beta_w", 0.1)):
@@ -258,3 +263,16 @@ def test_backward_validation():
         assert qb(oo=bad) == 0, field
     # arguments check out: the missing device is reported, not a crash
     assert call(gX=p) == rn.ERR_HIP
+
+
+def test_unroll_validation():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    o = rn.make_opts(8, 8, 0)
+    call = lambda T=5, l=16, W=p, oo=o: L.rnmf_unroll(p, p, 3000, 500, l, 8, W, p, p, T, None, ctypes.byref(oo), p,
+                                                       1 << 40, None)
+    assert call(T=-1) == rn.ERR_ARG
+    assert call(W=None) == rn.ERR_ARG
+    assert call(l=7) == rn.ERR_SHAPE
+    assert call() == rn.ERR_HIP
+    assert rn.state_elems(3000, 500, 16, 8) == 3000 * 8 + 16 * 8 + 8 * 500

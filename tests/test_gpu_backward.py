@@ -83,7 +83,8 @@ def run_device(X, Q, W0, H0, gW, gH, T, ckpt, dt):
 CASES64 = [(300, 200, 6, 12, 7, 3, 601),     # two 256-row blocks of W, ragged; 3 segments, last one short
            (1000, 513, 16, 30, 5, 5, 602),   # one segment; n one past a 256-column block
            (257, 700, 40, 64, 4, 1, 603),    # k above 32 (the 64-row H reverse), one sweep per segment
-           (90, 60, 1, 1, 3, 2, 604)]        # k = l = 1
+           (90, 60, 1, 1, 3, 2, 604),        # k = l = 1
+           (51200, 300, 8, 128, 3, 2, 605)]  # 200 rows x 128 FP64 per workgroup: Q slab streamed, not in LDS
 
 
 @pytest.mark.parametrize("m,n,k,l,T,ckpt,seed", CASES64)
@@ -121,6 +122,26 @@ def test_checkpoint_spacing_does_not_change_the_gradients():
             assert np.array_equal(a, b)
 
 
+def test_recorded_states_give_the_recomputed_gradients():
+    """rnmf_unroll's record and the recomputation inside rnmf_backward run
+    the same one-sweep launches on the same inputs: identical gradients."""
+    m, n, k, l, T, seed = 500, 350, 9, 18, 6, 625
+    X, Q, W0, H0, gW, gH = problem(m, n, k, l, seed)
+    for dt in (np.float64, np.float32):
+        Qd, B = dev(Q, dt), dev(Q.T @ X, dt)
+        W0d, Wt0, H0d = dev(W0, dt), dev(Q.T @ W0, dt), dev(H0, dt)
+        W, Wt, H = W0d.clone(), Wt0.clone(), H0d.clone()
+        states = rn.unroll(Qd, B, W, Wt, H, T)
+        st = rn.state_elems(m, n, l, k)
+        last = states[(T - 1) * st:T * st]
+        assert torch.equal(last[:m * k], W.flatten()) and torch.equal(last[m * k + l * k:], H.flatten())
+        a = rn.backward(Qd, B, W0d, Wt0, H0d, T, dev(gW), dev(gH), states=states, want_gX=True)
+        b = rn.backward(Qd, B, W0d, Wt0, H0d, T, dev(gW), dev(gH), ckpt_every=4, want_gX=True)
+        torch.cuda.synchronize()
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+
+
 def test_zero_sweeps_pass_the_upstream_gradients_through():
     m, n, k, l, seed = 200, 150, 5, 10, 631
     X, Q, W0, H0, gW, gH = problem(m, n, k, l, seed)
@@ -148,10 +169,12 @@ def test_unrolled_forward_matches_multi_sweep_launch():
         assert max(errs) <= bar, errs
 
 
-def test_autograd_function_matches_reference_loss_gradients():
+@pytest.mark.parametrize("ckpt", [None, 2])
+def test_autograd_function_matches_reference_loss_gradients(ckpt):
     """Loss ||X - W H||^2 + sum(H) (reading R23) through RandHALS: the loss
-    itself is ordinary torch, the sweeps and their reverse are librnmf's."""
-    m, n, k, l, T, ckpt, seed = 500, 300, 10, 20, 5, 2, 651
+    itself is ordinary torch, the sweeps and their reverse are librnmf's
+    (recorded states, or checkpoints every 2 sweeps)."""
+    m, n, k, l, T, seed = 500, 300, 10, 20, 5, 651
     X, Q, W0, H0, _, _ = problem(m, n, k, l, seed)
     rX, rW0, rH0, rL, _, _ = A.grads(Q, X, W0, H0, T)
     Fn = rn.rand_hals_fn()
