@@ -142,6 +142,28 @@ __device__ double gather(const u64* base, size_t stride, int nsrc, int a, unsign
   return sum;
 }
 
+// Workgroup-wide staging st(e, ld(e)) for e in [0, count): each thread takes
+// eight elements per round and issues all their loads before any store, so
+// the loads' latencies overlap (a plain loop waits for each load in turn).
+// Loads past the end read the last element (always in bounds) and are not
+// stored.
+template <int NT, typename Load, typename Store>
+__device__ __forceinline__ void stage(int count, Load ld_, Store st_) {
+  for (int e0 = threadIdx.x; e0 < count; e0 += NT * 8) {
+    decltype(ld_(0)) v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      v[u] = ld_(e < count ? e : count - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      if (e < count) st_(e, v[u]);
+    }
+  }
+}
+
 // Workgroup barrier for LDS data only: waits for this wavefront's LDS
 // operations but not for its outstanding global stores and exchange words,
 // which __syncthreads() would drain.
@@ -214,12 +236,14 @@ __global__ __launch_bounds__(WR_NT) void ad_wrev_kernel(WrevArgs<T> A) {
   double* zs = red + WR_NT;         // zn
   T* tile = (T*)(zs + zn);          // RES: nrows x lq
   __shared__ int sok;
-  for (int e = t; e < l * k; e += WR_NT) sgwt[e] = A.gWt[e];
+  stage<WR_NT>(l * k, [&](int e) { return A.gWt[e]; }, [&](int e, double v) { sgwt[e] = v; });
+  const T* qsl = A.Q + r0 * l;
   if (RES)
-    for (int64_t e = t; e < (int64_t)nrows * l; e += WR_NT) {
-      const int i = (int)(e / l), a = (int)(e - (e / l) * l);
-      tile[i * lq + a] = A.Q[(r0 + i) * l + a];
-    }
+    stage<WR_NT>(nrows * l, [&](int e) { return qsl[e]; },
+                 [&](int e, T v) {
+                   const int i = e / l, a = e - (e / l) * l;
+                   tile[i * lq + a] = v;
+                 });
   if (t == 0) sok = 1;
   // one slab row per thread: the next step's gW and W' entries are loaded
   // ahead, while the exchange of the current step is in flight
@@ -357,12 +381,14 @@ __global__ __launch_bounds__(256) void ad_wpost(const T* __restrict__ Wto, const
   }
 }
 
-// H rows in reverse.  The columns of H are independent: a workgroup takes 32
-// columns, stages their adjoints gH and the signs of H' in LDS, and each
-// wavefront runs 8 of them with lane p holding gh_p.  For j = k..1 with
+// H rows in reverse.  The columns of H are independent.  A workgroup takes
+// 32 columns and stages their adjoints gH and the signs of H' in LDS; each
+// wavefront runs 8 columns side by side (independent chains, so their
+// latencies overlap), lane p holding gh_p of each.  For j = k..1 with
 // S_jj > 0: ga = gh_j if H'(j, c) > 0 else 0; gA(j, c) = ga; gh_j <- 0;
-// gh_p -= S_pj / S_jj ga (p != j).  gH(:, c) <- gh (the adjoint of the old H).
+// gh_p -= S_pj (ga / S_jj) (p != j).  gH(:, c) <- gh (the adjoint of the old H).
 constexpr int HR_COLS = 32;
+constexpr int HR_CPW = 8;  // columns per wavefront
 
 template <typename T>
 __global__ __launch_bounds__(256) void ad_hrows(const T* __restrict__ Hn, const double* __restrict__ S, int64_t n,
@@ -373,30 +399,53 @@ __global__ __launch_bounds__(256) void ad_hrows(const T* __restrict__ Hn, const 
   __shared__ unsigned char tm[KMAX][HR_COLS];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * HR_COLS;
-  for (int e = t; e < k * k; e += 256) Ss[e] = S[e];
-  for (int e = t; e < k * HR_COLS; e += 256) {
-    const int p = e / HR_COLS, cc = e - (e / HR_COLS) * HR_COLS;
-    const int64_t c = c0 + cc;
-    const bool in = c < n;
-    tg[p][cc] = in ? gH[(int64_t)p * n + c] : 0.0;
-    tm[p][cc] = (in && (double)Hn[(int64_t)p * n + c] > 0.0) ? 1 : 0;
-  }
+  stage<256>(k * k, [&](int e) { return S[e]; }, [&](int e, double v) { Ss[e] = v; });
+  // columns past n read column n - 1 and are stored as zero adjoints and signs
+  auto gidx = [&](int e) {
+    const int p = (int)(e / HR_COLS), cc = (int)(e - (e / HR_COLS) * HR_COLS);
+    const int64_t c = (c0 + cc) < n ? (c0 + cc) : (n - 1);
+    return (int64_t)p * n + c;
+  };
+  auto inb = [&](int e) { return c0 + (e - (e / HR_COLS) * HR_COLS) < n; };
+  stage<256>(k * HR_COLS, [&](int e) { return gH[gidx(e)]; },
+             [&](int e, double v) { tg[e / HR_COLS][e - (e / HR_COLS) * HR_COLS] = inb(e) ? v : 0.0; });
+  stage<256>(k * HR_COLS, [&](int e) { return Hn[gidx(e)]; },
+             [&](int e, T v) {
+               tm[e / HR_COLS][e - (e / HR_COLS) * HR_COLS] = (inb(e) && (double)v > 0.0) ? 1 : 0;
+             });
   __syncthreads();
-  for (int cc = wv; cc < HR_COLS; cc += 4) {
-    double gh = lane < k ? tg[lane][cc] : 0.0;
-    for (int j = k - 1; j >= 0; --j) {
-      const double d = Ss[j * k + j];
-      double ga = 0.0;
-      if (d > 0.0) {
-        const double ghj = __shfl(gh, j, 64);
-        ga = tm[j][cc] ? ghj : 0.0;
-        if (lane == j) gh = 0.0;
-        else if (lane < k) gh = fma(-Ss[lane * k + j], ga / d, gh);
-      }
-      if (lane == 0) ta[j][cc] = ga;
+  const int cb = wv * HR_CPW;
+  double gh[HR_CPW];
+#pragma unroll
+  for (int q = 0; q < HR_CPW; ++q) gh[q] = lane < k ? tg[lane][cb + q] : 0.0;
+  for (int j = k - 1; j >= 0; --j) {
+    const double d = Ss[j * k + j];
+    if (!(d > 0.0)) {
+      if (lane < HR_CPW) ta[j][cb + lane] = 0.0;
+      continue;
     }
-    if (lane < k) tg[lane][cc] = gh;
+    const double spj = lane < k ? Ss[lane * k + j] : 0.0;
+    double ga[HR_CPW];
+#pragma unroll
+    for (int q = 0; q < HR_CPW; ++q) {
+      const double ghj = __shfl(gh[q], j, 64);
+      ga[q] = tm[j][cb + q] ? ghj : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < HR_CPW; ++q) {
+      const double f = ga[q] / d;
+      gh[q] = (lane == j) ? 0.0 : fma(-spj, f, gh[q]);
+    }
+    if (lane < HR_CPW) {
+      double v = ga[0];
+#pragma unroll
+      for (int q = 1; q < HR_CPW; ++q) v = (lane == q) ? ga[q] : v;
+      ta[j][cb + lane] = v;
+    }
   }
+#pragma unroll
+  for (int q = 0; q < HR_CPW; ++q)
+    if (lane < k) tg[lane][cb + q] = gh[q];
   __syncthreads();
   for (int e = t; e < k * HR_COLS; e += 256) {
     const int p = e / HR_COLS, cc = e - (e / HR_COLS) * HR_COLS;
@@ -405,6 +454,121 @@ __global__ __launch_bounds__(256) void ad_hrows(const T* __restrict__ Hn, const 
       gH[(int64_t)p * n + c] = tg[p][cc];
       gA[(int64_t)p * n + c] = ta[p][cc];
     }
+  }
+}
+
+// C (M x K, FP64) += A (M x K) Mp, with Mp the K x K factor zero-padded to
+// 64 x 64 (FP64), K <= 64.  Lane j of a wavefront holds column j of Mp in
+// registers; the workgroup stages 128 rows of A in LDS (row stride K | 1),
+// and each wavefront runs 32 of them, two at a time, every lane reading the
+// same A entries.  Row i of C is then read and written by the lanes in one
+// contiguous piece.  A is finite (the states of a forward that the sweep
+// kernel has checked), so a zero entry of Mp cancels any entry of A.
+template <typename T>
+__global__ __launch_bounds__(256) void ad_rowmat(const T* __restrict__ A, const double* __restrict__ Mp, int64_t M,
+                                                 int K, double* __restrict__ C) {
+  __shared__ T At[128 * (KMAX + 1)];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, kq = K | 1;
+  const int64_t i0 = (int64_t)blockIdx.x * 128;
+  const int rows = (M - i0) < 128 ? (int)(M - i0) : 128;
+  const T* ab = A + i0 * K;
+  for (int e = t; e < 128 * (KMAX + 1); e += 256) At[e] = (T)0;
+  __syncthreads();
+  stage<256>(rows * K, [&](int e) { return ab[e]; },
+             [&](int e, T v) {
+               const int r = e / K, q = e - (e / K) * K;
+               At[r * kq + q] = v;
+             });
+  double mc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) mc[q] = Mp[q * KMAX + lane];
+  __syncthreads();
+  // the sum runs over all 64 entries: reads past a row's K entries stay in
+  // the tile (at most 127 * 65 + 63) and meet the zero rows q >= K of Mp;
+  // they are the next row's (finite) entries or the zeros written above
+  for (int r = w * 32; r < w * 32 + 32 && r < rows; r += 2) {
+    const bool two = r + 1 < rows;
+    const T* a0 = At + r * kq;
+    const T* a1 = At + (two ? r + 1 : r) * kq;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      s0 = fma((double)a0[q], mc[q], s0);
+      s1 = fma((double)a1[q], mc[q], s1);
+    }
+    if (lane < K) {
+      C[(i0 + r) * K + lane] += s0;
+      if (two) C[(i0 + r + 1) * K + lane] += s1;
+    }
+  }
+}
+
+// Mp (64 x 64) = G + G^T for the k x k G, zero outside the leading k x k.
+__global__ __launch_bounds__(256) void ad_symm_pad(const double* __restrict__ G, int k, double* __restrict__ Mp) {
+  for (int e = threadIdx.x; e < KMAX * KMAX; e += 256) {
+    const int i = e / KMAX, j = e - (e / KMAX) * KMAX;
+    Mp[e] = (i < k && j < k) ? G[i * k + j] + G[j * k + i] : 0.0;
+  }
+}
+
+// Partial Gram W^T W (k <= 64) of a slab of rows, FP64: the workgroup stages
+// 128 rows at a time in LDS and thread (bi, bj) accumulates the 4 x 4 block
+// (4 bi.., 4 bj..) over them, rows in order.  Written in the partial layout
+// of the Cholesky QR Gram (entry (a, b), a <= b, at a * LMAX + b of the
+// workgroup's slot), summed by launch_gram_sum.
+template <typename T>
+__global__ __launch_bounds__(256) void ad_wgram(const T* __restrict__ W, int64_t m, int k, int64_t rows_per,
+                                                double* __restrict__ part) {
+  __shared__ double tile[128 * (KMAX + 1)];
+  const int t = threadIdx.x, bi = t >> 4, bj = t & 15;
+  constexpr int KP = KMAX + 1;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = (r0 + rows_per) < m ? (r0 + rows_per) : m;
+  const bool live = 4 * bi < k && 4 * bj < k && bi <= bj;
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int64_t c0 = r0; c0 < r1; c0 += 128) {
+    const int cnt = (r1 - c0) < 128 ? (int)(r1 - c0) : 128;
+    // the chunk's rows are contiguous: element e is row e / k, column e % k
+    const T* wb = W + c0 * k;
+    stage<256>(cnt * k, [&](int e) { return wb[e]; },
+               [&](int e, T v) {
+                 const int r = e / k, q = e - (e / k) * k;
+                 tile[r * KP + q] = (double)v;
+               });
+    for (int e = t; e < cnt * (KMAX - k); e += 256) {
+      const int r = e / (KMAX - k), q = k + (e - (e / (KMAX - k)) * (KMAX - k));
+      tile[r * KP + q] = 0.0;
+    }
+    __syncthreads();
+    if (live)
+      for (int r = 0; r < cnt; ++r) {
+        const double* row = tile + r * KP;
+        double u[4], v[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          u[x] = row[4 * bi + x];
+          v[x] = row[4 * bj + x];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = fma(u[x], v[y], acc[x][y]);
+      }
+    __syncthreads();
+  }
+  if (live) {
+    double* dst = part + (size_t)blockIdx.x * LMAX * LMAX;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int a = 4 * bi + x, b = 4 * bj + y;
+        if (a < k && b < k && a <= b) dst[a * LMAX + b] = acc[x][y];
+      }
   }
 }
 
@@ -551,6 +715,36 @@ template <typename T>
 static hipError_t hrows_t(const T* Hn, const double* S, int64_t n, int k, double* gH, double* gA, hipStream_t s) {
   const dim3 g((unsigned)((n + HR_COLS - 1) / HR_COLS));
   hipLaunchKernelGGL(ad_hrows<T>, g, dim3(256), 0, s, Hn, S, n, k, gH, gA);
+  return hipGetLastError();
+}
+
+int ad_wgram_splits(int64_t m, int cus) {
+  int64_t g = (m + 127) / 128;
+  if (g > cus) g = cus;
+  return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t ad_wgram_run(const void* W, int64_t m, int k, double* part, int splits, double* S, int dt, hipStream_t s) {
+  if (k < 1 || k > KMAX) return hipErrorInvalidValue;
+  const int64_t rows_per = (m + splits - 1) / splits;
+  const int used = (int)((m + rows_per - 1) / rows_per);
+  if (dt == 0) hipLaunchKernelGGL(ad_wgram<double>, dim3(used), dim3(256), 0, s, (const double*)W, m, k, rows_per, part);
+  else hipLaunchKernelGGL(ad_wgram<float>, dim3(used), dim3(256), 0, s, (const float*)W, m, k, rows_per, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gram_sum(part, used, k, S, s);
+}
+
+hipError_t ad_symm_pad_run(const double* G, int k, double* Mp, hipStream_t s) {
+  hipLaunchKernelGGL(ad_symm_pad, dim3(1), dim3(256), 0, s, G, k, Mp);
+  return hipGetLastError();
+}
+
+hipError_t ad_rowmat_run(const void* A, const double* Mm, int64_t M, int K, double* C, int dt, hipStream_t s) {
+  if (K < 1 || K > KMAX) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((M + 127) / 128));
+  if (dt == 0) hipLaunchKernelGGL(ad_rowmat<double>, g, dim3(256), 0, s, (const double*)A, Mm, M, K, C);
+  else hipLaunchKernelGGL(ad_rowmat<float>, g, dim3(256), 0, s, (const float*)A, Mm, M, K, C);
   return hipGetLastError();
 }
 

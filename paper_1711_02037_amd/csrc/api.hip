@@ -575,7 +575,7 @@ struct BackBufs {
   SweepBufs sw;
   std::vector<State> ckpt;  // states at the start of segments 1..nseg-1
   std::vector<State> seg;   // the states of one segment, len + 1 of them
-  double *gWt, *gA, *gT, *gV, *gS, *Msym, *S, *Tm, *V, *GU;
+  double *gWt, *gA, *gT, *gV, *gS, *Msym, *Mpad, *S, *Tm, *V, *GU;
   double *gpart, *hpart;  // Gram partials of W^T W and of H H^T
   WrevShape wsh;          // the persistent reverse W phase
   u64* wx;                // its exchange slots
@@ -597,13 +597,14 @@ BackBufs plan_backward(Arena& a, int64_t m, int64_t n, int l, int k, int T, int 
   b.gV = a.take<double>((size_t)k * k);
   b.gS = a.take<double>((size_t)k * k);
   b.Msym = a.take<double>((size_t)k * k);
+  b.Mpad = a.take<double>((size_t)KMAX * KMAX);
   b.S = a.take<double>((size_t)k * k);
   b.Tm = a.take<double>((size_t)l * k);
   b.V = a.take<double>((size_t)k * k);
   b.GU = a.take<double>((size_t)l * k);
   b.wsh = plan_wrev(m, l, k, md.dt, d.cus, d.max_lds);
   b.wx = a.take<u64>(wrev_ws_words(b.wsh));
-  b.gsplits = gram_splits(m, d.cus);
+  b.gsplits = ad_wgram_splits(m, d.cus);
   b.gpart = a.take<double>((size_t)b.gsplits * LMAX * LMAX);
   b.hsplits = hgram_splits(n);
   b.hpart = a.take<double>((size_t)b.hsplits * LMAX * LMAX);
@@ -653,15 +654,15 @@ rnmf_status reverse_sweep(const void* Q, const void* B, const State& o_, const S
   HIPCHK(ad_symm_run(b.gV, k, b.Msym, s));
   HIPCHK(ad_gemm_sd(k, n, k, b.Msym, 0, k, 0, n_.H, sd, n, 0, gH, n, 1.0, 1, s));
   // H rows in reverse with S = W^T W of the sweep's input
-  HIPCHK(launch_gram(o_.W, dt, m, k, b.gpart, b.gsplits, b.S, s));
+  HIPCHK(ad_wgram_run(o_.W, m, k, b.gpart, b.gsplits, b.S, dt, s));
   HIPCHK(ad_hrows_run(n_.H, b.S, n, k, gH, b.gA, dt, s));
   HIPCHK(ad_gs_run(n_.H, o_.H, b.gA, b.S, n, k, b.gS, dt, s));
   HIPCHK(ad_scale_rows_run(b.gA, b.S, n, k, s));
   // R = B^T W~: gB += W~ gA, gW~ += B gA^T; S: gW += W (gS + gS^T)
   HIPCHK(ad_gemm_sd(l, n, k, o_.Wt, sd, k, 0, b.gA, 0, n, 0, gB, n, 1.0, 1, s));
   HIPCHK(ad_gemm_sd(l, k, n, B, sd, n, 0, b.gA, 0, n, 1, b.gWt, k, 1.0, 1, s));
-  HIPCHK(ad_symm_run(b.gS, k, b.Msym, s));
-  HIPCHK(ad_gemm_sd(m, k, k, o_.W, sd, k, 0, b.Msym, 0, k, 0, gW, k, 1.0, 1, s));
+  HIPCHK(ad_symm_pad_run(b.gS, k, b.Mpad, s));
+  HIPCHK(ad_rowmat_run(o_.W, b.Mpad, m, k, gW, dt, s));
   return RNMF_OK;
 }
 

@@ -137,6 +137,11 @@ hipError_t ad_wpost_run(const void* Wto, const void* Wtn, const double* Tm, cons
                         int l, int k, double* gT, double* gV, int dt, hipStream_t s);
 hipError_t ad_hrows_run(const void* Hn, const double* S, int64_t n, int k, double* gH, double* gA, int dt,
                         hipStream_t s);
+int ad_wgram_splits(int64_t m, int cus);
+hipError_t ad_wgram_run(const void* W, int64_t m, int k, double* part, int splits, double* S, int dt, hipStream_t s);
+hipError_t ad_symm_pad_run(const double* G, int k, double* Mp, hipStream_t s);
+// C (M x K) += A Mp with Mp the K x K factor zero-padded to 64 x 64
+hipError_t ad_rowmat_run(const void* A, const double* Mm, int64_t M, int K, double* C, int dt, hipStream_t s);
 hipError_t ad_gs_run(const void* Hn, const void* Ho, const double* gA, const double* S, int64_t n, int k,
                      double* gS, int dt, hipStream_t s);
 hipError_t ad_scale_rows_run(double* gA, const double* S, int64_t n, int k, hipStream_t s);
