@@ -212,13 +212,15 @@ def main():
             f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X); one at a time "
             f"~{batch['one_at_a_time_ms_estimate']:.0f} ms ({batch['speedup_vs_one_at_a_time']:.1f}x)")
 
-    # ---- reverse pass through 20 unrolled FP32 sweeps ------------------------
+    # ---- reverse pass through 20 unrolled FP32 sweeps (two workloads) ---------
     back = None
     if not args.no_backward:
-        back = backward_bench(rn, torch, X, Q32, W0, H0, dev)
-        log(f"backward: {back['ms_backward']:.2f} ms for {back['T']} sweeps from recorded states "
-            f"(recording forward {back['ms_forward_recorded']:.2f} ms, one-launch forward {back['ms_forward']:.2f} ms, "
-            f"recomputing backward {back['ms_backward_recompute']:.2f} ms)")
+        back = backward_section(rn, torch, synth, X, Q32, W0, H0, dev)
+        for nm in ("diff_8192x2048", "tall_100000x5000"):
+            b = back[nm]
+            log(f"backward {nm}: {b['ms_backward']:.2f} ms for {b['T']} sweeps from recorded states (recording "
+                f"forward {b['ms_forward_recorded']:.2f} ms, one-launch forward {b['ms_forward']:.2f} ms, "
+                f"checkpointed backward (every {b['ckpt_every']}) {b['ms_backward_checkpointed']:.2f} ms)")
 
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
@@ -349,13 +351,12 @@ def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=
             "note": "nonnegative double SVD of the randomized SVD Q B (FP64 Jacobi on B B^T)"}
 
 
-def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, reps=3):
-    """Reverse pass through T FP32 sweeps of this workload: rnmf_unroll with
-    every state recorded (T one-sweep launches, 21 MB per state here) and
-    rnmf_backward reading that record, against one launch of the same T
-    forward sweeps; also rnmf_backward recomputing the forward itself
-    (ckpt_every = T).  Events on the current stream, mean of `reps` calls
-    after one warm-up."""
+def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, ckpt=20, reps=3):
+    """Reverse pass through T FP32 sweeps: rnmf_unroll with every state
+    recorded (T one-sweep launches) and rnmf_backward reading that record,
+    rnmf_backward recomputing the forward from checkpoints every `ckpt`
+    sweeps, and one launch of the same T forward sweeps.  Events on the
+    current stream, mean of `reps` calls after one warm-up."""
     m, n = X.shape
     k, l = H0.shape[0], Q.shape[1]
     B = rn.compress(X, Q)
@@ -387,21 +388,37 @@ def backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, reps=3):
     ms_fr = timed(fwd_rec)
     bws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, 0, "fp32"), dev)
     ms_b = timed(lambda: rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, states=states, ws=bws))
-    cws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, T, "fp32"), dev)
-    ms_bc = timed(lambda: rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=T, ws=cws))
+    cws = rn._workspace(rn.backward_workspace_bytes(m, n, l, k, T, ckpt, "fp32"), dev)
+    ms_bc = timed(lambda: rn.backward(Q, B, W0, Wt0, H0, T, gW, gH, ckpt_every=ckpt, ws=cws))
 
     def fwd_one():
         W.copy_(W0); Wt.copy_(Wt0); H.copy_(H0)
         rn.hals_step(Q, B, W, Wt, H, nsweeps=T)
 
     ms_f = timed(fwd_one)
-    return {"T": T, "precision": "fp32 states, fp64 adjoints", "ms_backward": round(ms_b, 3),
-            "ms_forward_recorded": round(ms_fr, 3), "ms_backward_recompute": round(ms_bc, 3),
-            "ms_forward": round(ms_f, 3), "ratio_to_forward": round((ms_fr + ms_b) / ms_f, 2),
-            "note": "gradients of (W_T, H_T) with respect to B, W0, H0 with Q fixed. ms_backward reads the "
-                    "states that rnmf_unroll recorded (ms_forward_recorded: T one-sweep launches plus the "
-                    "copies); ms_backward_recompute reruns those T launches itself; ms_forward is one launch "
-                    "of T sweeps; the ratio is (recorded forward + backward) / ms_forward"}
+    return {"m": m, "n": n, "k": k, "l": l, "T": T, "ckpt_every": ckpt,
+            "precision": "fp32 states, fp64 adjoints", "ms_backward": round(ms_b, 3),
+            "ms_forward_recorded": round(ms_fr, 3), "ms_backward_checkpointed": round(ms_bc, 3),
+            "ms_forward": round(ms_f, 3), "ratio_to_forward": round((ms_fr + ms_b) / ms_f, 2)}
+
+
+def backward_section(rn, torch, synth, X, Q, W0, H0, dev):
+    """The reverse pass on the differentiation workload (8,192 x 2,048, k = 32,
+    T = 20, checkpoints every 5 sweeps) and on this benchmark's workload
+    (T = 20, all states kept)."""
+    w = synth.workload("diff_8192x2048")
+    Xh, Omh, W0h, H0h, _ = synth.make("diff_8192x2048")
+    Xd = torch.from_numpy(Xh).to(dev)
+    Qd = rn.sketch(Xd, w["k"], w["p"], w["q"], omega=torch.from_numpy(Omh).to(dev))
+    c5 = backward_bench(rn, torch, Xd, Qd, torch.from_numpy(W0h).to(dev), torch.from_numpy(H0h).to(dev), dev,
+                        T=w["sweeps"], ckpt=w["ckpt_every"])
+    c3 = backward_bench(rn, torch, X, Q, W0, H0, dev, T=20, ckpt=20)
+    return {"diff_8192x2048": c5, "tall_100000x5000": c3,
+            "note": "gradients of (W_T, H_T) with respect to B, W0, H0 with Q fixed. ms_backward reads the states "
+                    "that rnmf_unroll recorded (ms_forward_recorded: T one-sweep launches plus the copies); "
+                    "ms_backward_checkpointed recomputes them from checkpoints every ckpt_every sweeps; "
+                    "ms_forward is one launch of T sweeps; ratio_to_forward = (recorded forward + backward) / "
+                    "ms_forward"}
 
 
 def batch_bench(rn, torch, synth, dev, reps=3):
