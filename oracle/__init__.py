@@ -40,6 +40,10 @@ from .rhals import (  # noqa: F401
     qb,
     qb_streaming,
     rhals_sweep,
+    rhals_sweep_ordered,
+    hals_sweep_ordered,
+    order_blocked,
+    order_interleaved,
     nndsvd,
     svd_init,
     hals_sweep,

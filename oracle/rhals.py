@@ -40,6 +40,11 @@ R10 The projected gradient of Sec. 3.3 is evaluated after each full sweep, with
     taken on the surrogate X^ = Q B.
 R11 "Relative error" is ||X - W H||_F / ||X||_F, computed directly.
 R12 max(0, x) is computed as (x if x > 0 else +0).
+R24 Update orders (Sec. 3.2): besides the two blocked orders, the interleaved
+    order W(:,1) -> H(1,:) -> ... -> W(:,k) -> H(k,:) and the shuffled order,
+    read as the interleaved order over a random permutation of the components
+    per sweep (the permutation is an input).  Each block update takes the
+    products of the factors as they are at that moment.
 R18 Regularized rules (Sec. 3.4 and its appendix) are taken as printed: the
     ridge weight alpha enlarges the scale (S_jj + alpha, V_jj + alpha) and
     damps the old block by S_jj / (S_jj + alpha); the LASSO weight beta is
@@ -326,6 +331,98 @@ def hals_sweep(X, W, H, order=ORDER_H_FIRST, reg=NO_REG):
         h_phase()
     else:
         raise ValueError("unknown order")
+    return W, H
+
+
+# ----------------------------------------------------------------------------
+# Update orders (Sec. 3.2: the two cyclic orders and the shuffled order)
+# ----------------------------------------------------------------------------
+# An order is a sequence of block updates: entry e < k updates column e of W
+# (with its lift and map-back in rHALS), entry e >= k updates row e - k of H.
+# Reading R24: every block update takes the Gram and cross products of the
+# factors as they are at that moment (in the blocked orders this equals
+# forming them once per phase, as the other factor does not move within a
+# phase); the shuffled order updates the components (W(:,j), H(j,:)) of the
+# interleaved order in a random order per sweep, the permutation being an
+# input.
+
+def order_blocked(k, w_first=False):
+    """W(:,1..k) then H(1..k,:) (w_first), or H rows then W columns
+    (Algorithm 1's order)."""
+    w = list(range(k))
+    h = [k + j for j in range(k)]
+    return w + h if w_first else h + w
+
+
+def order_interleaved(k, perm=None):
+    """W(:,j) -> H(j,:) for j = perm[0], perm[1], ... (the first cyclic order
+    of Sec. 3.2 for perm = 0..k-1; the shuffled order for a random perm)."""
+    perm = range(k) if perm is None else perm
+    out = []
+    for j in perm:
+        out += [int(j), k + int(j)]
+    return out
+
+
+def rhals_sweep_ordered(Q, B, W, Wt, H, order):
+    """One sweep of randomized HALS (Sec. 3.2, plain rules) with the block
+    updates in the given order (reading R24).  For column j of W, with
+    T(:,j) = B H(j,:)^T, V(:,j) = H H(j,:)^T and d = V_jj:
+        W~(:,j) <- W~(:,j) + (T(:,j) - W~ V(:,j)) / d,
+        W(:,j) <- [Q W~(:,j)]_+,  W~(:,j) <- Q^T W(:,j);
+    for row j of H, with S(:,j) = W^T W(:,j), R(:,j) = B^T W~(:,j), s = S_jj:
+        H(j,:) <- [H(j,:) + (R(:,j) - H^T S(:,j)) / s]_+.
+    Blocks with a zero scale are skipped (reading R9).  Returns new copies
+    (W, Wt, H)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    W = np.array(W, dtype=np.float64)
+    Wt = np.array(Wt, dtype=np.float64)
+    H = np.array(H, dtype=np.float64)
+    k = H.shape[0]
+    for e in order:
+        if e < k:
+            j = e
+            T_j = B @ H[j, :]
+            V_j = H @ H[j, :]
+            d = V_j[j]
+            if d > 0.0:
+                Wt[:, j] = Wt[:, j] + (T_j - Wt @ V_j) / d
+                W[:, j] = clip(Q @ Wt[:, j])
+                Wt[:, j] = Q.T @ W[:, j]
+        else:
+            j = e - k
+            S_j = W.T @ W[:, j]
+            R_j = B.T @ Wt[:, j]
+            d = S_j[j]
+            if d > 0.0:
+                H[j, :] = clip(H[j, :] + (R_j - H.T @ S_j) / d)
+    return W, Wt, H
+
+
+def hals_sweep_ordered(X, W, H, order):
+    """One sweep of deterministic HALS (Sec. 3.1, plain rules) with the block
+    updates in the given order: W(:,j) <- [W(:,j) + ((X H^T)(:,j) -
+    W (H H^T)(:,j)) / (H H^T)_jj]_+ and H(j,:) <- [H(j,:) + ((X^T W)(:,j) -
+    H^T (W^T W)(:,j)) / (W^T W)_jj]_+, the products taken from the current
+    factors.  Returns new copies (W, H)."""
+    X = np.asarray(X, dtype=np.float64)
+    W = np.array(W, dtype=np.float64)
+    H = np.array(H, dtype=np.float64)
+    k = H.shape[0]
+    for e in order:
+        if e < k:
+            j = e
+            V_j = H @ H[j, :]
+            d = V_j[j]
+            if d > 0.0:
+                W[:, j] = clip(W[:, j] + (X @ H[j, :] - W @ V_j) / d)
+        else:
+            j = e - k
+            S_j = W.T @ W[:, j]
+            d = S_j[j]
+            if d > 0.0:
+                H[j, :] = clip(H[j, :] + (X.T @ W[:, j] - H.T @ S_j) / d)
     return W, H
 
 
