@@ -222,6 +222,12 @@ def main():
                 f"forward {b['ms_forward_recorded']:.2f} ms, one-launch forward {b['ms_forward']:.2f} ms, "
                 f"checkpointed backward (every {b['ckpt_every']}) {b['ms_backward_checkpointed']:.2f} ms)")
 
+    # ---- update orders: interleaved and shuffled sweeps (ordered path) --------
+    orders = orders_bench(rn, torch, X, Q32, W0, H0, dev)
+    log(f"orders: interleaved {orders['interleaved_ms_per_sweep']:.2f} ms/sweep, shuffled "
+        f"{orders['shuffled_ms_per_sweep']:.2f} ms/sweep, blocked list {orders['blocked_list_ms_per_sweep']:.2f} "
+        f"ms/sweep (sweep kernel {orders['sweep_kernel_ms_per_sweep']:.3f})")
+
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -252,6 +258,7 @@ def main():
         "svd_init": svd,
         "batched": batch,
         "backward": back,
+        "orders": orders,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -419,6 +426,43 @@ def backward_section(rn, torch, synth, X, Q, W0, H0, dev):
                     "ms_backward_checkpointed recomputes them from checkpoints every ckpt_every sweeps; "
                     "ms_forward is one launch of T sweeps; ratio_to_forward = (recorded forward + backward) / "
                     "ms_forward"}
+
+
+def orders_bench(rn, torch, X, Q, W0, H0, dev, nsw=3):
+    """Milliseconds per sweep of rnmf_hals_ordered on this workload (FP32) for
+    the interleaved order, a shuffled order (one seeded permutation per sweep)
+    and the blocked list, beside the persistent sweep kernel's blocked sweep;
+    events on the current stream."""
+    import numpy as np
+    m, n = X.shape
+    k = H0.shape[0]
+    B = rn.compress(X, Q)
+    Wt0 = rn.compress(W0.contiguous(), Q)
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g = np.random.default_rng(1711)
+    lists = {"interleaved": [rn.order_interleaved(k)] * nsw,
+             "shuffled": [rn.order_interleaved(k, g.permutation(k)) for _ in range(nsw)],
+             "blocked_list": [rn.order_blocked(k)] * nsw}
+    out = {}
+    for name, od in lists.items():
+        W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+        rn.hals_ordered(Q, B, W, Wt, H, od[:1])
+        e0.record(st)
+        rn.hals_ordered(Q, B, W, Wt, H, od)
+        e1.record(st)
+        e1.synchronize()
+        out[name + "_ms_per_sweep"] = round(e0.elapsed_time(e1) / nsw, 3)
+    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+    rn.hals_step(Q, B, W, Wt, H, nsweeps=1)
+    e0.record(st)
+    rn.hals_step(Q, B, W, Wt, H, nsweeps=20)
+    e1.record(st)
+    e1.synchronize()
+    out["sweep_kernel_ms_per_sweep"] = round(e0.elapsed_time(e1) / 20, 4)
+    out["note"] = ("rnmf_hals_ordered runs any order of block updates with a few launches per block; the blocked "
+                   "orders run in the persistent sweep kernel (rnmf_hals_step)")
+    return out
 
 
 def batch_bench(rn, torch, synth, dev, reps=3):

@@ -242,6 +242,28 @@ rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, in
                           void* W, void* H, const rnmf_opts* opts, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* ---- Sweeps with an explicit order of block updates --------------------------
+ * Sec. 3.2 allows different orders of the block updates: the interleaved
+ * cyclic order W(:,1) -> H(1,:) -> ... -> W(:,k) -> H(k,:), the blocked
+ * orders (all columns of W, then all rows of H, or the reverse), and a
+ * shuffled order that takes the components in a random order per sweep.
+ * This entry point runs nsweeps compressed-HALS sweeps (plain rules,
+ * S = W^T W) on W, Wt, H in place, with the block updates of sweep s in the
+ * order order[s*2k .. s*2k + 2k - 1]: entry e < k updates column e of W
+ * (update, lift, clip and map-back), entry e >= k updates row e - k of H.
+ * Every block update takes the products of the factors as they are at that
+ * moment.  Each sweep's list must be a permutation of 0..2k-1
+ * (RNMF_ERR_ARG otherwise); order is host memory (nsweeps*2k int32), drawn
+ * by the caller for a shuffled order.  Blocks with a zero scale are skipped.
+ * Arguments as for rnmf_hals_step; gram_mode must be RNMF_GRAM_FULL and the
+ * regularization weights zero.  A few launches per block update: the
+ * blocked orders run much faster in rnmf_hals_step.  Workspace:
+ * rnmf_hals_ordered_workspace_bytes.  Asynchronous. */
+size_t rnmf_hals_ordered_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k);
+rnmf_status rnmf_hals_ordered(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
+                              void* Wt, void* H, int32_t nsweeps, const int32_t* order, const rnmf_opts* opts,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Reverse mode through unrolled sweeps ---------------------------------
  * T sweeps, one launch each, with every state recorded: the forward that
  * rnmf_backward differentiates without recomputation.  Runs T sweeps of

@@ -19,7 +19,7 @@ __all__ = [
     "RnmfError", "lib", "available", "make_opts", "sketch_width", "workspace_bytes",
     "sketch", "compress", "hals_step", "rel_error", "factorize", "cast_bf16",
     "status_string", "read_status", "hals", "svd_init", "Batch", "backward", "backward_workspace_bytes",
-    "unrolled_forward", "unroll", "rand_hals_fn",
+    "unrolled_forward", "unroll", "rand_hals_fn", "hals_ordered", "order_blocked", "order_interleaved",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +43,7 @@ EXPORTS = [
     "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
     "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
+    "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered",
 ]
 
 
@@ -133,6 +134,11 @@ def lib():
         L.rnmf_backward.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(Opts), vp, sz, vp]
         L.rnmf_unroll.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, vp, ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_hals_ordered_workspace_bytes.argtypes = [i64, i64, i32, i32]
+        L.rnmf_hals_ordered_workspace_bytes.restype = sz
+        L.rnmf_hals_ordered.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, ctypes.POINTER(i32),
+                                        ctypes.POINTER(Opts), vp, sz, vp]
+        L.rnmf_hals_ordered.restype = ctypes.c_int
         L.rnmf_unroll.restype = ctypes.c_int
         L.rnmf_backward.restype = ctypes.c_int
         L.rnmf_cast_bf16.argtypes = [vp, i64, i64, i64, vp, vp]
@@ -342,6 +348,49 @@ def hals(X, W, H, nsweeps=1, order="h_first", ws=None, reg=None):
     _check(lib().rnmf_hals(_ptr(X), _xt(X), m, n, X.stride(0), _ptr(W), _ptr(H), int(nsweeps), ctypes.byref(o),
                            _ptr(w), w.numel(), _stream(X.device)))
     _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(X.device)))
+
+
+def order_blocked(k, w_first=False):
+    """One sweep's block list for a blocked order: rows of H then columns of
+    W (Algorithm 1), or columns of W first.  Entry e < k is column e of W,
+    entry e >= k is row e - k of H."""
+    w = list(range(k))
+    h = [k + j for j in range(k)]
+    return w + h if w_first else h + w
+
+
+def order_interleaved(k, perm=None):
+    """One sweep's block list for the interleaved order W(:,j) -> H(j,:) with
+    j = perm[0], perm[1], ... (0..k-1 by default; a random perm gives the
+    shuffled order)."""
+    perm = range(k) if perm is None else perm
+    out = []
+    for j in perm:
+        out += [int(j), k + int(j)]
+    return out
+
+
+def hals_ordered(Q, B, W, Wt, H, orders, ws=None):
+    """Compressed HALS sweeps with explicit block orders, in place on W, Wt,
+    H (rnmf_hals_ordered): `orders` holds one list per sweep, each a
+    permutation of 0..2k-1 (see order_blocked, order_interleaved)."""
+    import numpy as np
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B"), (W, "W"), (Wt, "Wt"), (H, "H")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    k, n = H.shape
+    arr = np.ascontiguousarray(np.asarray(orders, dtype=np.int32).reshape(-1, 2 * k))
+    prec = "fp64" if Q.dtype == torch.float64 else "fp32"
+    o = make_opts(k, l - k, 0, precision=prec)
+    nb = lib().rnmf_hals_ordered_workspace_bytes(m, n, l, k)
+    if nb == 0:
+        raise RnmfError(ERR_ARG, lib().rnmf_last_error().decode())
+    keep, w = ws if ws is not None else _workspace(nb, Q.device)
+    _check(lib().rnmf_hals_ordered(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W), _ptr(Wt), _ptr(H), arr.shape[0],
+                                   arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(o), _ptr(w),
+                                   w.numel(), _stream(Q.device)))
+    _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(Q.device)))
 
 
 def svd_init(Q, B, k, ws=None):

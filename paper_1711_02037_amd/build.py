@@ -19,7 +19,7 @@ OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RNMF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "misc.hip", "xpass.hip", "qr.hip", "sweep.hip", "hals.hip", "svdinit.hip", "batch.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "misc.hip", "xpass.hip", "qr.hip", "sweep.hip", "hals.hip", "svdinit.hip", "batch.hip", "adjoint.hip", "ordered.hip"]
 
 # Packed FP32 instructions are disabled for device code; hipcc forwards the
 # flag to the host pass too, which warns that it does not know the feature.

@@ -884,6 +884,62 @@ rnmf_status rnmf_unroll(const void* Q, const void* B, int64_t m, int64_t n, int3
   return RNMF_OK;
 }
 
+size_t rnmf_hals_ordered_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t k) {
+  g_err.clear();
+  if (m < 1 || n < 1 || k < 1 || k > KMAX || l < k || l > LMAX || l > m) {
+    fail(RNMF_ERR_ARG, "need 1 <= k <= l <= min(m, %d), k <= %d", LMAX, KMAX);
+    return 0;
+  }
+  Arena a(nullptr);
+  a.take<char>(HDR_BYTES);
+  a.take<double>((size_t)ord_part_elems(m, n, l, k));
+  a.take<double>((size_t)l + k);
+  return a.used;
+}
+
+rnmf_status rnmf_hals_ordered(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
+                              void* Wt, void* H, int32_t nsweeps, const int32_t* order, const rnmf_opts* o, void* ws,
+                              size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!Q || !B || !W || !Wt || !H) return fail(RNMF_ERR_ARG, "Q, B, W, Wt and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (nsweeps < 0) return fail(RNMF_ERR_ARG, "nsweeps < 0");
+  if (nsweeps > 0 && !order) return fail(RNMF_ERR_ARG, "order is NULL");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  if (o->gram_mode != RNMF_GRAM_FULL) return fail(RNMF_ERR_ARG, "ordered sweeps use gram_mode RNMF_GRAM_FULL");
+  if (o->alpha_w != 0.0 || o->alpha_h != 0.0 || o->beta_w != 0.0 || o->beta_h != 0.0)
+    return fail(RNMF_ERR_ARG, "ordered sweeps use the plain rules (zero regularization weights)");
+  // every sweep's list must update each of the 2k blocks exactly once
+  std::vector<char> seen((size_t)2 * k);
+  for (int s = 0; s < nsweeps; ++s) {
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int i = 0; i < 2 * k; ++i) {
+      const int32_t e = order[(size_t)s * 2 * k + i];
+      if (e < 0 || e >= 2 * k || seen[e]) return fail(RNMF_ERR_ARG, "sweep %d: order is not a permutation of 0..2k-1", s);
+      seen[e] = 1;
+    }
+  }
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  double* part = a.take<double>((size_t)ord_part_elems(m, n, l, k));
+  double* vec = a.take<double>((size_t)l + k);
+  rnmf_status r;
+  if ((r = check_ws(ws, ws_bytes, a.used)) != RNMF_OK) return r;
+  Hdr h = header(ws);
+  HIPCHK(launch_fill_u32(h.status, 1, 0u, d.stream));
+  for (int s = 0; s < nsweeps; ++s)
+    for (int i = 0; i < 2 * k; ++i)
+      HIPCHK(launch_ordered_update(Q, B, W, Wt, H, m, n, l, k, order[(size_t)s * 2 * k + i], part, vec, md.dt,
+                                   d.stream));
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_svd_init(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
                           void* H, const rnmf_opts* o, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();

@@ -148,6 +148,13 @@ hipError_t ad_scale_rows_run(double* gA, const double* S, int64_t n, int k, hipS
 hipError_t ad_symm_run(const double* G, int k, double* M, hipStream_t s);
 hipError_t ad_fill_run(double* p, int64_t count, double v, hipStream_t s);
 
+// Sweeps with an explicit order of block updates (ordered.hip).  Entry e < k
+// updates column e of W, entry e >= k row e - k of H.  part holds
+// ord_part_elems doubles, vec l + k doubles.
+int ord_part_elems(int64_t m, int64_t n, int l, int k);
+hipError_t launch_ordered_update(const void* Q, const void* B, void* W, void* Wt, void* H, int64_t m, int64_t n,
+                                 int l, int k, int e, double* part, double* vec, int dt, hipStream_t s);
+
 // SVD-based initialization (svdinit.hip).  Workspace pieces, all FP64:
 // gpart (hgram_splits(n) x LMAX x LMAX), C (l x l), Ub (l x k), sv (k),
 // upart (svd_row_blocks(m) x k x 2), vpart (svd_col_blocks(n) x k x 2),

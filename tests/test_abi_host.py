@@ -276,3 +276,27 @@ def test_unroll_validation():
     assert call(l=7) == rn.ERR_SHAPE
     assert call() == rn.ERR_HIP
     assert rn.state_elems(3000, 500, 16, 8) == 3000 * 8 + 16 * 8 + 8 * 500
+
+
+def test_hals_ordered_validation():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    k = 4
+    o = rn.make_opts(k, 6, 0)
+    assert L.rnmf_hals_ordered_workspace_bytes(3000, 500, 10, k) > 0
+    assert L.rnmf_hals_ordered_workspace_bytes(3000, 500, 3, k) == 0
+
+    def call(order, nsw=1, oo=o, W=p):
+        arr = (ctypes.c_int32 * max(1, len(order)))(*order)
+        return L.rnmf_hals_ordered(p, p, 3000, 500, 10, k, W, p, p, nsw, arr, ctypes.byref(oo), p, 1 << 30, None)
+    good = rn.order_interleaved(k)
+    assert sorted(good) == list(range(2 * k)) and rn.order_blocked(3, True) == [0, 1, 2, 3, 4, 5]
+    assert call(good) == rn.ERR_HIP                      # arguments check out; no device here
+    assert call(good[:-1] + [good[0]]) == rn.ERR_ARG     # a block twice
+    assert call(good[:-1] + [2 * k]) == rn.ERR_ARG       # out of range
+    assert call(good, nsw=-1) == rn.ERR_ARG
+    assert call(good, W=None) == rn.ERR_ARG
+    for field, value in (("gram_mode", 1), ("alpha_h", 0.5)):
+        bad = rn.make_opts(k, 6, 0)
+        setattr(bad, field, value)
+        assert call(good, oo=bad) == rn.ERR_ARG, field
