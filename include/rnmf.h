@@ -92,6 +92,11 @@ enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
 #define RNMF_FLAG_TRACE 0x8u            /* rnmf_hals_step: record phase timestamps */
 #define RNMF_FLAG_SVD_INIT 0x20u        /* rnmf_factorize: W0, H0 by the SVD-based
                                            initialization (rnmf_svd_init)      */
+#define RNMF_FLAG_GAUSS_INIT 0x40u       /* rnmf_factorize: W0, H0 drawn from the seed
+                                           as standard normal entries with the
+                                           negative ones set to zero (the Remark
+                                           on initialization after Algorithm 1),
+                                           instead of uniform on [0, 1)          */
 #define RNMF_FLAG_SHIFTED_QR3 0x10u     /* every QR: shifted Cholesky QR pass first, then
                                            two plain passes (shifted CholeskyQR3)   */
 
@@ -215,7 +220,8 @@ rnmf_status rnmf_rel_error(const void* X, int xt, int64_t m, int64_t n, int64_t 
 /* Algorithm 1 end to end: sketch, compression, W~ = Q^T W0, sweeps until the
  * stop test or max_iter, then the relative error.  Omega (n x l), W0 (m x k),
  * H0 (k x n) are optional device inputs in the factor dtype; NULL draws them
- * from opts->seed (W0, H0 uniform on [0, 1)); with RNMF_FLAG_SVD_INIT, W0 and
+ * from opts->seed (W0, H0 uniform on [0, 1), or clipped standard normal with
+ * RNMF_FLAG_GAUSS_INIT); with RNMF_FLAG_SVD_INIT, W0 and
  * H0 must be NULL and come from rnmf_svd_init on this call's Q and B (needs
  * l <= 96).  W (out, m x k), H (out, k x n).
  * report (host, may be NULL) is filled after the stream is synchronised.

@@ -35,6 +35,7 @@ ORDER = {"h_first": 0, "w_first": 1}
 OMEGA = {"gaussian": 0, "uniform": 1}
 FLAG_CHECK_INPUT, FLAG_NO_SHIFT, FLAG_EXACT_Q, FLAG_TRACE, FLAG_SHIFTED_QR3 = 0x1, 0x2, 0x4, 0x8, 0x10
 FLAG_SVD_INIT = 0x20
+FLAG_GAUSS_INIT = 0x40
 OP_SKETCH, OP_COMPRESS, OP_HALS_STEP, OP_FACTORIZE, OP_REL_ERROR, OP_HALS, OP_SVD_INIT = range(7)
 
 EXPORTS = [
@@ -658,8 +659,9 @@ def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, 
               exact_q=False, ws=None, reg=None, init="random"):
     """Algorithm 1 end to end (rnmf_factorize).  Returns (W, H, report dict).
     reg: optional ridge / LASSO weights (Sec. 3.4; see make_opts).
-    init: "random" (W0, H0 given or uniform from seed) or "svd" (the
-    SVD-based initialization on this run's Q and B)."""
+    init: "random" (W0, H0 given or uniform from seed), "gauss" (W0, H0
+    given or standard normal from seed with the negative entries set to zero)
+    or "svd" (the SVD-based initialization on this run's Q and B)."""
     torch = _torch()
     _need_dev(X, "X"); _rowmajor(X, "X")
     m, n = X.shape
@@ -667,8 +669,10 @@ def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, 
                   exact_q, reg)
     if init == "svd":
         o.flags |= FLAG_SVD_INIT
+    elif init == "gauss":
+        o.flags |= FLAG_GAUSS_INIT
     elif init != "random":
-        raise ValueError("init must be 'random' or 'svd'")
+        raise ValueError("init must be 'random', 'gauss' or 'svd'")
     dt = _fdtype(precision)
     for t, nm in ((omega, "omega"), (W0, "W0"), (H0, "H0")):
         if t is not None:

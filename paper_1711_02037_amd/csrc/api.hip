@@ -129,7 +129,7 @@ rnmf_status check_opts(const rnmf_opts* o, int64_t m, int64_t n, bool need_kmax)
   if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode %d", o->gram_mode);
   if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order %d", o->order);
   if (o->flags & ~(RNMF_FLAG_CHECK_INPUT | RNMF_FLAG_NO_SHIFT | RNMF_FLAG_EXACT_Q | RNMF_FLAG_TRACE |
-                   RNMF_FLAG_SHIFTED_QR3 | RNMF_FLAG_SVD_INIT))
+                   RNMF_FLAG_SHIFTED_QR3 | RNMF_FLAG_SVD_INIT | RNMF_FLAG_GAUSS_INIT))
     return fail(RNMF_ERR_ARG, "unknown flag bits 0x%x", o->flags);
   if (!(o->tol == o->tol)) return fail(RNMF_ERR_ARG, "tol is NaN");
   if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
@@ -1276,6 +1276,8 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   if (ldx < n) return fail(RNMF_ERR_SHAPE, "ldx < n");
   const bool svd = (o->flags & RNMF_FLAG_SVD_INIT) != 0;
   if (svd && (W0 || H0)) return fail(RNMF_ERR_ARG, "RNMF_FLAG_SVD_INIT needs W0 and H0 to be NULL");
+  if (svd && (o->flags & RNMF_FLAG_GAUSS_INIT))
+    return fail(RNMF_ERR_ARG, "RNMF_FLAG_SVD_INIT and RNMF_FLAG_GAUSS_INIT exclude each other");
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
   const Mode md = mode_of(o);
@@ -1312,10 +1314,11 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   if (svd) {
     HIPCHK(launch_svd_init(Q, B, m, n, l, k, W, H, md.dt, vb, s));
   } else {
+    const int idist = (o->flags & RNMF_FLAG_GAUSS_INIT) ? 2 : 1;
     if (W0) HIPCHK(hipMemcpyAsync(W, W0, (size_t)m * k * md.es, hipMemcpyDeviceToDevice, s));
-    else HIPCHK(launch_philox(W, md.dt, m, k, o->seed, 4u, 1, s));
+    else HIPCHK(launch_philox(W, md.dt, m, k, o->seed, 4u, idist, s));
     if (H0) HIPCHK(hipMemcpyAsync(H, H0, (size_t)k * n * md.es, hipMemcpyDeviceToDevice, s));
-    else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, 1, s));
+    else HIPCHK(launch_philox(H, md.dt, k, n, o->seed, 5u, idist, s));
   }
   if ((r = run_init_wt(Q, W, m, k, l, Wt, ib, md, d)) != RNMF_OK) return r;
   HIPCHK(hipEventRecord(ev[1], s));

@@ -55,10 +55,11 @@ __global__ void philox_kernel(T* out, int64_t count, unsigned k0, unsigned k1, u
     unsigned c[4] = {(unsigned)(uint64_t)i, (unsigned)((uint64_t)i >> 32), sid, PHILOX_TAG};
     philox4x32_10(c, k0, k1);
     double v;
-    if (dist == 0) {
+    if (dist == 0 || dist == 2) {
       double u1 = u53(c[0], c[1]) + (1.0 / 9007199254740992.0);  // (0, 1]
       double u2 = u53(c[2], c[3]);
       v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+      if (dist == 2) v = v > 0.0 ? v : 0.0;  // Gaussian with the negative entries set to zero
     } else {
       v = u53(c[0], c[1]);
     }

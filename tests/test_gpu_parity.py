@@ -282,6 +282,33 @@ def test_factorize_generated_init_is_reproducible_and_nonnegative():
     assert a[2]["rel_err"] < 0.2
 
 
+def test_factorize_clipped_gaussian_init():
+    """init="gauss" (the Remark on initialization after Algorithm 1): with
+    max_iter = 0 the factorization returns its start, which must be standard
+    normal entries with the negative ones set to zero: about half exactly
+    zero, the rest a half-normal sample (Kolmogorov-Smirnov at 1e-3), the
+    same for the same seed and different from the uniform start; from that
+    start the sweeps follow the oracle's."""
+    from scipy import stats
+    X, Om, _, _ = problem(1500, 900, 20, 10, 10, 37, dtype=np.float64)
+    W, H, _ = rn.factorize(dev(X), 10, 10, 2, max_iter=0, seed=5, precision="fp64", omega=dev(Om), init="gauss")
+    W2, H2, _ = rn.factorize(dev(X), 10, 10, 2, max_iter=0, seed=5, precision="fp64", omega=dev(Om), init="gauss")
+    Wu, _, _ = rn.factorize(dev(X), 10, 10, 2, max_iter=0, seed=5, precision="fp64", omega=dev(Om))
+    assert torch.equal(W, W2) and torch.equal(H, H2) and not torch.equal(W, Wu)
+    v = np.concatenate([host(W).ravel(), host(H).ravel()])
+    N = v.size
+    zero = np.count_nonzero(v == 0.0)
+    assert v.min() >= 0.0
+    assert abs(zero - N / 2) <= 5 * np.sqrt(N / 4)
+    assert stats.kstest(v[v > 0], stats.halfnorm.cdf).pvalue > 1e-3
+    W0, H0 = host(W), host(H)
+    Wg, Hg, info = rn.factorize(dev(X), 10, 10, 2, max_iter=30, seed=5, precision="fp64", omega=dev(Om),
+                                init="gauss")
+    Wo, Ho, io = o.rhals(X, 10, Om, W0, H0, q=2, max_iter=30)
+    assert abs(info["rel_err"] - io["rel_err"]) <= 1e-10
+    assert relf(host(Wg), Wo) <= 1e-8 and relf(host(Hg), Ho) <= 1e-8
+
+
 def test_factorize_stops_on_tolerance():
     X, Om, W0, H0 = problem(1200, 500, 6, 6, 10, 35, dtype=np.float64)
     W, H, info = rn.factorize(dev(X), 6, 10, 2, max_iter=2000, tol=1e-4, precision="fp64", omega=dev(Om),
