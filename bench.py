@@ -177,11 +177,15 @@ def main():
 
     gb32, ms32 = pass_gbps(X, Q32, "fp32")
     gb16, ms16 = pass_gbps(Xb, Qb, "bf16")
+    rs = read_stream_gbps(torch, X, dev)
     xpass = {"fp32_compress_GBps": round(gb32, 1), "fp32_compress_ms": round(ms32, 4),
              "bf16_compress_GBps": round(gb16, 1), "bf16_compress_ms": round(ms16, 4),
              "frac_of_8TBps": {"fp32": round(gb32 / PEAK_HBM_GBPS, 4), "bf16": round(gb16 / PEAK_HBM_GBPS, 4)},
-             "note": "one rnmf_compress call = pack Q + one pass over X + split reduce"}
-    log(f"X pass: fp32 {gb32:.0f} GB/s, bf16 {gb16:.0f} GB/s")
+             "read_stream_GBps": round(rs, 1),
+             "frac_of_read_stream": {"fp32": round(gb32 / rs, 4), "bf16": round(gb16 / rs, 4)},
+             "note": "one rnmf_compress call = pack Q + one pass over X + split reduce; read_stream_GBps is "
+                     "torch's sum over the same FP32 X (a plain read stream of 2 GB)"}
+    log(f"X pass: fp32 {gb32:.0f} GB/s, bf16 {gb16:.0f} GB/s (read stream {rs:.0f} GB/s)")
 
     # ---- time to 1.01 x FP32 final error --------------------------------------
     ttt = None
@@ -222,6 +226,11 @@ def main():
                 f"forward {b['ms_forward_recorded']:.2f} ms, one-launch forward {b['ms_forward']:.2f} ms, "
                 f"checkpointed backward (every {b['ckpt_every']}) {b['ms_backward_checkpointed']:.2f} ms)")
 
+    # ---- the image-stack workload: iters/s of both forms -------------------------
+    c2 = c2_bench(rn, torch, synth, dev)
+    log(f"stack_32256x2410: bf16 {c2['bf16']['iters_per_s']:.0f} iters/s ({c2['bf16']['sweep_loop_iters_per_s']:.0f} "
+        f"in the sweep loop), fp32 {c2['fp32']['iters_per_s']:.0f} iters/s ({c2['fp32']['sweep_loop_iters_per_s']:.0f})")
+
     # ---- update orders: interleaved and shuffled sweeps (ordered path) --------
     orders = orders_bench(rn, torch, X, Q32, W0, H0, dev)
     log(f"orders: interleaved {orders['interleaved_ms_per_sweep']:.2f} ms/sweep, shuffled "
@@ -259,11 +268,51 @@ def main():
         "batched": batch,
         "backward": back,
         "orders": orders,
+        "stack_32256x2410": c2,
         "xpass": xpass,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def read_stream_gbps(torch, X, dev, reps=10):
+    """GB/s of torch's sum over X: a plain read stream of the same bytes the
+    X passes read, timed with events."""
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    X.sum()
+    e0.record(st)
+    for _ in range(reps):
+        X.sum()
+    e1.record(st)
+    e1.synchronize()
+    return X.numel() * X.element_size() / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+
+def c2_bench(rn, torch, synth, dev, steps=2):
+    """iters/s on the image-stack workload (32,256 x 2,410, k = 16, 500
+    sweeps), BF16 and FP32 forms: whole factorize steps and the sweep loop
+    alone (its launch timed with events inside rnmf_factorize)."""
+    w = synth.workload("stack_32256x2410")
+    Xh, Omh, W0h, H0h, _ = synth.make("stack_32256x2410", threads=16)
+    X, Om = torch.from_numpy(Xh).to(dev), torch.from_numpy(Omh).to(dev)
+    W0, H0 = torch.from_numpy(W0h).to(dev), torch.from_numpy(H0h).to(dev)
+    k, p, q, sw = w["k"], w["p"], w["q"], w["sweeps"]
+    out = {"m": w["m"], "n": w["n"], "k": k, "sweeps": sw}
+    for prec in ("bf16", "fp32"):
+        rn.factorize(X, k, p, q, max_iter=sw, precision=prec, omega=Om, W0=W0, H0=H0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = [rn.factorize(X, k, p, q, max_iter=sw, precision=prec, omega=Om, W0=W0, H0=H0)[2]
+                for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ms_sw = statistics.mean(r["ms_sweeps"] for r in reps)
+        out[prec] = {"iters_per_s": round(sw * steps / el, 1), "ms_per_step": round(el / steps * 1e3, 3),
+                     "sweep_loop_iters_per_s": round(sw / (ms_sw * 1e-3), 1), "ms_qb": round(reps[-1]["ms_qb"], 4),
+                     "rel_err": reps[-1]["rel_err"]}
+    return out
 
 
 def time_to_target(rn, torch, X, Om, W0, H0, k, p, q, sweeps, ws, step, e32_final, cap=400):
