@@ -107,6 +107,7 @@ __global__ __launch_bounds__(256) void gram_sum_kernel(const double* __restrict_
     const int lo = a < c ? a : c, hi = a < c ? c : a;
     // entry (lo, hi) lies in the upper block triangle that every partial holds
     const double* src = gpart + (size_t)lo * LMAX + hi;
+#pragma unroll 8
     for (int p = grp; p < splits; p += 8) s += src[(size_t)p * LMAX * LMAX];
   }
   red[grp][el] = s;
@@ -171,9 +172,23 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G,
   int shifted = 0;
   for (int attempt = (allow_shift == 2) ? 1 : 0; attempt < 2; ++attempt) {
     shifted = attempt;
-    for (int e = t; e < l * l; e += 256) {
-      const int i = e / l, j = e - (e / l) * l;
-      A[i][j] = (j <= i) ? G[e] : 0.0;
+    // eight loads in flight per thread (a plain loop waits for each in turn);
+    // indices past the end read the last entry, which is not stored
+    for (int e0 = t; e0 < l * l; e0 += 256 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        v[u] = G[e < l * l ? e : l * l - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        if (e < l * l) {
+          const int i = e / l, j = e - (e / l) * l;
+          A[i][j] = (j <= i) ? v[u] : 0.0;
+        }
+      }
     }
     for (int i = t; i < l; i += 256) dX[i] = 1.0;
     if (t == 0) fail_s = 0;
