@@ -614,12 +614,6 @@ __global__ __launch_bounds__(256) void ad_fill(double* __restrict__ p, int64_t c
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) p[e] = v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void ad_cast(const double* __restrict__ src, int64_t count, T* __restrict__ dst) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
-    dst[e] = (T)src[e];
-}
-
 unsigned grid_for(int64_t count) {
   int64_t b = (count + 255) / 256;
   if (b > 65535) b = 65535;
@@ -779,12 +773,6 @@ hipError_t ad_symm_run(const double* G, int k, double* M, hipStream_t s) {
 
 hipError_t ad_fill_run(double* p, int64_t count, double v, hipStream_t s) {
   hipLaunchKernelGGL(ad_fill, dim3(grid_for(count)), dim3(256), 0, s, p, count, v);
-  return hipGetLastError();
-}
-
-hipError_t ad_cast_run(const double* src, int64_t count, void* dst, int dt, hipStream_t s) {
-  if (dt == 0) hipLaunchKernelGGL(ad_cast<double>, dim3(grid_for(count)), dim3(256), 0, s, src, count, (double*)dst);
-  else hipLaunchKernelGGL(ad_cast<float>, dim3(grid_for(count)), dim3(256), 0, s, src, count, (float*)dst);
   return hipGetLastError();
 }
 
