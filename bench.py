@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--no-svd-init", action="store_true", help="skip the SVD-based initialization comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (512 uneven problems)")
     ap.add_argument("--no-backward", action="store_true", help="skip the reverse pass through unrolled sweeps")
+    ap.add_argument("--no-stack", action="store_true", help="skip the 32,256 x 2,410 image-stack workload")
+    ap.add_argument("--no-orders", action="store_true", help="skip the update-order timings")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -227,15 +229,20 @@ def main():
                 f"checkpointed backward (every {b['ckpt_every']}) {b['ms_backward_checkpointed']:.2f} ms)")
 
     # ---- the image-stack workload: iters/s of both forms -------------------------
-    c2 = c2_bench(rn, torch, synth, dev)
-    log(f"stack_32256x2410: bf16 {c2['bf16']['iters_per_s']:.0f} iters/s ({c2['bf16']['sweep_loop_iters_per_s']:.0f} "
-        f"in the sweep loop), fp32 {c2['fp32']['iters_per_s']:.0f} iters/s ({c2['fp32']['sweep_loop_iters_per_s']:.0f})")
+    c2 = None
+    if not args.no_stack:
+        c2 = c2_bench(rn, torch, synth, dev)
+        log(f"stack_32256x2410: bf16 {c2['bf16']['iters_per_s']:.0f} iters/s "
+            f"({c2['bf16']['sweep_loop_iters_per_s']:.0f} in the sweep loop), fp32 {c2['fp32']['iters_per_s']:.0f} "
+            f"iters/s ({c2['fp32']['sweep_loop_iters_per_s']:.0f})")
 
     # ---- update orders: interleaved and shuffled sweeps (ordered path) --------
-    orders = orders_bench(rn, torch, X, Q32, W0, H0, dev)
-    log(f"orders: interleaved {orders['interleaved_ms_per_sweep']:.2f} ms/sweep, shuffled "
-        f"{orders['shuffled_ms_per_sweep']:.2f} ms/sweep, blocked list {orders['blocked_list_ms_per_sweep']:.2f} "
-        f"ms/sweep (sweep kernel {orders['sweep_kernel_ms_per_sweep']:.3f})")
+    orders = None
+    if not args.no_orders:
+        orders = orders_bench(rn, torch, X, Q32, W0, H0, dev)
+        log(f"orders: interleaved {orders['interleaved_ms_per_sweep']:.2f} ms/sweep, shuffled "
+            f"{orders['shuffled_ms_per_sweep']:.2f} ms/sweep, blocked list {orders['blocked_list_ms_per_sweep']:.2f} "
+            f"ms/sweep (sweep kernel {orders['sweep_kernel_ms_per_sweep']:.3f})")
 
     # ---- FP64 oracle on the host ---------------------------------------------
     cpu = None
