@@ -1,17 +1,20 @@
 """GPU parity at the full sizes of the paper-shaped workloads, in the launch
 configurations the benchmark times (the streamed X passes with one workgroup
 per CU, the persistent sweep kernel with 256 workgroups and the Q slab in
-registers).  The FP64 oracle receives the device results it needs (Q, B, the
-initial factors) promoted to float64 and recomputes the step from them.
+registers).  Every input the oracle sees comes from the seeded recipe or from
+the oracle itself: the basis Q is the oracle's range finder on the same X and
+Omega, B = Q^T X is formed in FP64 on the host, and both are rounded once to
+FP32 and handed to both sides.
 
   tall 100,000 x 5,000, k = 50, l = 70 (the performance-study shape):
-    - compression B = Q^T X against the product in FP64 on the same Q;
-    - Q orthonormal, and its range captures X as well as the oracle's basis;
+    - the device's Q is orthonormal and captures X as well as the oracle's
+      basis; the device's B = Q^T X on the oracle's Q against the FP64
+      product;
     - one compressed-HALS sweep from identical inputs: W, W~, H each within
-      1e-5 relative (Frobenius) of the oracle's sweep, plain and with the
-      elastic-net rules of Sec. 3.4;
-    - the SVD-based initialization on the device's Q and B, W and H within
-      1e-5 relative of the oracle's.
+      1e-5 relative (Frobenius) of the oracle's sweep, plain, with the
+      elastic-net rules of Sec. 3.4, and in the interleaved update order;
+    - the SVD-based initialization on identical Q and B, W and H within 1e-5
+      relative of the oracle's.
   stack 32,256 x 2,410, k = 16 (the image-stack shape), 500 sweeps:
     - FP32 form: final relative error within 1e-4 of the oracle's;
     - BF16 form: final relative error at most 1.01 x the oracle's.
@@ -77,74 +80,82 @@ def tall():
     return X, Om, W0, H0, w
 
 
-def test_tall_full_size_compress_and_basis(tall):
+@pytest.fixture(scope="module")
+def tall_inputs(tall):
+    """The oracle's basis and compressed data for the tall workload, rounded
+    to FP32: Q32 (m x l), B32 (l x n), and Wt32 = Q32^T W0 (l x k)."""
     X, Om, W0, H0, w = tall
+    Qo = o.range_finder(X.astype(np.float64), Om.astype(np.float64), w["q"])
+    Q32 = Qo.astype(np.float32)
+    B32 = chunked_qtx(Q32.astype(np.float64), X).astype(np.float32)
+    Wt32 = (Q32.astype(np.float64).T @ W0.astype(np.float64)).astype(np.float32)
+    return Qo, Q32, B32, Wt32
+
+
+def test_tall_full_size_compress_and_basis(tall, tall_inputs):
+    X, Om, W0, H0, w = tall
+    Qo, Q32, _, _ = tall_inputs
     k, p, q = w["k"], w["p"], w["q"]
     Xd = dev(X)
     Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
-    B = rn.compress(Xd, Q)
-    Qh, Bh = host(Q), host(B)
+    Qh = host(Q)
     l = Qh.shape[1]
     assert np.linalg.norm(Qh.T @ Qh - np.eye(l)) <= 1e-5
-    assert relf(Bh, chunked_qtx(Qh, X)) <= 1e-5
-    # the oracle's basis (FP64 Householder QR) captures X equally well
-    Qo = o.range_finder(X.astype(np.float64), Om.astype(np.float64), q)
+    # the device's basis captures X as well as the oracle's (FP64 Householder QR)
     cg, co = capture(Qh, X), capture(Qo, X)
     assert abs(cg - co) <= 1e-5 * co
+    # compression on the oracle's basis against the FP64 product
+    B = rn.compress(Xd, dev(Q32))
+    assert relf(host(B), chunked_qtx(Q32.astype(np.float64), X)) <= 1e-5
 
 
-def test_tall_full_size_one_sweep_matches_oracle(tall):
+def _sweep_case(tall, tall_inputs, reg=None, order=None):
     X, Om, W0, H0, w = tall
-    k, p, q = w["k"], w["p"], w["q"]
-    Xd = dev(X)
-    Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
-    B = rn.compress(Xd, Q)
-    del Xd
-    W = dev(W0)
-    H = dev(H0)
-    Wt = rn.compress(W, Q)
-    Qh, Bh, Wh, Wth, Hh = host(Q), host(B), host(W), host(Wt), host(H)
-    rn.hals_step(Q, B, W, Wt, H, nsweeps=1)
-    Wo, Wto, Ho = o.rhals_sweep(Qh, Bh, Wh, Wth, Hh)
+    _, Q32, B32, Wt32 = tall_inputs
+    Q, B, W, Wt, H = dev(Q32), dev(B32), dev(W0), dev(Wt32), dev(H0)
+    f64 = lambda a: a.astype(np.float64)
+    if order is not None:
+        rn.hals_ordered(Q, B, W, Wt, H, [order])
+        Wo, Wto, Ho = o.rhals_sweep_ordered(f64(Q32), f64(B32), f64(W0), f64(Wt32), f64(H0), order)
+    else:
+        rn.hals_step(Q, B, W, Wt, H, nsweeps=1, reg=reg)
+        Wo, Wto, Ho = o.rhals_sweep(f64(Q32), f64(B32), f64(W0), f64(Wt32), f64(H0),
+                                    reg=o.Reg(**reg) if reg else o.NO_REG)
     assert relf(host(W), Wo) <= 1e-5
     assert relf(host(Wt), Wto) <= 1e-5
     assert relf(host(H), Ho) <= 1e-5
     assert host(W).min() >= 0.0 and host(H).min() >= 0.0
 
 
-def test_tall_full_size_regularized_sweep_matches_oracle(tall):
-    # the elastic-net rules (Sec. 3.4) in the same launch configuration
-    X, Om, W0, H0, w = tall
-    k, p, q = w["k"], w["p"], w["q"]
-    Xd = dev(X)
-    Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
-    B = rn.compress(Xd, Q)
-    del Xd
-    W = dev(W0)
-    H = dev(H0)
-    Wt = rn.compress(W, Q)
-    Qh, Bh, Wh, Wth, Hh = host(Q), host(B), host(W), host(Wt), host(H)
-    reg = dict(alpha_w=0.15 * float(np.mean(np.sum(Hh * Hh, axis=1))),
-               alpha_h=0.15 * float(np.mean(np.sum(Wh * Wh, axis=0))),
-               beta_w=0.02 * float(np.mean(np.abs(Qh @ (Bh @ Hh.T)))),
-               beta_h=0.02 * float(np.mean(np.abs(Bh.T @ Wth))))
-    rn.hals_step(Q, B, W, Wt, H, nsweeps=1, reg=reg)
-    Wo, Wto, Ho = o.rhals_sweep(Qh, Bh, Wh, Wth, Hh, reg=o.Reg(**reg))
-    assert relf(host(W), Wo) <= 1e-5
-    assert relf(host(Wt), Wto) <= 1e-5
-    assert relf(host(H), Ho) <= 1e-5
+def test_tall_full_size_one_sweep_matches_oracle(tall, tall_inputs):
+    _sweep_case(tall, tall_inputs)
 
 
-def test_tall_full_size_svd_init_matches_oracle(tall):
-    # the SVD-based initialization on the device's own Q and B
+def test_tall_full_size_regularized_sweep_matches_oracle(tall, tall_inputs):
+    # the elastic-net rules (Sec. 3.4) in the same launch configuration, with
+    # weights set from the problem's own scales
     X, Om, W0, H0, w = tall
-    k, p, q = w["k"], w["p"], w["q"]
-    Xd = dev(X)
-    Q = rn.sketch(Xd, k, p, q, omega=dev(Om))
-    B = rn.compress(Xd, Q)
-    del Xd
-    W, H = rn.svd_init(Q, B, k)
-    Wo, Ho = o.svd_init(host(Q), host(B), k)
+    _, Q32, B32, Wt32 = tall_inputs
+    Q, B, Wt, W, H = (a.astype(np.float64) for a in (Q32, B32, Wt32, W0, H0))
+    reg = dict(alpha_w=0.15 * float(np.mean(np.sum(H * H, axis=1))),
+               alpha_h=0.15 * float(np.mean(np.sum(W * W, axis=0))),
+               beta_w=0.02 * float(np.mean(np.abs(Q @ (B @ H.T)))),
+               beta_h=0.02 * float(np.mean(np.abs(B.T @ Wt))))
+    _sweep_case(tall, tall_inputs, reg=reg)
+
+
+def test_tall_full_size_interleaved_sweep_matches_oracle(tall, tall_inputs):
+    # one sweep in the interleaved order W(:,1) -> H(1,:) -> ... (rnmf_hals_ordered)
+    _sweep_case(tall, tall_inputs, order=rn.order_interleaved(tall[4]["k"]))
+
+
+def test_tall_full_size_svd_init_matches_oracle(tall, tall_inputs):
+    # the SVD-based initialization on identical Q and B
+    X, Om, W0, H0, w = tall
+    _, Q32, B32, _ = tall_inputs
+    k = w["k"]
+    W, H = rn.svd_init(dev(Q32), dev(B32), k)
+    Wo, Ho = o.svd_init(Q32.astype(np.float64), B32.astype(np.float64), k)
     assert relf(host(W), Wo) <= 1e-5 and relf(host(H), Ho) <= 1e-5
     assert host(W).min() >= 0.0 and host(H).min() >= 0.0
 

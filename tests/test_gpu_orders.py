@@ -139,28 +139,3 @@ def test_zero_scale_blocks_are_skipped():
     errs = [relf(a, b) for a, b in zip(got, ref)]
     assert max(errs) <= 1e-10, errs
     assert not got[0][:, 1].any() and not got[2][1, :].any()
-
-
-def test_full_size_interleaved_sweep_fp32():
-    """One interleaved sweep at 100,000 x 5,000 (k = 50, l = 70) on the
-    device's own Q and B, against the oracle's ordered sweep on the same
-    (FP32) inputs."""
-    w = s.workload("tall_100000x5000")
-    m, n, k = w["m"], w["n"], w["k"]
-    X = torch.from_numpy(s.low_rank_rows(m, n, w["rank"], w["seed"], noise_abs=w["noise_abs"],
-                                         dtype=np.float32, threads=16)).to(DEV)
-    Om = dev(s.omega(n, k + w["p"], w["seed"]), np.float32)
-    Qd = rn.sketch(X, k, w["p"], w["q"], omega=Om)
-    Bd = rn.compress(X, Qd)
-    del X
-    W0, H0 = s.init_factors(m, n, k, w["seed"], dtype=np.float32)
-    Wd, Hd = dev(W0, np.float32), dev(H0, np.float32)
-    Wtd = rn.compress(Wd, Qd)
-    Q, B, Wt0 = host(Qd), host(Bd), host(Wtd)
-    order = [rn.order_interleaved(k)]
-    rn.hals_ordered(Qd, Bd, Wd, Wtd, Hd, order)
-    torch.cuda.synchronize()
-    ref = oracle_run(Q, B, W0.astype(np.float64), Wt0, H0.astype(np.float64), order)
-    errs = [relf(host(a), b) for a, b in zip((Wd, Wtd, Hd), ref)]
-    print("full-size interleaved fp32 errors W Wt H", errs, flush=True)
-    assert max(errs) <= 1e-5, errs
