@@ -593,9 +593,31 @@ __device__ __noinline__ void gram_w(const float* __restrict__ W, int64_t m, int 
   float* Wsh = scr;  // GT x (BKM + 1)
   const int gi = t % 16, gj = t / 16;
   double s[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  // The next tile's loads are in flight while the current one is used.  A
+  // load past the tile's last valid element reads that element instead and
+  // is zeroed when stored, so no value is consumed before the next store.
+  float wv[8];
+  int valid = (int)((m < GT ? m : GT) * k);
+  auto fetch = [&](int64_t r0, int cnt) {
+    gcf* base = G(W + r0 * k);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = t + u * BT;
+      wv[u] = base[e < cnt ? e : cnt - 1];
+    }
+  };
+  fetch(0, valid);
   for (int64_t r0 = 0; r0 < m; r0 += GT) {
-    rows_load<8>(Wsh, BKM + 1, G(W), r0, m, GT, k);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t + u * BT >= valid) wv[u] = 0.f;
+    flat_store<8>(wv, Wsh, BKM + 1, k, GT * k);
     lds_sync();
+    if (r0 + GT < m) {
+      const int64_t left = m - (r0 + GT);
+      valid = (int)((left < GT ? left : GT) * k);
+      fetch(r0 + GT, valid);
+    }
     for (int rr = 0; rr < GT; ++rr) {
       double a[2], b[2];
 #pragma unroll
@@ -839,14 +861,37 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
 
 // Columns of W (Algorithm 1): update vector in the compressed space, lift and
 // clip on all rows (Q streamed in RQW-row tiles; the next tile's loads are in
-// flight while the current one is used), map back with FP64 sums.
-__device__ __noinline__ void w_phase(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k, float* Wts,
-                        const float* Ts, const float* Vs, float* vec, float* ws, double* red, float* scr) {
-  constexpr int RQW = 128;  // rows per tile; RQW * BLM / BT = 32 loads per thread
+// flight while the current one is used), map back with FP64 sums.  A tile is
+// fetched with one lane per column of Q (2^LG >= l lanes per row, BT >> LG
+// rows per pass).  Lanes past column l and rows past m load a valid element of
+// Q (column l - 1, row m - 1) into LDS slots that the lift and the map-back
+// never read with a nonzero weight, so the loads need no selects and all of a
+// tile's loads are in flight together.
+template <int LG>
+__device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k,
+                                       float* Wts, const float* Ts, const float* Vs, float* vec, float* ws,
+                                       double* red, float* scr) {
+  constexpr int RP = BT >> LG;   // rows per pass
+  constexpr int CNT = RQW / RP;  // loads per thread per tile
+  static_assert(CNT * RP == RQW && (1 << LG) <= P1 - 1, "tile shape");
   const int t = threadIdx.x;
   float* Qs = scr;  // RQW x P1
   const int a = t & 63, g = t >> 6;
+  const int c = t & ((1 << LG) - 1), i0 = t >> LG;
+  const int cq = c < l ? c : l - 1;
+  float* qst = Qs + i0 * P1 + c;
   const int ntile = (int)((m + RQW - 1) / RQW);
+  gcf* Qg = G(Q);
+  auto fetch = [&](float(&v)[CNT], int64_t r0) {
+    const int64_t left = m - 1 - r0;
+    const int lim = left < RQW - 1 ? (int)left : RQW - 1;  // last row of the tile
+    gcf* base = Qg + r0 * l + cq;
+#pragma unroll
+    for (int s = 0; s < CNT; ++s) {
+      const int i = i0 + s * RP;
+      v[s] = base[(i < lim ? i : lim) * l];
+    }
+  };
   for (int j = 0; j < k; ++j) {
     const float d = Vs[j * BKM + j];
     if (!(d > 0.f)) continue;
@@ -864,25 +909,23 @@ __device__ __noinline__ void w_phase(const float* __restrict__ Q, float* __restr
       }
       vec[t] = v;
     }
-    float qv[32];
-    flat_fetch<32>(qv, G(Q), (int)((m < RQW ? m : RQW) * l));
+    float qv[CNT];
+    fetch(qv, 0);
     double macc = 0.0;
     for (int ti = 0; ti < ntile; ++ti) {
       const int64_t r0 = (int64_t)ti * RQW;
-      flat_store<32>(qv, Qs, P1, l, RQW * l);
+#pragma unroll
+      for (int s = 0; s < CNT; ++s) qst[s * RP * P1] = qv[s];
       lds_sync();  // Qs (and, the first time, vec) visible
-      if (ti + 1 < ntile) {
-        const int64_t left = m - (r0 + RQW);
-        flat_fetch<32>(qv, G(Q + (r0 + RQW) * l), (int)((left < RQW ? left : RQW) * l));
-      }
+      if (ti + 1 < ntile) fetch(qv, r0 + RQW);
       if (t < RQW) {
         float u0 = 0.f, u1 = 0.f;
-        int c = 0;
-        for (; c + 2 <= l; c += 2) {
-          u0 = fmaf(Qs[t * P1 + c], vec[c], u0);
-          u1 = fmaf(Qs[t * P1 + c + 1], vec[c + 1], u1);
+        int cc = 0;
+        for (; cc + 2 <= l; cc += 2) {
+          u0 = fmaf(Qs[t * P1 + cc], vec[cc], u0);
+          u1 = fmaf(Qs[t * P1 + cc + 1], vec[cc + 1], u1);
         }
-        for (; c < l; ++c) u0 = fmaf(Qs[t * P1 + c], vec[c], u0);
+        for (; cc < l; ++cc) u0 = fmaf(Qs[t * P1 + cc], vec[cc], u0);
         const float w = (r0 + t < m) ? clipf(u0 + u1) : 0.f;
         ws[t] = w;
         if (r0 + t < m) GW(W)[(r0 + t) * k + j] = w;
@@ -901,6 +944,13 @@ __device__ __noinline__ void w_phase(const float* __restrict__ Q, float* __restr
     lds_sync();
   }
   __syncthreads();  // W is read next by other threads of the workgroup
+}
+__device__ __forceinline__ void w_phase(const float* Q, float* W, int64_t m, int l, int k, float* Wts, const float* Ts,
+                                        const float* Vs, float* vec, float* ws, double* red, float* scr) {
+  if (l <= 32)
+    w_phase_t<5>(Q, W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
+  else
+    w_phase_t<6>(Q, W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
 }
 
 // ||X - W H||_F^2 and ||X||_F^2 (FP64 sums, fixed order) for thread 0.
