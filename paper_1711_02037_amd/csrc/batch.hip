@@ -33,7 +33,7 @@ constexpr int OFF_T = OFF_WT + BLM * BKM;        // T: BLM x BKM
 constexpr int OFF_V = OFF_T + BLM * BKM;         // V: BKM x BKM
 constexpr int OFF_S = OFF_V + BKM * BKM;         // S: BKM x BKM
 constexpr int OFF_VEC = OFF_S + BKM * BKM;       // update vector: BLM
-constexpr int RQW = 128;                         // Q rows per tile (W phase)
+constexpr int RQW = 256;                         // most Q rows per tile (W phase)
 constexpr int OFF_WS = OFF_VEC + BLM;            // lifted column tile: RQW
 constexpr int OFF_RED = OFF_WS + RQW;            // doubles: 2 x BT (2 floats each)
 constexpr int OFF_SCR = OFF_RED + 2 * 2 * BT;    // scratch
@@ -44,9 +44,8 @@ constexpr int SCR_CHOL_D = 2 * BLM * P1;
 constexpr int SCR_AT = SCR_CHOL_D + 2 * 2 * BLM;
 constexpr int SCR_FLOATS = SCR_AT + BLM * BLM;
 constexpr int LDS_FLOATS = OFF_SCR + SCR_FLOATS;
-static_assert(RQW * P1 <= SCR_FLOATS, "W-phase Q tile");
 static_assert(256 * 17 <= SCR_AT, "Cholesky QR apply tile below the factor");
-static_assert(4 * BLM <= 2 * BT, "map-back partials fit the reduction buffer");
+static_assert(8 * BLM <= 2 * BT, "map-back partials fit the reduction buffer");
 static_assert(OFF_RED % 2 == 0 && OFF_SCR % 2 == 0 && SCR_CHOL_D % 2 == 0, "FP64 alignment");
 static_assert(256 * (NCX + 1) + NCX * BLM <= SCR_FLOATS, "X A tiles");
 static_assert(MTZ * (4 * 64 + 1) + MTZ * BLM <= SCR_FLOATS, "X^T Q tiles");
@@ -152,6 +151,60 @@ __device__ __forceinline__ void pow2_store(const float (&v)[CNT], float* dst, in
     if (e < R * C) dst[(e >> lg) * dp + (e & (C - 1))] = v[s];
   }
 }
+// Fetches issued one tile ahead of their use: every load reads a valid
+// element (a flat index past the tile's valid count reads the last valid
+// element; a pow2 row or column past the matrix reads its last row or column)
+// and carries no select, so no load is waited for before the tile is stored.
+// The stores then write zero where the plain fetches above would have loaded
+// zero.
+template <int CNT>
+__device__ __forceinline__ void flat_fetch_ahead(float (&v)[CNT], gcf* base, int valid) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    const int e = t + s * BT;
+    v[s] = base[e < valid ? e : valid - 1];
+  }
+}
+template <int CNT>
+__device__ __forceinline__ void flat_store_valid(float (&v)[CNT], int valid, float* dst, int dp, int C, int total) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s)
+    if (t + s * BT >= valid) v[s] = 0.f;
+  flat_store<CNT>(v, dst, dp, C, total);
+}
+template <int CNT>
+__device__ __forceinline__ void pow2_fetch_ahead(float (&v)[CNT], gcf* src, int64_t sp, int64_t r0, int64_t rows,
+                                                 int64_t c0, int64_t cols, int R, int lg) {
+  const int t = threadIdx.x;
+  const int C = 1 << lg;
+  const int c = t & (C - 1), i0 = t >> lg, di = BT >> lg;
+  const int64_t rl = rows - r0;
+  const int rmax = (int)(rl < R ? rl : R);
+  gcf* base = src + r0 * sp + (c0 + c < cols ? c0 + c : cols - 1);
+#pragma unroll
+  for (int s = 0; s < CNT; ++s) {
+    const int i = i0 + s * di;
+    v[s] = base[(int64_t)(i < rmax ? i : rmax - 1) * sp];
+  }
+}
+// pow2_store of a pow2_fetch_ahead tile: zero in the rows past rows - r0 and
+// the columns past cols - c0.
+template <int CNT>
+__device__ __forceinline__ void pow2_store_valid(float (&v)[CNT], int64_t r0, int64_t rows, int64_t c0, int64_t cols,
+                                                 float* dst, int dp, int R, int lg) {
+  const int t = threadIdx.x;
+  const int C = 1 << lg;
+  const int c = t & (C - 1), i0 = t >> lg, di = BT >> lg;
+  const int64_t rl = rows - r0;
+  const int rmax = (int)(rl < R ? rl : R);
+  const bool colok = c0 + c < cols;
+#pragma unroll
+  for (int s = 0; s < CNT; ++s)
+    if (!(colok && i0 + s * di < rmax)) v[s] = 0.f;
+  pow2_store<CNT>(v, dst, dp, R, lg);
+}
 __device__ __forceinline__ int ilog2(int x) { return 31 - __builtin_clz(x); }
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
@@ -203,12 +256,16 @@ __device__ __noinline__ void xa_pass_t(const float* __restrict__ X, int64_t ldx,
     if (e % LC >= l) As[e] = 0.f;       // padding columns, never written below
   const int nr = (int)((m + RT - 1) / RT), nc = (int)((n + NCX - 1) / NCX);
   float xv[XCNT], av[ACNT];
+  int64_t fr0 = 0, fc0 = 0;  // the fetched chunk
+  int avalid = 0;
 #define XA_FETCH(qq)                                                                     \
   do {                                                                                   \
-    const int64_t r0_ = (int64_t)((qq) / nc) * RT, c0_ = (int64_t)((qq) % nc) * NCX;   \
-    const int64_t left_ = n - c0_;                                                       \
-    pow2_fetch<XCNT>(xv, G(X), ldx, r0_, m, c0_, n, RT, 5);                              \
-    flat_fetch<ACNT>(av, G(A + c0_ * l), (int)((left_ < NCX ? left_ : NCX) * l));       \
+    fr0 = (int64_t)((qq) / nc) * RT;                                                     \
+    fc0 = (int64_t)((qq) % nc) * NCX;                                                    \
+    const int64_t left_ = n - fc0;                                                       \
+    avalid = (int)((left_ < NCX ? left_ : NCX) * l);                                     \
+    pow2_fetch_ahead<XCNT>(xv, G(X), ldx, fr0, m, fc0, n, RT, 5);                        \
+    flat_fetch_ahead<ACNT>(av, G(A + fc0 * l), avalid);                                  \
   } while (0)
   XA_FETCH(0);
   double acc[4][4];
@@ -217,8 +274,8 @@ __device__ __noinline__ void xa_pass_t(const float* __restrict__ X, int64_t ldx,
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
   for (int qq = 0; qq < nr * nc; ++qq) {
-    pow2_store<XCNT>(xv, Xs, NCX + 1, RT, 5);
-    flat_store<ACNT>(av, As, LC, l, NCX * l);
+    pow2_store_valid<XCNT>(xv, fr0, m, fc0, n, Xs, NCX + 1, RT, 5);
+    flat_store_valid<ACNT>(av, avalid, As, LC, l, NCX * l);
     lds_sync();
     if (qq + 1 < nr * nc) XA_FETCH(qq + 1);
     float s[4][4];
@@ -288,12 +345,16 @@ __device__ __noinline__ void xtq_pass_t(const float* __restrict__ X, int64_t ldx
     if (e % LC >= l) Qs[e] = 0.f;     // padding columns, never written below
   const int ncb = (int)((n + NZ - 1) / NZ), nrb = (int)((m + MTZ - 1) / MTZ);
   float xv[XCNT], qv[QCNT];
+  int64_t fr0 = 0, fc0 = 0;  // the fetched chunk
+  int qvalid = 0;
 #define XTQ_FETCH(qq)                                                                    \
   do {                                                                                   \
-    const int64_t c0_ = (int64_t)((qq) / nrb) * NZ, r0_ = (int64_t)((qq) % nrb) * MTZ;  \
-    const int64_t left_ = m - r0_;                                                       \
-    pow2_fetch<XCNT>(xv, G(X), ldx, r0_, m, c0_, n, MTZ, lgz);                           \
-    flat_fetch<QCNT>(qv, G(Q + r0_ * l), (int)((left_ < MTZ ? left_ : MTZ) * l));       \
+    fc0 = (int64_t)((qq) / nrb) * NZ;                                                    \
+    fr0 = (int64_t)((qq) % nrb) * MTZ;                                                   \
+    const int64_t left_ = m - fr0;                                                       \
+    qvalid = (int)((left_ < MTZ ? left_ : MTZ) * l);                                     \
+    pow2_fetch_ahead<XCNT>(xv, G(X), ldx, fr0, m, fc0, n, MTZ, lgz);                     \
+    flat_fetch_ahead<QCNT>(qv, G(Q + fr0 * l), qvalid);                                  \
   } while (0)
   XTQ_FETCH(0);
   double acc[4][4];
@@ -302,8 +363,8 @@ __device__ __noinline__ void xtq_pass_t(const float* __restrict__ X, int64_t ldx
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
   for (int qq = 0; qq < ncb * nrb; ++qq) {
-    pow2_store<XCNT>(xv, Xs, NZ + 1, MTZ, lgz);
-    flat_store<QCNT>(qv, Qs, LC, l, MTZ * l);
+    pow2_store_valid<XCNT>(xv, fr0, m, fc0, n, Xs, NZ + 1, MTZ, lgz);
+    flat_store_valid<QCNT>(qv, qvalid, Qs, LC, l, MTZ * l);
     lds_sync();
     if (qq + 1 < ncb * nrb) XTQ_FETCH(qq + 1);
     float s[4][4];
@@ -781,16 +842,21 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
+  // the next tile's loads are in flight while the current one is used
+  float zv[16], hv[8];
+  int zvalid = 0;
+  auto fetch = [&](int64_t c0) {
+    const int64_t left = n - c0;
+    zvalid = (int)((left < 64 ? left : 64) * l);
+    flat_fetch_ahead<16>(zv, G(Bt + c0 * l), zvalid);
+    pow2_fetch_ahead<8>(hv, G(H), n, 0, k, c0, n, k, 6);
+  };
+  fetch(0);
   for (int64_t c0 = 0; c0 < n; c0 += 64) {
-    {
-      float zv[16], hv[8];
-      const int64_t left = n - c0;
-      flat_fetch<16>(zv, G(Bt + c0 * l), (int)((left < 64 ? left : 64) * l));
-      pow2_fetch<8>(hv, G(H), n, 0, k, c0, n, k, 6);
-      flat_store<16>(zv, Zs, P1, l, 64 * l);
-      pow2_store<8>(hv, Hs, 65, k, 6);
-    }
+    flat_store_valid<16>(zv, zvalid, Zs, P1, l, 64 * l);
+    pow2_store_valid<8>(hv, 0, k, c0, n, Hs, 65, k, 6);
     lds_sync();
+    if (c0 + 64 < n) fetch(c0 + 64);
     float s[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -860,36 +926,40 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
 }
 
 // Columns of W (Algorithm 1): update vector in the compressed space, lift and
-// clip on all rows (Q streamed in RQW-row tiles; the next tile's loads are in
+// clip on all rows (Q streamed in RQ-row tiles; the next tile's loads are in
 // flight while the current one is used), map back with FP64 sums.  A tile is
 // fetched with one lane per column of Q (2^LG >= l lanes per row, BT >> LG
-// rows per pass).  Lanes past column l and rows past m load a valid element of
-// Q (column l - 1, row m - 1) into LDS slots that the lift and the map-back
-// never read with a nonzero weight, so the loads need no selects and all of a
-// tile's loads are in flight together.
+// rows per pass) and held in LDS at pitch 2^LG + 1: 256 rows when l <= 32,
+// 128 otherwise, so that every thread lifts at most one row and maps back 32.
+// Lanes past column l and rows past m load a valid element of Q (column
+// l - 1, row m - 1) into LDS slots that the lift and the map-back never read
+// with a nonzero weight, so the loads need no selects and all of a tile's
+// loads are in flight together.
 template <int LG>
 __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k,
                                        float* Wts, const float* Ts, const float* Vs, float* vec, float* ws,
                                        double* red, float* scr) {
-  constexpr int RP = BT >> LG;   // rows per pass
-  constexpr int CNT = RQW / RP;  // loads per thread per tile
-  static_assert(CNT * RP == RQW && (1 << LG) <= P1 - 1, "tile shape");
+  constexpr int C = 1 << LG;             // lanes per row of the tile
+  constexpr int PQ = C + 1;              // LDS pitch
+  constexpr int RQ = LG == 5 ? 256 : 128;  // rows per tile
+  constexpr int RP = BT >> LG;           // rows per pass, and map-back groups
+  constexpr int CNT = RQ / RP;           // loads per thread per tile
+  static_assert(CNT * RP == RQ && RQ <= RQW && RQ * PQ <= SCR_FLOATS && RP * BLM <= 2 * BT, "tile shape");
   const int t = threadIdx.x;
-  float* Qs = scr;  // RQW x P1
-  const int a = t & 63, g = t >> 6;
-  const int c = t & ((1 << LG) - 1), i0 = t >> LG;
+  float* Qs = scr;  // RQ x PQ
+  const int c = t & (C - 1), i0 = t >> LG;  // fetch lane; map-back column c, group i0
   const int cq = c < l ? c : l - 1;
-  float* qst = Qs + i0 * P1 + c;
-  const int ntile = (int)((m + RQW - 1) / RQW);
+  float* qst = Qs + i0 * PQ + c;
+  const int ntile = (int)((m + RQ - 1) / RQ);
   gcf* Qg = G(Q);
   auto fetch = [&](float(&v)[CNT], int64_t r0) {
     const int64_t left = m - 1 - r0;
-    const int lim = left < RQW - 1 ? (int)left : RQW - 1;  // last row of the tile
-    gcf* base = Qg + r0 * l + cq;
+    const int lim = left < RQ - 1 ? (int)left : RQ - 1;  // last row of the tile
+    gcf* base = Qg + r0 * l;                              // the same for every lane
 #pragma unroll
     for (int s = 0; s < CNT; ++s) {
       const int i = i0 + s * RP;
-      v[s] = base[(i < lim ? i : lim) * l];
+      v[s] = base[(unsigned)((i < lim ? i : lim) * l + cq)];
     }
   };
   for (int j = 0; j < k; ++j) {
@@ -913,34 +983,39 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
     fetch(qv, 0);
     double macc = 0.0;
     for (int ti = 0; ti < ntile; ++ti) {
-      const int64_t r0 = (int64_t)ti * RQW;
+      const int64_t r0 = (int64_t)ti * RQ;
 #pragma unroll
-      for (int s = 0; s < CNT; ++s) qst[s * RP * P1] = qv[s];
+      for (int s = 0; s < CNT; ++s) qst[s * RP * PQ] = qv[s];
       lds_sync();  // Qs (and, the first time, vec) visible
-      if (ti + 1 < ntile) fetch(qv, r0 + RQW);
-      if (t < RQW) {
+      if (ti + 1 < ntile) fetch(qv, r0 + RQ);
+      if (t < RQ) {
         float u0 = 0.f, u1 = 0.f;
         int cc = 0;
         for (; cc + 2 <= l; cc += 2) {
-          u0 = fmaf(Qs[t * P1 + cc], vec[cc], u0);
-          u1 = fmaf(Qs[t * P1 + cc + 1], vec[cc + 1], u1);
+          u0 = fmaf(Qs[t * PQ + cc], vec[cc], u0);
+          u1 = fmaf(Qs[t * PQ + cc + 1], vec[cc + 1], u1);
         }
-        for (; cc < l; ++cc) u0 = fmaf(Qs[t * P1 + cc], vec[cc], u0);
+        for (; cc < l; ++cc) u0 = fmaf(Qs[t * PQ + cc], vec[cc], u0);
         const float w = (r0 + t < m) ? clipf(u0 + u1) : 0.f;
         ws[t] = w;
         if (r0 + t < m) GW(W)[(r0 + t) * k + j] = w;
       }
       lds_sync();
-      if (a < l) {
+      if (c < l) {
         float p = 0.f;
-        for (int rr = g; rr < RQW; rr += 4) p = fmaf(Qs[rr * P1 + a], ws[rr], p);
+        for (int rr = i0; rr < RQ; rr += RP) p = fmaf(Qs[rr * PQ + c], ws[rr], p);
         macc += (double)p;
       }
       lds_sync();  // Qs and ws are overwritten next
     }
-    red[g * BLM + a] = macc;
+    red[i0 * BLM + c] = macc;
     lds_sync();
-    if (t < l) Wts[t * BKM + j] = (float)((red[t] + red[BLM + t]) + (red[2 * BLM + t] + red[3 * BLM + t]));
+    if (t < l) {
+      double v = (red[t] + red[BLM + t]) + (red[2 * BLM + t] + red[3 * BLM + t]);
+      if (RP == 8)
+        v += (red[4 * BLM + t] + red[5 * BLM + t]) + (red[6 * BLM + t] + red[7 * BLM + t]);
+      Wts[t * BKM + j] = (float)v;
+    }
     lds_sync();
   }
   __syncthreads();  // W is read next by other threads of the workgroup
