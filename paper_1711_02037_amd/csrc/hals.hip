@@ -63,30 +63,67 @@ __global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, cons
 // Columns of W, one thread per row r: the row and V live in LDS (FP64); for
 // each column j the update uses the row as already updated (Gauss-Seidel).
 // Regularized rule (Sec. 3.4): scale V_jj + aw, numerator - bw - aw W(r, j).
+// The row of W is loaded with all its loads in flight, and T(r, :) is read
+// eight columns ahead of its use; a thread past the last row reads row m - 1
+// (so no load needs a select) and writes nothing.
 template <typename T>
 __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, const double* __restrict__ V,
                                                    T* __restrict__ W, int64_t m, int k, double aw, double bw) {
   __shared__ double Vs[KMAX * KMAX];
   __shared__ double ws[KMAX][128];
-  for (int e = threadIdx.x; e < k * k; e += 128) Vs[e] = V[e];
+  for (int e0 = threadIdx.x; e0 < k * k; e0 += 8 * 128) {  // eight loads in flight
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + i * 128;
+      v[i] = V[e < k * k ? e : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (e0 + i * 128 < k * k) Vs[e0 + i * 128] = v[i];
+  }
   const int t = threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * 128 + t;
   const bool live = r < m;
-  for (int p = 0; p < k; ++p) ws[p][t] = live ? (double)W[r * k + p] : 0.0;
+  const T* wrow = W + (live ? r : m - 1) * k;
+  const T* trow = Tm + (live ? r : m - 1) * k;
+  {
+    T v[KMAX];
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p) v[p] = wrow[p < k ? p : k - 1];
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p)
+      if (p < k) ws[p][t] = (double)v[p];
+  }
   __syncthreads();
   if (!live) return;
-  for (int j = 0; j < k; ++j) {
-    const double d = Vs[j * k + j] + aw;
-    if (!(d > 0.0)) continue;
-    double s0 = 0.0, s1 = 0.0;
-    int p = 0;
-    for (; p + 2 <= k; p += 2) {
-      s0 = fma(ws[p][t], Vs[p * k + j], s0);
-      s1 = fma(ws[p + 1][t], Vs[(p + 1) * k + j], s1);
+  T tc[8], tn[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tc[i] = trow[i < k ? i : k - 1];
+  for (int j0 = 0; j0 < k; j0 += 8) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int jn = j0 + 8 + i;
+      tn[i] = trow[jn < k ? jn : k - 1];
     }
-    for (; p < k; ++p) s0 = fma(ws[p][t], Vs[p * k + j], s0);
-    const double num = ((double)Tm[r * k + j] - (s0 + s1)) - fma(aw, ws[j][t], bw);
-    ws[j][t] = (double)clip0h<T>((T)(ws[j][t] + num / d));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = j0 + i;
+      if (j >= k) break;
+      const double d = Vs[j * k + j] + aw;
+      if (!(d > 0.0)) continue;
+      double s0 = 0.0, s1 = 0.0;
+      int p = 0;
+      for (; p + 2 <= k; p += 2) {
+        s0 = fma(ws[p][t], Vs[p * k + j], s0);
+        s1 = fma(ws[p + 1][t], Vs[(p + 1) * k + j], s1);
+      }
+      for (; p < k; ++p) s0 = fma(ws[p][t], Vs[p * k + j], s0);
+      const double num = ((double)tc[i] - (s0 + s1)) - fma(aw, ws[j][t], bw);
+      ws[j][t] = (double)clip0h<T>((T)(ws[j][t] + num / d));
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tc[i] = tn[i];
   }
   for (int q = 0; q < k; ++q) W[r * k + q] = (T)ws[q][t];
 }
