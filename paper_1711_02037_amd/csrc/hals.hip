@@ -60,30 +60,32 @@ __global__ __launch_bounds__(256) void hrow_kernel(const T* __restrict__ R, cons
   if (lane < k) H[(int64_t)lane * n + c] = (T)h;
 }
 
-// Columns of W, one thread per row r: the row and V live in LDS (FP64); for
+// Columns of W, one thread per row r: V (FP64) and the row (in T, which
+// holds every value the update produces exactly) live in LDS, sized for k; for
 // each column j the update uses the row as already updated (Gauss-Seidel).
 // Regularized rule (Sec. 3.4): scale V_jj + aw, numerator - bw - aw W(r, j).
 // The row of W is loaded with all its loads in flight, and T(r, :) is read
 // eight columns ahead of its use; a thread past the last row reads row m - 1
 // (so no load needs a select) and writes nothing.
-template <typename T>
-__global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, const double* __restrict__ V,
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void wrow_kernel(const T* __restrict__ Tm, const double* __restrict__ V,
                                                    T* __restrict__ W, int64_t m, int k, double aw, double bw) {
-  __shared__ double Vs[KMAX * KMAX];
-  __shared__ double ws[KMAX][128];
-  for (int e0 = threadIdx.x; e0 < k * k; e0 += 8 * 128) {  // eight loads in flight
+  extern __shared__ double wr_lds[];
+  double* Vs = wr_lds;        // k x k
+  T* ws = (T*)(wr_lds + k * k);  // k x NT: entry (p, t) at p * NT + t
+  for (int e0 = threadIdx.x; e0 < k * k; e0 += 8 * NT) {  // eight loads in flight
     double v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int e = e0 + i * 128;
+      const int e = e0 + i * NT;
       v[i] = V[e < k * k ? e : 0];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-      if (e0 + i * 128 < k * k) Vs[e0 + i * 128] = v[i];
+      if (e0 + i * NT < k * k) Vs[e0 + i * NT] = v[i];
   }
   const int t = threadIdx.x;
-  const int64_t r = (int64_t)blockIdx.x * 128 + t;
+  const int64_t r = (int64_t)blockIdx.x * NT + t;
   const bool live = r < m;
   const T* wrow = W + (live ? r : m - 1) * k;
   const T* trow = Tm + (live ? r : m - 1) * k;
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, con
     for (int p = 0; p < KMAX; ++p) v[p] = wrow[p < k ? p : k - 1];
 #pragma unroll
     for (int p = 0; p < KMAX; ++p)
-      if (p < k) ws[p][t] = (double)v[p];
+      if (p < k) ws[p * NT + t] = v[p];
   }
   __syncthreads();
   if (!live) return;
@@ -115,17 +117,18 @@ __global__ __launch_bounds__(128) void wrow_kernel(const T* __restrict__ Tm, con
       double s0 = 0.0, s1 = 0.0;
       int p = 0;
       for (; p + 2 <= k; p += 2) {
-        s0 = fma(ws[p][t], Vs[p * k + j], s0);
-        s1 = fma(ws[p + 1][t], Vs[(p + 1) * k + j], s1);
+        s0 = fma((double)ws[p * NT + t], Vs[p * k + j], s0);
+        s1 = fma((double)ws[(p + 1) * NT + t], Vs[(p + 1) * k + j], s1);
       }
-      for (; p < k; ++p) s0 = fma(ws[p][t], Vs[p * k + j], s0);
-      const double num = ((double)tc[i] - (s0 + s1)) - fma(aw, ws[j][t], bw);
-      ws[j][t] = (double)clip0h<T>((T)(ws[j][t] + num / d));
+      for (; p < k; ++p) s0 = fma((double)ws[p * NT + t], Vs[p * k + j], s0);
+      const double wj = (double)ws[j * NT + t];
+      const double num = ((double)tc[i] - (s0 + s1)) - fma(aw, wj, bw);
+      ws[j * NT + t] = clip0h<T>((T)(wj + num / d));
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) tc[i] = tn[i];
   }
-  for (int q = 0; q < k; ++q) W[r * k + q] = (T)ws[q][t];
+  for (int q = 0; q < k; ++q) W[r * k + q] = ws[q * NT + t];
 }
 
 // Hp (lp x ldp, zero padded) = H (k x n): the small operand of X H^T in the
@@ -181,14 +184,35 @@ hipError_t launch_hrow(const void* R, const double* S, void* H, int64_t n, int k
   return hipGetLastError();
 }
 
+// 256 rows per workgroup where V and the rows fit in 128 KB of LDS (at most
+// 96 KB with 128 rows, for any k <= KMAX).
+template <typename T>
+static hipError_t wrow_t(const T* Tm, const double* V, T* W, int64_t m, int k, double aw, double bw,
+                         hipStream_t s) {
+  const size_t v_bytes = (size_t)k * k * sizeof(double);
+  const size_t b256 = v_bytes + (size_t)k * 256 * sizeof(T), b128 = v_bytes + (size_t)k * 128 * sizeof(T);
+  hipError_t e;
+  if (b256 <= 128 * 1024) {
+    if ((e = hipFuncSetAttribute((const void*)wrow_kernel<T, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)b256)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((wrow_kernel<T, 256>), dim3((unsigned)ceil_div(m, 256)), dim3(256), b256, s, Tm, V, W, m, k,
+                       aw, bw);
+  } else {
+    if ((e = hipFuncSetAttribute((const void*)wrow_kernel<T, 128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)b128)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((wrow_kernel<T, 128>), dim3((unsigned)ceil_div(m, 128)), dim3(128), b128, s, Tm, V, W, m, k,
+                       aw, bw);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_wrow(const void* Tm, const double* V, void* W, int64_t m, int k, double aw, double bw, int dt,
                        hipStream_t s) {
-  dim3 grid((unsigned)ceil_div(m, 128));
-  if (dt == 0)
-    hipLaunchKernelGGL(wrow_kernel<double>, grid, dim3(128), 0, s, (const double*)Tm, V, (double*)W, m, k, aw, bw);
-  else
-    hipLaunchKernelGGL(wrow_kernel<float>, grid, dim3(128), 0, s, (const float*)Tm, V, (float*)W, m, k, aw, bw);
-  return hipGetLastError();
+  if (k < 1 || k > KMAX) return hipErrorInvalidValue;
+  if (dt == 0) return wrow_t((const double*)Tm, V, (double*)W, m, k, aw, bw, s);
+  return wrow_t((const float*)Tm, V, (float*)W, m, k, aw, bw, s);
 }
 
 hipError_t launch_pad(const void* H, int k, int64_t n, int lp, int64_t ldp, void* Hp, int dt, hipStream_t s) {
