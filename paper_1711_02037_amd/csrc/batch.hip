@@ -88,8 +88,7 @@ __device__ __forceinline__ gf* GW(float* p) { return (gf*)p; }
 //   pow2: an R x 2^lg tile of a row-major matrix with row pitch sp (2^lg <=
 //         BT: a thread keeps its column and steps down BT >> lg rows).
 template <int CNT>
-__device__ __forceinline__ void flat_fetch(float (&v)[CNT], gcf* base, int valid) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void flat_fetch(float (&v)[CNT], gcf* base, int valid, int t = threadIdx.x) {
 #pragma unroll
   for (int s = 0; s < CNT; ++s) {
     const int e = t + s * BT;
@@ -99,8 +98,8 @@ __device__ __forceinline__ void flat_fetch(float (&v)[CNT], gcf* base, int valid
   }
 }
 template <int CNT>
-__device__ __forceinline__ void flat_store(const float (&v)[CNT], float* dst, int dp, int C, int total) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void flat_store(const float (&v)[CNT], float* dst, int dp, int C, int total,
+                                           int t = threadIdx.x) {
   // element t + s * BT: row i, column c; each step adds BT = qs * C + rs
   int i = t / C, c = t - (t / C) * C;
   const int qs = BT / C, rs = BT - (BT / C) * C;
@@ -770,10 +769,16 @@ __device__ __noinline__ void h_phase_t(const float* __restrict__ Bt, float* __re
   }
   for (int64_t c0 = 0; c0 < n; c0 += NCT) {
     {
+      // The thread index goes through an empty asm statement once per tile,
+      // so the tile's 32 element positions are recomputed here rather than
+      // hoisted out of the loop, where they would stay live across the
+      // column updates (and be spilled).
+      int tt = t;
+      asm volatile("" : "+v"(tt));
       float zv[32];
       const int64_t left = n - c0;
-      flat_fetch<32>(zv, G(Bt + c0 * l), (int)((left < NCT ? left : NCT) * l));
-      flat_store<32>(zv, Zs, pz, l, NCT * l);
+      flat_fetch<32>(zv, G(Bt + c0 * l), (int)((left < NCT ? left : NCT) * l), tt);
+      flat_store<32>(zv, Zs, pz, l, NCT * l, tt);
     }
     lds_sync();
     const int64_t c = c0 + t;
