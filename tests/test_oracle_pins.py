@@ -267,6 +267,35 @@ def test_rhals_sweep_lowdim_gram_is_compressed_minimiser():
     assert np.allclose(Hn, Hb, atol=1e-10)
 
 
+def test_rhals_sweep_mixed_gram_is_proximal_compressed_minimiser():
+    # GRAM_MIXED (the note after the rHALS H rule in Sec. 3.2): numerator from
+    # the compressed Gram W~^T W~, scale (W^T W)_jj.  That update is the exact
+    # minimiser over h >= 0 of the compressed residual cost plus a proximal
+    # term, 1/2 ||Rt - w~_j h^T||^2 + 1/2 rho ||h - h_old||^2 with
+    # rho = ||w_j||^2 - ||w~_j||^2 >= 0 (the part of W(:,j) outside range(Q)).
+    # Solved here per column by scipy's NNLS on the stacked system
+    # [w~_j; sqrt(rho)] h = [Rt(:, c); sqrt(rho) h_old(c)].  Swapping the
+    # numerator and the scale (or using one Gram for both) fails it, because
+    # W has a large component outside range(Q) in this setup.
+    from scipy.optimize import nnls
+    X, Q, B, W, Wt, H = _rhals_setup(65)
+    Wn, Wtn, Hn = o.rhals_sweep(Q, B, W, Wt, H, gram_mode=o.GRAM_MIXED)
+    k = H.shape[0]
+    Hb = H.copy()
+    for j in range(k):
+        rho = W[:, j] @ W[:, j] - Wt[:, j] @ Wt[:, j]
+        assert rho > 0.1 * (W[:, j] @ W[:, j])  # the pin separates the Grams
+        Rt = B - Wt @ Hb + np.outer(Wt[:, j], Hb[j, :])
+        A = np.concatenate([Wt[:, j], [math.sqrt(rho)]]).reshape(-1, 1)
+        Hb[j, :] = [nnls(A, np.concatenate([Rt[:, c], [math.sqrt(rho) * Hb[j, c]]]))[0][0]
+                    for c in range(Hb.shape[1])]
+    assert np.allclose(Hn, Hb, atol=1e-10)
+    # the W phase does not depend on the Gram mode
+    Wf, Wtf, _ = o.rhals_sweep(Q, B, W, Wt, Hb, order=o.ORDER_W_FIRST)
+    Wm, Wtm, _ = o.rhals_sweep(Q, B, W, Wt, Hb, gram_mode=o.GRAM_MIXED, order=o.ORDER_W_FIRST)
+    assert np.array_equal(Wf, Wm) and np.array_equal(Wtf, Wtm)
+
+
 def test_rhals_full_space_equivalent_form():
     # In m-space, the W~ step plus lift equals W_j <- [P_Q (W_j + (X^ H^T_j -
     # W V_j) / V_jj)]_+ with P_Q = Q Q^T, which holds because W~ = Q^T W.
