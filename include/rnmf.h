@@ -82,8 +82,11 @@ enum { RNMF_GRAM_FULL = 0, RNMF_GRAM_LOWDIM = 1, RNMF_GRAM_MIXED = 2 };
  * other blocked order. */
 enum { RNMF_ORDER_H_FIRST = 0, RNMF_ORDER_W_FIRST = 1 };
 /* Test matrix distribution when Omega is generated (Sec. 2.3 / Remark on the
- * random test matrix): standard normal (default) or uniform on [0, 1). */
-enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1 };
+ * random test matrix): standard normal (default) or uniform on [0, 1).
+ * GAUSS_CLIPPED (standard normal with the negative entries set to zero) is the
+ * distribution of the Gaussian start (RNMF_FLAG_GAUSS_INIT); rnmf_random takes
+ * all three. */
+enum { RNMF_OMEGA_GAUSSIAN = 0, RNMF_OMEGA_UNIFORM = 1, RNMF_DIST_GAUSS_CLIPPED = 2 };
 
 /* opts.flags */
 #define RNMF_FLAG_CHECK_INPUT 0x1u      /* scan X for NaN/Inf/negative values  */
@@ -198,8 +201,9 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
  * Q: m x l; B: l x n; W: m x k (in/out); Wt: l x k (in/out, the compressed
  * factor W~, normally Q^T W); H: k x n (in/out).  If opts->tol > 0 the sweeps
  * stop once ||grad^P f||^2 on Q B falls below tol times its value at entry
- * (Sec. 3.3).  dev_stats (device, optional): 4 doubles = {sweeps done,
- * ||grad^P||^2 at entry, at exit, status word}.  Requires k <= 64 and
+ * (Sec. 3.3).  dev_stats (device, optional): 3 doubles = {sweeps done,
+ * ||grad^P||^2 at entry, at exit}; the device status word stays in ws
+ * (rnmf_read_status).  Requires k <= 64 and
  * l <= 128.  With RNMF_FLAG_TRACE, workgroup 0 writes 10 + 2k timestamps of
  * the device's 100 MHz real-time counter for the first sweep (entry, Q slab
  * loaded, prologue, H phase, T/V exchange, each W column before and after its
@@ -396,6 +400,32 @@ rnmf_status rnmf_hals(const void* X, int xt, int64_t m, int64_t n, int64_t ldx, 
  * for callers that keep a BF16 copy of X for RNMF_PREC_BF16.  Asynchronous. */
 rnmf_status rnmf_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx,
                            void* Xb, void* stream);
+
+/* The library's seeded random matrices (Algorithm 1, step 2, and the Remark on
+ * the random test matrix after it): fills `out` (device, rows x cols, packed
+ * row-major, RNMF_F64 or RNMF_F32) with the stream that rnmf_sketch and
+ * rnmf_factorize draw when a pointer is NULL.  Element e = r * cols + c is
+ * computed from one Philox4x32-10 block (Salmon et al., SC 2011) with counter
+ * (e mod 2^32, e div 2^32, stream_id, 0x524E4D46) and key (seed mod 2^32,
+ * seed div 2^32); with output words (c0, c1, c2, c3) and
+ * u(a, b) = ((b << 21) xor (a >> 11)) / 2^53:
+ *   RNMF_OMEGA_UNIFORM:      u(c0, c1), in [0, 1);
+ *   RNMF_OMEGA_GAUSSIAN:     sqrt(-2 log(u(c0, c1) + 2^-53)) cos(2 pi u(c2, c3))
+ *                            (Box-Muller, cosine branch);
+ *   RNMF_DIST_GAUSS_CLIPPED: the Gaussian value with negative values set to 0;
+ * computed in FP64 and rounded once to the output type.  Stream ids used by
+ * the library: 3 Omega, 4 W0, 5 H0.  Asynchronous. */
+rnmf_status rnmf_random(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed, uint32_t stream_id,
+                        int32_t dist, void* stream);
+
+/* The Philox4x32-10 block function behind rnmf_random, on caller-given inputs
+ * (all device arrays): out[4i..4i+3] = philox4x32_10(ctr[4i..4i+3],
+ * key[2i..2i+1]) for i < count; ten rounds with multipliers 0xD2511F53 and
+ * 0xCD9E8D57 and key increments 0x9E3779B9 and 0xBB67AE85 (Salmon et al.,
+ * SC 2011).  It lets a caller reproduce or verify the generator's stream.
+ * count = 0 is a no-op.  Asynchronous. */
+rnmf_status rnmf_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                               void* stream);
 
 /* Synchronises `stream` and returns the device status word recorded in `ws`
  * by the most recent asynchronous call that used `ws` (each entry point clears

@@ -44,7 +44,7 @@ EXPORTS = [
     "rnmf_factorize", "rnmf_cast_bf16", "rnmf_read_status", "rnmf_hals", "rnmf_svd_init",
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
     "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
-    "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered",
+    "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered", "rnmf_random", "rnmf_philox4x32_10",
 ]
 
 
@@ -91,6 +91,10 @@ def lib():
                                "`python -m paper_1711_02037_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.rnmf_random.argtypes = [vp, ctypes.c_int, i64, i64, ctypes.c_uint64, ctypes.c_uint32, i32, vp]
+        L.rnmf_random.restype = ctypes.c_int
+        L.rnmf_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
+        L.rnmf_philox4x32_10.restype = ctypes.c_int
         L.rnmf_default_opts.argtypes = [ctypes.POINTER(Opts)]
         L.rnmf_default_opts.restype = None
         L.rnmf_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, ctypes.POINTER(Opts)]
@@ -702,6 +706,39 @@ def cast_bf16(X):
     Xb = torch.empty((m, n), dtype=torch.bfloat16, device=X.device)
     _check(lib().rnmf_cast_bf16(_ptr(X), m, n, X.stride(0), _ptr(Xb), _stream(X.device)))
     return Xb
+
+
+DISTS = {"gaussian": 0, "uniform": 1, "gauss_clipped": 2}
+
+
+def random(rows, cols, seed, stream_id, dist="gaussian", dtype=None, device="cuda:0"):
+    """The library's seeded random matrix (rnmf_random): rows x cols, FP32 by
+    default; stream ids 3, 4, 5 are the ones rnmf_factorize uses for Omega,
+    W0 and H0."""
+    torch = _torch()
+    dt = dtype or torch.float32
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("dtype must be float32 or float64")
+    out = torch.empty((rows, cols), dtype=dt, device=device)
+    _check(lib().rnmf_random(_ptr(out), 0 if dt == torch.float64 else 1, rows, cols, int(seed) & (2**64 - 1),
+                             int(stream_id), DISTS[dist], _stream(out.device)))
+    return out
+
+
+def philox4x32_10(ctr, key):
+    """The Philox4x32-10 block function (rnmf_philox4x32_10) on device int32
+    tensors ctr (count x 4) and key (count x 2); returns count x 4 words
+    (int32 storage of the unsigned words)."""
+    torch = _torch()
+    _need_dev(ctr, "ctr"); _need_dev(key, "key")
+    if ctr.dtype != torch.int32 or key.dtype != torch.int32:
+        raise ValueError("ctr and key must be int32 tensors")
+    if ctr.dim() != 2 or ctr.shape[1] != 4 or key.shape != (ctr.shape[0], 2):
+        raise ValueError("ctr must be count x 4 and key count x 2")
+    ctr, key = ctr.contiguous(), key.contiguous()
+    out = torch.empty_like(ctr)
+    _check(lib().rnmf_philox4x32_10(_ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0], _stream(ctr.device)))
+    return out
 
 
 def read_status(ws):

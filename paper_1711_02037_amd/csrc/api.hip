@@ -1378,6 +1378,27 @@ rnmf_status rnmf_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, vo
   return RNMF_OK;
 }
 
+rnmf_status rnmf_random(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed, uint32_t stream_id,
+                        int32_t dist, void* stream) {
+  g_err.clear();
+  if (!out) return fail(RNMF_ERR_ARG, "out must be non-NULL");
+  if (rows < 0 || cols < 0) return fail(RNMF_ERR_SHAPE, "bad shape");
+  if (dt != RNMF_F64 && dt != RNMF_F32) return fail(RNMF_ERR_DTYPE, "out must be RNMF_F64 or RNMF_F32");
+  if (dist < RNMF_OMEGA_GAUSSIAN || dist > RNMF_DIST_GAUSS_CLIPPED)
+    return fail(RNMF_ERR_ARG, "dist must be RNMF_OMEGA_GAUSSIAN, RNMF_OMEGA_UNIFORM or RNMF_DIST_GAUSS_CLIPPED");
+  HIPCHK(launch_philox(out, dt == RNMF_F64 ? 0 : 1, rows, cols, seed, stream_id, dist, (hipStream_t)stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                               void* stream) {
+  g_err.clear();
+  if (count < 0) return fail(RNMF_ERR_SHAPE, "count must be >= 0");
+  if (count > 0 && (!ctr || !key || !out)) return fail(RNMF_ERR_ARG, "ctr, key and out must be non-NULL");
+  HIPCHK(launch_philox_raw(ctr, key, out, count, (hipStream_t)stream));
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_read_status(void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   if (!ws || ws_bytes < HDR_BYTES) return fail(RNMF_ERR_WORKSPACE, "workspace missing or too small");

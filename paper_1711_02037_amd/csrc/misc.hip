@@ -67,6 +67,29 @@ __global__ void philox_kernel(T* out, int64_t count, unsigned k0, unsigned k1, u
   }
 }
 
+// The bare block function on caller-given counters and keys (4 and 2 words
+// each per element), for reproducing the generator's stream off the device.
+__global__ void philox_raw_kernel(const unsigned* __restrict__ ctr, const unsigned* __restrict__ key,
+                                  unsigned* __restrict__ out, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) {
+    unsigned c[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    philox4x32_10(c, key[2 * i], key[2 * i + 1]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[4 * i + e] = c[e];
+  }
+}
+
+hipError_t launch_philox_raw(const unsigned* ctr, const unsigned* key, unsigned* out, int64_t count,
+                             hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(philox_raw_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ctr, key, out, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_philox(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed,
                          unsigned sid, int dist, hipStream_t s) {
   int64_t count = rows * cols;
@@ -141,7 +164,7 @@ __global__ void cast_bf16_kernel(const float* __restrict__ X, int64_t m, int64_t
       w.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
       *(uint2*)dst = w;
     } else {
-      for (int e = 0; c0 + e < ldb; ++e) dst[e] = o[e];
+      for (int e = 0; e < 4 && c0 + e < ldb; ++e) dst[e] = o[e];
     }
   }
   if (check) or_status(status, flag);

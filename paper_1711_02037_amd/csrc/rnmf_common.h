@@ -61,6 +61,8 @@ struct Dev {
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t s);
 // dist: 0 standard normal, 1 uniform [0, 1), 2 standard normal with the
 // negative entries set to zero
+hipError_t launch_philox_raw(const unsigned* ctr, const unsigned* key, unsigned* out, int64_t count,
+                             hipStream_t s);
 hipError_t launch_philox(void* out, int dt, int64_t rows, int64_t cols, uint64_t seed,
                          unsigned stream_id, int dist, hipStream_t s);
 hipError_t launch_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, bf16_t* Xb,

@@ -308,6 +308,72 @@ __device__ __forceinline__ T sum_stride8(T x) {
 
 template <typename T> __device__ __forceinline__ T clip0(T x) { return x > (T)0 ? x : (T)0; }
 
+// Per-column all-reduce by block owners.  The l-vector is cut into blocks of
+// 16 words (one 128-byte line of a slot: 16 / W elements); block b has one
+// owner workgroup, which sums the block over all G partial slots and
+// publishes the totals in C copies (every other workgroup reads copy g mod C).
+// Thread t of the owner takes element t mod EPB of the block from slots
+// t / EPB + i * (NTH / EPB), so the loads of one wave cover whole lines and
+// all of them are in flight together.  The sum runs in a fixed order (over i,
+// across the lanes holding the same element, then over the waves), so every
+// reader receives bit-identical totals whatever the arrival order.  Against
+// a two-hop exchange in which every workgroup gathers from 16 slots twice,
+// this moves about 1/14 of the polling traffic and takes one owner hop and one
+// reader hop.
+template <typename T>
+__device__ __forceinline__ void owner_block(const u64* P, u64* R, int G, size_t slot, int l, int b, int C,
+                                            unsigned e, T* red, bool& ok) {
+  constexpr int W = Words<T>::n;
+  constexpr int EPB = 16 / W;
+  constexpr int SS = NTH / EPB;
+  constexpr int MAXI = 256 / SS;  // G <= 256
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int ein = t % EPB, el = b * EPB + ein;
+  const bool live = el < l;
+  const int s0 = t / EPB;
+  u64 w[MAXI][W];
+#pragma unroll
+  for (int i = 0; i < MAXI; ++i) {
+    const int src = s0 + i * SS;
+    const bool act = live && src < G;
+#pragma unroll
+    for (int h = 0; h < W; ++h)
+      w[i][h] = act ? ld_ll(P + (size_t)src * slot + (size_t)el * W + h) : ((u64)e << 32);
+  }
+  long spins = 0;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+      for (int h = 0; h < W; ++h) all = all && ((unsigned)(w[i][h] >> 32) == e);
+    if (all) break;
+    if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+      for (int h = 0; h < W; ++h)
+        if ((unsigned)(w[i][h] >> 32) != e) w[i][h] = ld_ll(P + (size_t)(s0 + i * SS) * slot + (size_t)el * W + h);
+  }
+  T acc = (T)0;
+#pragma unroll
+  for (int i = 0; i < MAXI; ++i) acc += value_of<T>(w[i]);
+  if constexpr (W == 1) acc = swap_sum32(swap_sum16(acc));  // lanes with equal lane % 16
+  else acc = sum_stride8(acc);                                // lanes with equal lane % 8
+  if (lane < EPB) red[wave * EPB + lane] = acc;
+  lds_sync();
+  if (t < C * EPB) {
+    const int cp = t / EPB, ei = t % EPB;
+    if (b * EPB + ei < l) {
+      T tot = (T)0;
+#pragma unroll
+      for (int wv = 0; wv < NTH / 64; ++wv) tot += red[wv * EPB + ei];
+      put<T>(R + (size_t)cp * slot, b * EPB + ei, tot, e);
+    }
+  }
+  lds_sync();
+}
+
 // Maps a linear block index to (row block, column block) of the upper block
 // triangle of an nb x nb block matrix, in row-major order.
 __device__ __forceinline__ void upper_block(int b, int nb, int& r, int& c) {
@@ -739,14 +805,17 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // W phase with the Q slab in registers.  Per column: lift and clip (a
   // register GEMV reduced over the 8 column-group lanes), the local map-back
   // (reduced over the row groups: the 8 of a wave by lane permutes, then the
-  // waves through LDS), one
-  // device-wide exchange by threads t < l; while it is in flight, threads
-  // t >= 128 prepare the next column's update vector without the column being
-  // exchanged, whose term is added once its value arrives.
+  // waves through LDS), and one device-wide exchange of the l-vector through
+  // the block owners; while it is in flight, threads t >= 128 prepare the next
+  // column's update vector without the column being exchanged, whose term is
+  // added once its value arrives.
   auto w_phase_reg = [&]() __attribute__((always_inline)) -> bool {
     T* part = red2;                    // 8 x 72: per-wave map-back partials
     T* cpart = red2 + 8 * 72;          // 5 x LPS: partial sums for the next update vector
     double* spart = (double*)(red2 + 8 * 72 + 5 * LPS);  // 2 x 384: local S partial sums
+    T* ored = red2 + 8 * 72 + 5 * LPS + 768 * 8 / sizeof(T);  // 128: exchange owner's wave sums
+    const int nblk_x = (l * Words<T>::n + 15) / 16;          // 16-word blocks of the l-vector
+    const int ncopy_x = a.G < 16 ? a.G : 16;                 // copies of the totals
     int jprev = -1;  // column whose S partials await their reduction
     const T aw = (T)a.aw, bw = (T)a.bw;
     auto next_col = [&](int j) __attribute__((always_inline)) -> int {
@@ -820,20 +889,14 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       const unsigned par = (x.small_use++) & 1u;
       T wt = (T)0;
       bool ok = true;
+      const size_t slot = (size_t)LPS * 2;
+      u64* P = a.xs_part + ((size_t)par * a.G) * slot;
+      u64* RS = a.xs_row + ((size_t)par * a.G) * slot;
       if (t < l) {
         T s = part[t];
 #pragma unroll
         for (int wv = 1; wv < 8; ++wv) s += part[wv * 72 + t];
-        const size_t slot = (size_t)LPS * 2;
-        u64* P = a.xs_part + ((size_t)par * a.G) * slot;
-        u64* RS = a.xs_row + ((size_t)par * a.G) * slot;
         put<T>(P + (size_t)x.g * slot, t, s, e);
-        s = gather_sum<T>(P + (size_t)x.i * a.GC * slot, slot, a.GC, t, e, ok);
-        if (a.GR > 1) {
-          put<T>(RS + (size_t)x.g * slot, t, s, e);
-          s = gather_sum<T>(RS + (size_t)x.j * slot, (size_t)a.GC * slot, a.GR, t, e, ok);
-        }
-        wt = s;
       } else if (t >= 128) {
         if (nj < k) {
           // sum over i != jj of W~(a, i) V(i, nj), in 5 parts of the index range
@@ -874,6 +937,11 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           }
         }
       }
+      // block owners sum the partials; every workgroup then reads the totals
+      for (int b = 0; b < nblk_x; ++b)
+        if (((nblk_x <= a.G) ? (b * a.G) / nblk_x : b % a.G) == g)
+          owner_block<T>(P, RS, a.G, slot, l, b, ncopy_x, e, ored, ok);
+      if (t < l) wt = gather_sum<T>(RS + (size_t)(g % ncopy_x) * slot, slot, 1, t, e, ok);
       s_cols |= 1ull << jj;
       if (!ok) abort_flag = 1;
       lds_sync();
@@ -1155,7 +1223,7 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   size_t stage = 32 * (size_t)(4 * ((k + 3) / 4));
   if (stage > red2) red2 = stage;
   if ((size_t)(LMAX + KMAX) * 8 > red2) red2 = (size_t)(LMAX + KMAX) * 8;  // T/V column staging
-  if ((size_t)(8 * 72 + 5 * LPS) + 768 * 8 / es > red2) red2 = 8 * 72 + 5 * LPS + 768 * 8 / es;  // W phase (REGQ)
+  if ((size_t)(8 * 72 + 5 * LPS) + 768 * 8 / es + 128 > red2) red2 = 8 * 72 + 5 * LPS + 768 * 8 / es + 128;  // W phase (REGQ)
 
   if ((size_t)NTH * 8 / es > red2) red2 = (size_t)NTH * 8 / es;  // pg reduction as doubles
   red2 = round_up(red2, 4);

@@ -300,3 +300,17 @@ def test_hals_ordered_validation():
         bad = rn.make_opts(k, 6, 0)
         setattr(bad, field, value)
         assert call(good, oo=bad) == rn.ERR_ARG, field
+
+
+def test_generator_entry_points_validate_arguments():
+    L = rn.lib()
+    p = ctypes.c_void_p(4096)
+    assert L.rnmf_random(None, rn.F32, 4, 4, 1, 3, 0, None) == rn.ERR_ARG
+    assert L.rnmf_random(p, rn.F32, -1, 4, 1, 3, 0, None) == rn.ERR_SHAPE
+    assert L.rnmf_random(p, rn.BF16, 4, 4, 1, 3, 0, None) == rn.ERR_DTYPE
+    assert L.rnmf_random(p, rn.F32, 4, 4, 1, 3, 3, None) == rn.ERR_ARG
+    assert L.rnmf_random(p, rn.F32, 4, 4, 1, 3, -1, None) == rn.ERR_ARG
+    assert L.rnmf_random(p, rn.F64, 0, 4, 1, 3, 1, None) == rn.OK      # empty: nothing to launch
+    assert L.rnmf_philox4x32_10(None, None, None, -1, None) == rn.ERR_SHAPE
+    assert L.rnmf_philox4x32_10(None, p, p, 3, None) == rn.ERR_ARG
+    assert L.rnmf_philox4x32_10(None, None, None, 0, None) == rn.OK
