@@ -214,6 +214,32 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
                            int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* rnmf_hals_step without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It runs the same sweep kernel; its scratch memory (the
+ * status word, the statistics and the exchange buffers) is a fixed array of
+ * RNMF_NOALLOC_SCRATCH_BYTES in the library's device code, one per GPU, held
+ * until the process ends.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no allocating library routine.  Arguments as for rnmf_hals_step,
+ * plus dev_status (device, optional): one uint32 that receives the device
+ * status bits of the sweeps (0 = fine; nonzero: rnmf_status_string of
+ * rnmf_read_status's mapping - a non-finite value or a wait that hit its spin
+ * limit); dev_stats as for rnmf_hals_step.  RNMF_FLAG_TRACE is rejected (the
+ * trace would land in the hidden scratch).  The scratch holds 4 KiB plus the
+ * sweep's exchange buffers, which at 256 workgroups take
+ * 8 (262,144 + 512 c + 2,048 ceil(c / 16)) bytes for c = l k + k^2: any
+ * c <= 7,781 fits (k = 50 with l <= 105, k = 64 with l <= 57; k = 50, l = 70
+ * takes 32.8 MB).  A larger problem returns RNMF_ERR_WORKSPACE before any
+ * launch, naming the bytes it needs.  Every call on
+ * one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (on different streams or host threads) race and must be serialised by the
+ * caller.  Each call clears what must start at zero.  Asynchronous. */
+#define RNMF_NOALLOC_SCRATCH_BYTES (40u << 20)
+rnmf_status rnmf_hals_step_noalloc(const void* Q, const void* B, int64_t m, int64_t n,
+                                   int32_t l, int32_t k, void* W, void* Wt, void* H,
+                                   int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,
+                                   uint32_t* dev_status, void* stream);
+
 /* Relative error ||X - W H||_F / ||X||_F (reading of the "error" of Sec. 4),
  * with FP64 accumulation.  W: m x k, H: k x n in the factor dtype.  out
  * (device): 2 doubles = {||X - W H||_F^2, ||X||_F^2}.  Asynchronous. */

@@ -45,6 +45,7 @@ EXPORTS = [
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
     "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
     "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered", "rnmf_random", "rnmf_philox4x32_10",
+    "rnmf_hals_step_noalloc",
 ]
 
 
@@ -91,6 +92,9 @@ def lib():
                                "`python -m paper_1711_02037_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.rnmf_hals_step_noalloc.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, ctypes.POINTER(Opts),
+                                             vp, vp, vp]
+        L.rnmf_hals_step_noalloc.restype = ctypes.c_int
         L.rnmf_random.argtypes = [vp, ctypes.c_int, i64, i64, ctypes.c_uint64, ctypes.c_uint32, i32, vp]
         L.rnmf_random.restype = ctypes.c_int
         L.rnmf_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
@@ -332,6 +336,26 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
         t0 = ts[0]
         return int(s[0]), s[1], s[2], [(x - t0) / 100.0 if x else None for x in ts]
     return int(s[0]), s[1], s[2]
+
+
+def hals_step_noalloc(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, reg=None):
+    """hals_step through rnmf_hals_step_noalloc: the same sweeps with the
+    library's fixed per-GPU scratch instead of a workspace (the library
+    allocates nothing).  Returns (sweeps done, pg^2 at entry, pg^2 at exit,
+    device status bits)."""
+    torch = _torch()
+    for t, nm in ((Q, "Q"), (B, "B"), (W, "W"), (Wt, "Wt"), (H, "H")):
+        _need_dev(t, nm); _packed(t, nm)
+    m, l = Q.shape
+    k, n = H.shape
+    prec = precision or ("fp64" if Q.dtype == torch.float64 else "fp32")
+    o = make_opts(k, l - k, 0, tol=tol, precision=prec, gram=gram, order=order, reg=reg)
+    stats = torch.zeros(4, dtype=torch.float64, device=Q.device)
+    status = torch.zeros(1, dtype=torch.int32, device=Q.device)
+    _check(lib().rnmf_hals_step_noalloc(_ptr(Q), _ptr(B), m, n, l, k, _ptr(W), _ptr(Wt), _ptr(H), int(nsweeps),
+                                        ctypes.byref(o), _ptr(stats), _ptr(status), _stream(Q.device)))
+    s = stats.cpu().tolist()
+    return int(s[0]), s[1], s[2], int(status.cpu().item())
 
 
 def hals(X, W, H, nsweeps=1, order="h_first", ws=None, reg=None):

@@ -675,6 +675,30 @@ rnmf_status reverse_sweep(const void* Q, const void* B, const State& o_, const S
   return RNMF_OK;
 }
 
+// Scratch of rnmf_hals_step_noalloc: one copy per GPU in the library's device
+// code.  In host code `noalloc_scratch` names a host-side stand-in, never the
+// device memory: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char noalloc_scratch[RNMF_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64] = {nullptr};
+
+rnmf_status noalloc_scratch_ptr(void** out) {
+  int id = 0;
+  HIPCHK(hipGetDevice(&id));
+  if (id < 0 || id >= 64) return fail(RNMF_ERR_HIP, "device id %d out of range", id);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[id]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)));
+    if (!p || (uintptr_t)p % 256) return fail(RNMF_ERR_HIP, "scratch symbol address unusable");
+    g_noalloc_ptr[id] = p;
+  }
+  *out = g_noalloc_ptr[id];
+  return RNMF_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -853,6 +877,46 @@ rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, i
   }
   HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, reg_of(o), b.xbuf,
                       stats, h.status, trace, d.stream));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_hals_step_noalloc(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
+                                   void* Wt, void* H, int32_t nsweeps, const rnmf_opts* o, double* dev_stats,
+                                   uint32_t* dev_status, void* stream) {
+  g_err.clear();
+  if (!o) return fail(RNMF_ERR_ARG, "opts is NULL");
+  if (!Q || !B || !W || !Wt || !H) return fail(RNMF_ERR_ARG, "Q, B, W, Wt and H must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (nsweeps < 0) return fail(RNMF_ERR_ARG, "nsweeps < 0");
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  if (o->gram_mode < 0 || o->gram_mode > 2) return fail(RNMF_ERR_ARG, "unknown gram_mode");
+  if (o->order < 0 || o->order > 1) return fail(RNMF_ERR_ARG, "unknown order");
+  if (o->flags & RNMF_FLAG_TRACE) return fail(RNMF_ERR_ARG, "RNMF_FLAG_TRACE needs a workspace (rnmf_hals_step)");
+  if (check_reg(o) != RNMF_OK) return RNMF_ERR_ARG;
+  Dev d;
+  if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const Mode md = mode_of(o);
+  // size first (null base), then carve the scratch the same way
+  Arena sz(nullptr);
+  sz.take<char>(HDR_BYTES);
+  plan_hals(sz, m, n, l, k, md, d, o->tol > 0.0);
+  if (sz.used > (size_t)RNMF_NOALLOC_SCRATCH_BYTES)
+    return fail(RNMF_ERR_WORKSPACE, "this problem needs %zu bytes of scratch; rnmf_hals_step_noalloc holds %zu "
+                "(use rnmf_hals_step with a workspace)", sz.used, (size_t)RNMF_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  rnmf_status r;
+  if ((r = noalloc_scratch_ptr(&ws)) != RNMF_OK) return r;
+  Arena a(ws);
+  a.take<char>(HDR_BYTES);
+  SweepBufs b = plan_hals(a, m, n, l, k, md, d, o->tol > 0.0);
+  Hdr h = header(ws);
+  unsigned* status = dev_status ? (unsigned*)dev_status : h.status;
+  HIPCHK(launch_fill_u32(status, 1, 0u, d.stream));
+  double* stats = dev_stats ? dev_stats : h.stats;
+  HIPCHK(launch_sweep(b.sh, md.dt, Q, B, W, Wt, H, m, n, l, k, nsweeps, o->tol, o->gram_mode, o->order, reg_of(o),
+                      b.xbuf, stats, status, nullptr, d.stream));
   return RNMF_OK;
 }
 
