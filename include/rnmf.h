@@ -144,6 +144,8 @@ typedef struct rnmf_report {
   double ms_qb;       /* stream time of cast, sketch, compression and init (ms)  */
   double ms_sweeps;   /* stream time of the sweep launch (ms)                    */
   double ms_error;    /* stream time of the final error (ms)                     */
+  double comp_err;    /* ||B - W~ H||_F / ||B||_F on the compressed data, FP64   */
+                      /* accumulation (the error the sweeps minimise, Sec. 3.2)  */
 } rnmf_report;
 
 /* Operation selector for rnmf_workspace_bytes. */

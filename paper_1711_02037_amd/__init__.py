@@ -71,7 +71,7 @@ class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("l_eff", ctypes.c_int32), ("q_eff", ctypes.c_int32),
                 ("qr_path", ctypes.c_int32), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("rel_err", ctypes.c_double), ("pg_ratio", ctypes.c_double), ("ms_qb", ctypes.c_double),
-                ("ms_sweeps", ctypes.c_double), ("ms_error", ctypes.c_double)]
+                ("ms_sweeps", ctypes.c_double), ("ms_error", ctypes.c_double), ("comp_err", ctypes.c_double)]
 
 
 class RnmfError(RuntimeError):
@@ -718,7 +718,7 @@ def factorize(X, k, p=20, q=2, max_iter=200, tol=0.0, precision="fp32", seed=0, 
     _check(st, allow=(NOT_CONVERGED,))
     info = dict(iters=rep.iters, l=rep.l_eff, q=rep.q_eff, shifted_qr=bool(rep.qr_path & 1),
                 status=rep.status, rel_err=rep.rel_err, pg_ratio=rep.pg_ratio, ms_qb=rep.ms_qb,
-                ms_sweeps=rep.ms_sweeps, ms_error=rep.ms_error)
+                ms_sweeps=rep.ms_sweeps, ms_error=rep.ms_error, comp_err=rep.comp_err)
     return W, H, info
 
 

@@ -1400,11 +1400,13 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
   HIPCHK(hipEventRecord(ev[2], s));
   HIPCHK(launch_relerr(X, xt, md.dt, m, n, ldx, W, H, k, rb.part, rb.np, h.rel, s));
   HIPCHK(hipEventRecord(ev[3], s));
+  // compressed error ||B - W~ H|| / ||B|| (into rel[2], rel[3]); rb.part is free again
+  HIPCHK(launch_relerr(B, md.dt == 0 ? RNMF_F64 : RNMF_F32, md.dt, l, n, n, Wt, H, k, rb.part, rb.np, h.rel + 2, s));
   unsigned char host[256];
   HIPCHK(hipMemcpyAsync(host, ws, sizeof(host), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   unsigned bits;
-  double stats[3], rel[2];
+  double stats[3], rel[4];
   std::memcpy(&bits, host, 4);
   std::memcpy(stats, host + 64, sizeof(stats));
   std::memcpy(rel, host + 128, sizeof(rel));
@@ -1420,6 +1422,7 @@ rnmf_status rnmf_factorize(const void* X, int xt, int64_t m, int64_t n, int64_t 
     rep->status = st;
     rep->reserved = 0;
     rep->rel_err = rel[1] > 0 ? std::sqrt(rel[0] / rel[1]) : 0.0;
+    rep->comp_err = rel[3] > 0 ? std::sqrt(rel[2] / rel[3]) : 0.0;
     rep->pg_ratio = ratio;
     float ms[3] = {0.f, 0.f, 0.f};
     for (int i = 0; i < 3; ++i)

@@ -24,51 +24,83 @@ int gram_splits(int64_t rows, int cus) {
   return s;
 }
 
-// Partial Gram over a row range: each thread accumulates 4 x 4 blocks of the
-// upper block triangle.  Rows are staged through LDS in FP64.
+// Partial Gram over a row range.  The 4 x 4 blocks of the upper block
+// triangle are spread over the 512 threads; when there are fewer blocks than
+// threads, NG row groups share each block (rows rg, rg + NG, ...) and their
+// partials are added in group order at the end.  Rows are staged through LDS
+// in FP64, RC rows at a time, and the next chunk is loaded into registers
+// while the current one is used, so the loads of a chunk are in flight
+// together instead of one short chunk per round trip.
+constexpr int GRAM_NT = 512;
+constexpr int GRAM_PF = 24;  // staged values per thread: RC * ldl <= GRAM_NT * GRAM_PF
+
+int gram_ldl(int l) { return ((l + 3) / 4) * 4; }
+int gram_rc(int l) {
+  int rc = (GRAM_NT * GRAM_PF) / gram_ldl(l);
+  if (rc > 128) rc = 128;
+  return rc & ~7;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int64_t rows, int l, int64_t rlen,
-                                                   double* __restrict__ gpart, const unsigned* skip) {
+__global__ __launch_bounds__(GRAM_NT) void gram_kernel(const T* __restrict__ Y, int64_t rows, int l, int64_t rlen,
+                                                       int RC, double* __restrict__ gpart, const unsigned* skip) {
   if (skip && *skip == 0u) return;
-  constexpr int RC = 16;
-  __shared__ double Ys[RC][LMAX + 4];
-  const int lb = (l + 3) / 4;
+  extern __shared__ __align__(16) double Ys[];  // RC x ldl
+  const int t = threadIdx.x;
+  const int ldl = ((l + 3) / 4) * 4;
+  const int lb = ldl / 4;
   const int nblk = lb * (lb + 1) / 2;
+  const int NG = (GRAM_NT / nblk > 1) ? GRAM_NT / nblk : 1;  // row groups per block
   const int64_t rb = (int64_t)blockIdx.x * rlen;
   const int64_t re = (rb + rlen < rows) ? rb + rlen : rows;
-  constexpr int MAXB = 3;  // blocks per thread: ceil(528 / 256) for l = 128
-  int ba[MAXB], bb[MAXB];
-  double acc[MAXB][16];
+  // blocks of this thread: one per row group when NG > 1, else up to two
+  int ba[2] = {-1, -1}, bb[2] = {-1, -1};
+  const int rg = (NG > 1) ? t / nblk : 0;
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    int b = threadIdx.x + 256 * q;
-    ba[q] = -1;
-    bb[q] = -1;
-    if (b < nblk) {
-      // map linear index to (row block a <= column block c) in row-major upper order
+  for (int q = 0; q < 2; ++q) {
+    const int b = (NG > 1) ? ((q == 0 && rg < NG) ? t % nblk : -1) : t + q * GRAM_NT;
+    if (b >= 0 && b < nblk) {
       int a = 0, rem = b;
       while (rem >= lb - a) { rem -= lb - a; ++a; }
       ba[q] = a;
       bb[q] = a + rem;
     }
+  }
+  double acc[2][16];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[q][e] = 0.0;
-  }
+  // element e of a chunk: row e / ldl, column e % ldl (columns >= l are zero)
+  T pf[GRAM_PF];
+  auto fetch = [&](int64_t r0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < GRAM_PF; ++u) {
+      const int e = t + u * GRAM_NT;
+      const int rr = e / ldl, c = e - (e / ldl) * ldl;
+      const int64_t r = r0 + rr;
+      pf[u] = (rr < RC && r < re && c < l) ? Y[r * l + c] : (T)0;
+    }
+  };
+  fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += RC) {
-    for (int e = threadIdx.x; e < RC * (LMAX + 4); e += 256) {
-      int rr = e / (LMAX + 4), c = e % (LMAX + 4);
-      int64_t r = r0 + rr;
-      Ys[rr][c] = (r < re && c < l) ? (double)Y[r * l + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < GRAM_PF; ++u) {
+      const int e = t + u * GRAM_NT;
+      if (e < RC * ldl) Ys[e] = (double)pf[u];
     }
     __syncthreads();
+    if (r0 + RC < re) fetch(r0 + RC);
+    const int nr = (re - r0 < RC) ? (int)(re - r0) : RC;
 #pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
+    for (int q = 0; q < 2; ++q) {
       if (ba[q] < 0) continue;
-      const int a4 = 4 * ba[q], c4 = 4 * bb[q];
-      for (int rr = 0; rr < RC; ++rr) {
-        double x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { x[u] = Ys[rr][a4 + u]; y[u] = Ys[rr][c4 + u]; }
+      const double* xa = Ys + 4 * ba[q];
+      const double* xc = Ys + 4 * bb[q];
+      for (int rr = rg; rr < nr; rr += NG) {
+        const double2 x01 = *(const double2*)(xa + rr * ldl), x23 = *(const double2*)(xa + rr * ldl + 2);
+        const double2 y01 = *(const double2*)(xc + rr * ldl), y23 = *(const double2*)(xc + rr * ldl + 2);
+        const double x[4] = {x01.x, x01.y, x23.x, x23.y}, y[4] = {y01.x, y01.y, y23.x, y23.y};
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -78,8 +110,32 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ Y, int6
     __syncthreads();
   }
   double* dst = gpart + (size_t)blockIdx.x * LMAX * LMAX;
+  if (NG > 1) {
+    // fixed-order sum of the row groups' partials through LDS (nblk x 16 doubles)
+    for (int gi = 0; gi < NG; ++gi) {
+      if (rg == gi && ba[0] >= 0) {
+        const int b = t % nblk;
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
+        for (int e = 0; e < 16; ++e) Ys[b * 16 + e] = (gi == 0) ? acc[0][e] : Ys[b * 16 + e] + acc[0][e];
+      }
+      __syncthreads();
+    }
+    if (t < nblk) {
+      int a = 0, rem = t;
+      while (rem >= lb - a) { rem -= lb - a; ++a; }
+      const int a4 = 4 * a, c4 = 4 * (a + rem);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int aa = a4 + u, cc = c4 + v;
+          if (aa < l && cc < l) dst[aa * LMAX + cc] = Ys[t * 16 + u * 4 + v];
+        }
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
     if (ba[q] < 0) continue;
     const int a4 = 4 * ba[q], c4 = 4 * bb[q];
 #pragma unroll
@@ -124,10 +180,24 @@ hipError_t launch_gram(const void* Y, int dt, int64_t rows, int l, double* gpart
                        hipStream_t s, const unsigned* skip) {
   int64_t rlen = (rows + splits - 1) / splits;
   int rs = ceil_div(rows, rlen);
-  if (dt == 0)
-    hipLaunchKernelGGL(gram_kernel<double>, dim3(rs), dim3(256), 0, s, (const double*)Y, rows, l, rlen, gpart, skip);
-  else
-    hipLaunchKernelGGL(gram_kernel<float>, dim3(rs), dim3(256), 0, s, (const float*)Y, rows, l, rlen, gpart, skip);
+  const int rc = gram_rc(l);
+  // chunk staging, and the NG x nblk x 16 partial sums at the end
+  const int lb = gram_ldl(l) / 4, nblk = lb * (lb + 1) / 2;
+  size_t lds = (size_t)rc * gram_ldl(l) * 8;
+  if ((size_t)nblk * 16 * 8 > lds) lds = (size_t)nblk * 16 * 8;
+  if (dt == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)gram_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gram_kernel<double>, dim3(rs), dim3(GRAM_NT), lds, s, (const double*)Y, rows, l, rlen, rc,
+                       gpart, skip);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)gram_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gram_kernel<float>, dim3(rs), dim3(GRAM_NT), lds, s, (const float*)Y, rows, l, rlen, rc,
+                       gpart, skip);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_sum_kernel, dim3(ceil_div(l * l, 32)), dim3(256), 0, s, gpart, rs, l, G, skip);
@@ -312,14 +382,148 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ G,
   }
 }
 
+// Cholesky of G and the inverse of its factor in one workgroup, unblocked and
+// right-looking, with every entry held in a register of one thread for the
+// whole factorisation.  The entries are the lower triangle of the trailing
+// matrix A (initially G) and the lower triangle of Y (initially I), which
+// becomes X = L^{-1}.  At step j, with d = A(j,j):
+//   A(i,p) -= A(i,j) A(p,j) / d     for j < p <= i  (trailing update)
+//   Y(i,c) -= A(i,j) Y(j,c) / d     for c <= j < i  (forward substitution)
+// and X(j,c) = Y(j,c) / sqrt(d) once row j of Y is final.  Column j of A and
+// row j of Y are the only values a step needs from other threads: their
+// owners publish them to LDS (double-buffered) right after their own update
+// of the previous step, so each step costs one workgroup barrier.
+// Entries are ranked by the last step that updates them (A(i,p): p - 1,
+// Y(i,c): i - 1), latest first, and entry rank e goes to thread e mod NT,
+// slot e div NT: a thread's slots become idle in order, so its loop over
+// slots stops at the first idle one, at about the same slot across a wave.
+// With l + 1 entries per key the rank has a closed form, no sort is needed.
+constexpr int CHOL_NT = 1024;
+
+template <typename OT, int CHOL_MAXS>  // CHOL_MAXS: slots per thread, >= l (l + 1) / CHOL_NT
+__global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const double* __restrict__ G, int l, int64_t rows,
+                                                         OT* __restrict__ At, int lp, unsigned* ctl, int mode,
+                                                         int allow_shift, unsigned* status) {
+  __shared__ double vcol[2][LMAX];  // column j of A (rows i >= j)
+  __shared__ double yrow[2][LMAX];  // row j of Y (columns c <= j)
+  __shared__ double rinv[LMAX];     // 1 / sqrt(d_j)
+  __shared__ double trace_s;
+  const int t = threadIdx.x;
+  if (mode == 2 && ctl && *ctl == 0u) return;  // no shifted pass happened: nothing to do
+  const int NE = l * (l + 1);
+  // slot code: (key + 1) << 17 | type << 16 | i << 8 | c  (type 0: A, 1: Y); -1: no entry
+  int code[CHOL_MAXS];
+#pragma unroll
+  for (int s2 = 0; s2 < CHOL_MAXS; ++s2) {
+    const int e = t + s2 * CHOL_NT;
+    code[s2] = -1;
+    if (e < NE) {
+      const int p = e / (l + 1), r = e - (e / (l + 1)) * (l + 1);
+      const int b = l - 1 - p;  // bucket: entries whose last step is b - 1
+      if (r < l - b) code[s2] = (b << 17) | (0 << 16) | ((b + r) << 8) | b;          // A(b + r, b)
+      else code[s2] = (b << 17) | (1 << 16) | (b << 8) | (r - (l - b));               // Y(b, r - (l - b))
+    }
+  }
+  // zero the parts of the packed operand that no entry writes
+  for (int e = t; e < lp * lp; e += CHOL_NT) {
+    const int c = e / lp, kk = e - (e / lp) * lp;
+    if (!(c < l && kk <= c)) At[e] = (OT)0;
+  }
+  bool fail = false;
+  int shifted = 0;
+  double v[CHOL_MAXS];
+  for (int attempt = (allow_shift == 2) ? 1 : 0; attempt < 2; ++attempt) {
+    shifted = attempt;
+    double shift = 0.0;
+    if (attempt == 1) {
+      if (t == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < l; ++i) tr += G[i * l + i];
+        trace_s = tr;
+      }
+      __syncthreads();
+      const double u = 1.1102230246251565e-16;
+      shift = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u * trace_s;
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < CHOL_MAXS; ++s2) {
+      v[s2] = 0.0;
+      const int cd = code[s2];
+      if (cd >= 0) {
+        const int ty = (cd >> 16) & 1, i = (cd >> 8) & 0xFF, c = cd & 0xFF;
+        if (ty == 0) v[s2] = G[i * l + c] + (i == c ? shift : 0.0);
+        else v[s2] = (i == c) ? 1.0 : 0.0;
+        // publish column 0 of A and row 0 of Y
+        if (ty == 0 && c == 0) vcol[0][i] = v[s2];
+        if (ty == 1 && i == 0) yrow[0][c] = v[s2];
+      }
+    }
+    __syncthreads();
+    fail = false;
+    for (int j = 0; j < l; ++j) {
+      const int b = j & 1, nb = b ^ 1;
+      const double d = vcol[b][j];
+      if (!(d > 0.0) || !(d < INFINITY)) { fail = true; break; }  // the same value in every thread
+      const double ri = 1.0 / sqrt(d);
+      const double dinv = ri * ri;
+      if (t == 0) rinv[j] = ri;
+#pragma unroll
+      for (int s2 = 0; s2 < CHOL_MAXS; ++s2) {
+        const int cd = code[s2];
+        if ((cd >> 17) <= j) break;  // key < j: this slot and the later ones are done (or empty)
+        const int ty = (cd >> 16) & 1, i = (cd >> 8) & 0xFF, c = cd & 0xFF;
+        const double a = vcol[b][i] * dinv;
+        if (ty == 0) {
+          v[s2] = fma(-a, vcol[b][c], v[s2]);  // c > j
+          if (c == j + 1) vcol[nb][i] = v[s2];
+        } else {
+          if (c <= j) v[s2] = fma(-a, yrow[b][c], v[s2]);  // i > j
+          if (i == j + 1) yrow[nb][c] = v[s2];
+        }
+      }
+      __syncthreads();
+    }
+    if (!fail) break;
+    if (!allow_shift) break;
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) atomicOr(status, ST_NOT_SPD);
+    // leave the packed operand as zero so that downstream results are inert
+    for (int e = t; e < lp * lp; e += CHOL_NT) At[e] = (OT)0;
+    return;
+  }
+  // At[c][k] = X(c, k) = Y(c, k) / sqrt(d_c) for k <= c
+#pragma unroll
+  for (int s2 = 0; s2 < CHOL_MAXS; ++s2) {
+    const int cd = code[s2];
+    if (cd >= 0 && ((cd >> 16) & 1)) {
+      const int i = (cd >> 8) & 0xFF, c = cd & 0xFF;
+      At[(size_t)i * lp + c] = (OT)(v[s2] * rinv[i]);
+    }
+  }
+  if (shifted && t == 0) {
+    atomicOr(status, ST_SHIFTED);
+    if (ctl) atomicOr(ctl, 1u);
+  }
+}
+
 hipError_t launch_chol(double* G, int l, int64_t rows, void* At, int lp, int cdt, unsigned* ctl, int pass,
                        int allow_shift, unsigned* status, hipStream_t s) {
-  if (cdt == 0)
-    hipLaunchKernelGGL(chol_kernel<double>, dim3(1), dim3(256), 0, s, G, l, rows, (double*)At, lp, ctl, pass,
-                       allow_shift, status);
-  else
-    hipLaunchKernelGGL(chol_kernel<float>, dim3(1), dim3(256), 0, s, G, l, rows, (float*)At, lp, ctl, pass,
-                       allow_shift, status);
+  const int ne = l * (l + 1);
+#define CHOL_LAUNCH(OT, S)                                                                                  \
+  hipLaunchKernelGGL((chol_inv_kernel<OT, S>), dim3(1), dim3(CHOL_NT), 0, s, G, l, rows, (OT*)At, lp, ctl, pass, \
+                     allow_shift, status)
+  if (cdt == 0) {
+    if (ne <= 5 * CHOL_NT) CHOL_LAUNCH(double, 5);
+    else if (ne <= 10 * CHOL_NT) CHOL_LAUNCH(double, 10);
+    else CHOL_LAUNCH(double, 17);
+  } else {
+    if (ne <= 5 * CHOL_NT) CHOL_LAUNCH(float, 5);
+    else if (ne <= 10 * CHOL_NT) CHOL_LAUNCH(float, 10);
+    else CHOL_LAUNCH(float, 17);
+  }
+#undef CHOL_LAUNCH
   return hipGetLastError();
 }
 

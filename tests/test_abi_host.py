@@ -149,6 +149,7 @@ def test_deterministic_hals_validation():
 def test_opts_layout_matches_the_header():
     # rnmf_opts: 4 x int32, double tol, uint64 seed, 6 x int32, 4 x double
     assert ctypes.sizeof(rn.Opts) == 88
+    assert ctypes.sizeof(rn.Report) == 72
     assert rn.Opts.alpha_w.offset == 56 and rn.Opts.beta_h.offset == 80
     o = rn.Opts()
     rn.lib().rnmf_default_opts(ctypes.byref(o))

@@ -239,6 +239,9 @@ def test_factorize_fp64_small_matches_oracle():
     assert info["iters"] == 100
     assert abs(info["rel_err"] - io["rel_err"]) <= 1e-10
     assert relf(host(W), Wo) <= 1e-8 and relf(host(H), Ho) <= 1e-8
+    # compressed error ||B - W~ H|| / ||B|| on the oracle's own B, W~, H
+    comp_o = np.linalg.norm(io["B"] - io["Wt"] @ Ho) / np.linalg.norm(io["B"])
+    assert abs(info["comp_err"] - comp_o) <= 1e-9
 
 
 @pytest.mark.parametrize("m,n,k,p,sweeps", [(2000, 700, 12, 20, 60), (777, 1301, 20, 10, 40)])
@@ -249,6 +252,8 @@ def test_factorize_fp32_final_error_matches_oracle(m, n, k, p, sweeps):
                          H0.astype(np.float64), q=2, max_iter=sweeps)
     assert abs(info["rel_err"] - io["rel_err"]) <= 1e-4
     assert abs(info["rel_err"] - o.rel_error(X.astype(np.float64), host(W), host(H))) <= 1e-6
+    comp_o = np.linalg.norm(io["B"] - io["Wt"] @ Ho) / np.linalg.norm(io["B"])
+    assert abs(info["comp_err"] - comp_o) <= 1e-4
     assert host(W).min() >= 0 and host(H).min() >= 0
 
 
