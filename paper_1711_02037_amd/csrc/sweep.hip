@@ -132,6 +132,7 @@ struct SweepArgs {
   int nsweeps; double tol; int gram_mode, order;
   double aw, ah, bw, bh;  // ridge (alpha) and LASSO (beta) weights
   int G, GR, GC, rows_per, cols_per, rows_lds, lq, cb;
+  int xown;              // the last xown workgroups own the per-column exchange blocks
   int red2_elems;
   int alias_sv;          // S shares V's LDS slot (no projected gradient needed)
   u64* trace;            // optional phase timestamps (workgroup 0, first sweep)
@@ -404,6 +405,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   const int c0 = g * a.cols_per;
   int nc = a.n - c0; if (nc > a.cols_per) nc = a.cols_per; if (nc < 0) nc = 0;
   const int nrl = nr < a.rows_lds ? nr : a.rows_lds;  // rows whose Q lives in LDS
+  const bool xowner_wg = a.xown > 0 && g >= a.G - a.xown;  // dedicated exchange owner (no rows)
   const int lq = a.lq;
 
   // LDS carve-up (red2 first so that it is 8-byte aligned for the FP64 sums)
@@ -806,12 +808,13 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // register GEMV reduced over the 8 column-group lanes), the local map-back
   // (reduced over the row groups: the 8 of a wave by lane permutes, then the
   // waves through LDS), and one device-wide exchange of the l-vector through
-  // the block owners; while it is in flight, threads t >= 128 prepare the next
-  // column's update vector without the column being exchanged, whose term is
-  // added once its value arrives.
+  // the block owners.  While it is in flight, thread t < l forms the part of
+  // the next column's update that does not involve the column being exchanged
+  // (its term is added once the value arrives, so one workgroup barrier
+  // separates the arrival from the next lift), and threads t >= 128 form the
+  // local partial sums of S = W^T W for the finished columns.
   auto w_phase_reg = [&]() __attribute__((always_inline)) -> bool {
     T* part = red2;                    // 8 x 72: per-wave map-back partials
-    T* cpart = red2 + 8 * 72;          // 5 x LPS: partial sums for the next update vector
     double* spart = (double*)(red2 + 8 * 72 + 5 * LPS);  // 2 x 384: local S partial sums
     T* ored = red2 + 8 * 72 + 5 * LPS + 768 * 8 / sizeof(T);  // 128: exchange owner's wave sums
     const int nblk_x = (l * Words<T>::n + 15) / 16;          // 16-word blocks of the l-vector
@@ -840,6 +843,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     }
     lds_sync();
     while (jj < k) {
+      if (!xowner_wg) {
       // lift and clip: W(r, j) = max(0, Q(r, :) v - beta_w / (V_jj + alpha_w))
       const T shift = bw / (Vm[jj * k + jj] + aw);
       T vs[CQ];
@@ -881,6 +885,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
         for (int s = 0; s < CQ; ++s) part[wave * 72 + gc * CQ + s] = pv[s];
       }
+      }  // !xowner_wg
       const int nj = next_col(jj);
       lds_sync();
       if (tr_sweep) { TRACE(5 + 2 * jj); }
@@ -892,23 +897,27 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       const size_t slot = (size_t)LPS * 2;
       u64* P = a.xs_part + ((size_t)par * a.G) * slot;
       u64* RS = a.xs_row + ((size_t)par * a.G) * slot;
-      if (t < l) {
+      T cs = (T)0;  // sum over i != jj of W~(t, i) V(i, nj): the known part of the next update
+      if (t < l && !xowner_wg) {
         T s = part[t];
 #pragma unroll
         for (int wv = 1; wv < 8; ++wv) s += part[wv * 72 + t];
         put<T>(P + (size_t)x.g * slot, t, s, e);
-      } else if (t >= 128) {
         if (nj < k) {
-          // sum over i != jj of W~(a, i) V(i, nj), in 5 parts of the index range
-          const int h = t - 128, aa = h % l, pt = h / l;
-          if (pt < 5) {
-            const int i0 = (k * pt) / 5, i1 = (k * (pt + 1)) / 5;
-            T s = (T)0;
-            for (int ii = i0; ii < i1; ++ii)
-              if (ii != jj) s = fma(Wts[aa * k + ii], Vm[ii * k + nj], s);
-            cpart[pt * LPS + aa] = s;
+          // row t of W~ is private to thread t during the W phase
+          const T* wr = Wts + t * k;
+          T c0 = (T)0, c1 = (T)0, c2 = (T)0, c3 = (T)0;
+          int ii = 0;
+          for (; ii + 4 <= k; ii += 4) {
+            c0 = fma(ii == jj ? (T)0 : wr[ii], Vm[ii * k + nj], c0);
+            c1 = fma(ii + 1 == jj ? (T)0 : wr[ii + 1], Vm[(ii + 1) * k + nj], c1);
+            c2 = fma(ii + 2 == jj ? (T)0 : wr[ii + 2], Vm[(ii + 2) * k + nj], c2);
+            c3 = fma(ii + 3 == jj ? (T)0 : wr[ii + 3], Vm[(ii + 3) * k + nj], c3);
           }
+          for (; ii < k; ++ii) c0 = fma(ii == jj ? (T)0 : wr[ii], Vm[ii * k + nj], c0);
+          cs = (c0 + c1) + (c2 + c3);
         }
+      } else if (t >= 128) {
         if (need_S) {
           // local S(i, j) = sum_r W(r, i) W(r, j) for i <= j (columns i < j
           // are final): entry i, rows r = p, p + P, ... in part p
@@ -938,29 +947,26 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         }
       }
       // block owners sum the partials; every workgroup then reads the totals
-      for (int b = 0; b < nblk_x; ++b)
-        if (((nblk_x <= a.G) ? (b * a.G) / nblk_x : b % a.G) == g)
-          owner_block<T>(P, RS, a.G, slot, l, b, ncopy_x, e, ored, ok);
-      if (t < l) wt = gather_sum<T>(RS + (size_t)(g % ncopy_x) * slot, slot, 1, t, e, ok);
-      s_cols |= 1ull << jj;
-      if (!ok) abort_flag = 1;
-      lds_sync();
-      if (abort_flag) return false;
-      jprev = jj;
-      if (t < l) {
+      for (int b = 0; b < nblk_x; ++b) {
+        const int ow = a.xown > 0 ? a.G - a.xown + b : ((nblk_x <= a.G) ? (b * a.G) / nblk_x : b % a.G);
+        if (ow == g) owner_block<T>(P, RS, a.G - a.xown, slot, l, b, ncopy_x, e, ored, ok);
+      }
+      if (t < l && !xowner_wg) {
+        wt = gather_sum<T>(RS + (size_t)(g % ncopy_x) * slot, slot, 1, t, e, ok);
         Wts[t * k + jj] = wt;
         if (g == 0 && !(wt == wt)) atomicOr(a.status, ST_NONFINITE_SWEEP);
         if (nj < k) {
-          T s = cpart[t];
-#pragma unroll
-          for (int pt = 1; pt < 5; ++pt) s += cpart[pt * LPS + t];
-          s = fma(wt, Vm[jj * k + nj], s);
+          const T s = fma(wt, Vm[jj * k + nj], cs);
           const T wo = Wts[t * k + nj];
           vec[t] = wo + ((Tm[t * k + nj] - s) - aw * wo) / (Vm[nj * k + nj] + aw);
         }
       }
+      s_cols |= 1ull << jj;
+      if (!ok) abort_flag = 1;
       if (tr_sweep) { TRACE(6 + 2 * jj); }
       lds_sync();
+      if (abort_flag) return false;
+      jprev = jj;
       jj = nj;
     }
     if (need_S && jprev >= 0) {
@@ -1212,8 +1218,15 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   sh.G = G;
   sh.GC = G < 16 ? G : 16;
   sh.GR = G / sh.GC;
-  sh.rows_per = ceil_div(m, G);
-  sh.cols_per = ceil_div(n, G);
+  // with many workgroups, the per-column exchange of the register-slab W
+  // phase is served by dedicated owner workgroups (one per 16-word block of
+  // the l-vector) that hold no rows or columns, so that no workgroup's local
+  // work sits on the exchange's critical path; dropped below if the Q slab
+  // does not fit in registers
+  const int xown = (G >= 64) ? (l * (dt == 0 ? 2 : 1) + 15) / 16 : 0;
+  sh.xown = xown;
+  sh.rows_per = ceil_div(m, G - xown);
+  sh.cols_per = ceil_div(n, G - xown);
   sh.cb = l * k + k * k;
   sh.nt = NTH;
   const size_t es = dt == 0 ? 8 : 4;
@@ -1229,9 +1242,23 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   red2 = round_up(red2, 4);
   sh.red2_elems = (int)red2;
   // REGQ needs the W rows and the B and H columns in LDS besides the fixed part
-  const size_t regq_extra = ((size_t)sh.rows_per * k + (size_t)(l + k) * sh.cols_per) * es;
-  const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
-  const bool regq_fits = sh.rows_per <= 64 * RQ && l <= 8 * CQ && fixed2 + regq_extra + 1024 <= (size_t)d.max_lds;
+  auto regq_extra_of = [&]() {
+    return ((size_t)sh.rows_per * k + (size_t)(l + k) * sh.cols_per) * es;
+  };
+  auto regq_fits_of = [&]() {
+    const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
+    return sh.rows_per <= 64 * RQ && l <= 8 * CQ && fixed2 + regq_extra_of() + 1024 <= (size_t)d.max_lds;
+  };
+  bool regq_fits = regq_fits_of();
+  if (!regq_fits && sh.xown) {
+    // without the owners the rows spread over all workgroups; the LDS-slab
+    // path exchanges by the two-hop scheme over all workgroups
+    sh.xown = 0;
+    sh.rows_per = ceil_div(m, G);
+    sh.cols_per = ceil_div(n, G);
+    regq_fits = regq_fits_of();
+  }
+  const size_t regq_extra = regq_extra_of();
   sh.alias_sv = (need_pg || regq_fits) ? 0 : 1;
   size_t fixed = ((size_t)l * k + (size_t)l * k + (size_t)(sh.alias_sv ? 1 : 2) * k * k + LPS + sh.rows_per + red2) * es;
   size_t budget = (size_t)d.max_lds - 1024;  // static shared + alignment slack
@@ -1272,7 +1299,7 @@ hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void*
   a.aw = reg.aw; a.ah = reg.ah; a.bw = reg.bw; a.bh = reg.bh;                                    \
   a.G = sh.G; a.GR = sh.GR; a.GC = sh.GC; a.rows_per = sh.rows_per; a.cols_per = sh.cols_per;  \
   a.rows_lds = sh.rows_lds; a.lq = l | 1; a.cb = sh.cb; a.red2_elems = sh.red2_elems;               \
-  a.alias_sv = sh.alias_sv; a.trace = trace;                                                     \
+  a.alias_sv = sh.alias_sv; a.trace = trace; a.xown = sh.xown;                                    \
   a.xs_part = xs_part; a.xs_row = xs_row; a.xb_part = xb_part; a.xb_row = xb_row;              \
   a.xb_fin = xb_fin; a.lpw = slot; a.cbw = cbw; a.csw = csw; a.stats = stats; a.status = status;
   if (dt == 0) {
