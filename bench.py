@@ -164,6 +164,11 @@ def main():
 
     # ---- passes over X: compression = one X pass ------------------------------
     Q32 = rn.sketch(X, k, p, q, omega=Om)
+    split = sweep_split(rn, torch, X, Q32, W0, H0, k)
+    roofline["limited_by"] = ("latency of the k-long chain of device-wide exchanges (one per W column); "
+                              "the FLOP fraction is reported against the FP32 vector peak")
+    roofline["per_sweep_us"] = split
+    log(f"sweep split: {split}")
     Xb = rn.cast_bf16(X)
     Qb = rn.sketch(Xb, k, p, q, omega=Om, precision="bf16")
     cws = rn._workspace(max(rn.workspace_bytes(rn.OP_COMPRESS, m, n, rn.make_opts(k, p, q, precision=pr))
@@ -408,6 +413,29 @@ def hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev):
             "speedup_per_sweep": round(ms / sweeps / r_ms_sweep, 3),
             "speedup_200_sweeps": round(ms / r_ms_run, 3),
             "note": "HALS streams X twice per sweep; rHALS streams it (2q+2) times once, then sweeps on B"}
+
+
+def sweep_split(rn, torch, X, Q, W0, H0, k):
+    """Where a sweep's time goes: one traced two-sweep launch (phase timestamps
+    of workgroup 0 in the first sweep, from the device's 100 MHz counter) on
+    this workload's Q and B = Q^T X.  Per W column: the device-wide exchange
+    (from the column's partial store to its totals) and the local work between
+    exchanges (update vector, lift, clip, map-back)."""
+    B = rn.compress(X, Q)
+    Wt0 = rn.compress(W0, Q)
+    W, Wt, H = W0.clone(), Wt0.clone(), H0.clone()
+    ts = rn.hals_step(Q, B, W, Wt, H, nsweeps=2, trace=True)[3]
+    pre = [ts[5 + 2 * j] for j in range(k)]
+    post = [ts[6 + 2 * j] for j in range(k)]
+    if any(v is None for v in pre + post + [ts[2], ts[3], ts[4], ts[5 + 2 * k], ts[7 + 2 * k], ts[8 + 2 * k]]):
+        return None
+    ex = [b - a for a, b in zip(pre, post)]
+    loc = [pre[j] - post[j - 1] for j in range(1, k)]
+    return {"sweep": round(ts[8 + 2 * k] - ts[2], 2), "h_phase": round(ts[3] - ts[2], 2),
+            "tv_products_and_exchange": round(ts[4] - ts[3], 2), "w_phase": round(ts[5 + 2 * k] - ts[4], 2),
+            "s_products_and_exchange": round(ts[7 + 2 * k] - ts[5 + 2 * k], 2),
+            "per_column_exchange": round(sum(ex) / len(ex), 3), "per_column_local": round(sum(loc) / len(loc), 3),
+            "columns": k, "source": "first sweep of a traced launch, workgroup 0"}
 
 
 def svd_init_compare(rn, torch, X, Om, Q, k, p, q, sweeps, reps_f, ws_dev, reps=5):

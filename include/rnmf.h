@@ -210,7 +210,8 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
  * the device's 100 MHz real-time counter for the first sweep (entry, Q slab
  * loaded, prologue, H phase, T/V exchange, each W column before and after its
  * exchange, W phase, local S, S exchange, sweep end, kernel end) as uint64 at
- * byte offset 1024 of ws.  Asynchronous. */
+ * byte offset 1024 of ws, and at entry 120 the end of the local T/V products
+ * (before their exchange).  Asynchronous. */
 rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
                            int32_t l, int32_t k, void* W, void* Wt, void* H,
                            int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,

@@ -63,6 +63,39 @@ def rhals_sweep_t(Q, B, W, Wt, H):
     return torch.stack(w_cols, dim=1), torch.stack(wt_cols, dim=1), H
 
 
+def rhals_sweep_t_masked(Q, B, W, Wt, H, mW, mH):
+    """rhals_sweep_t with every clip replaced by a given activity: mH (k x n)
+    and mW (m x k) hold 1 where the clipped value is kept and 0 where it is
+    set to zero.  With the activities of a trajectory, this sweep is the
+    linear piece of the unrolled map that the trajectory lies on; its
+    derivative is the one reading R22 gives there (0 where the activity is
+    0, including a pre-clip value of exactly 0)."""
+    k = H.shape[0]
+    R = B.T @ Wt
+    S = W.T @ W
+    rows = [H[j] for j in range(k)]
+    for j in range(k):
+        d = S[j, j]
+        if d.item() > 0.0:
+            Hc = torch.stack(rows)
+            a = rows[j] + (R[:, j] - Hc.T @ S[:, j]) / d
+            rows[j] = a * mH[j]
+    H = torch.stack(rows)
+    T = B @ H.T
+    V = H @ H.T
+    wt_cols = [Wt[:, j] for j in range(k)]
+    w_cols = [W[:, j] for j in range(k)]
+    for j in range(k):
+        d = V[j, j]
+        if d.item() > 0.0:
+            Wtc = torch.stack(wt_cols, dim=1)
+            u = wt_cols[j] + (T[:, j] - Wtc @ V[:, j]) / d
+            w = (Q @ u) * mW[:, j]
+            w_cols[j] = w
+            wt_cols[j] = Q.T @ w
+    return torch.stack(w_cols, dim=1), torch.stack(wt_cols, dim=1), H
+
+
 def unrolled(Q, X, W0, H0, T):
     """(W_T, H_T) after T sweeps from W0, H0 on B = Q^T X (reading R21), as
     torch float64 tensors connected to X, W0 and H0."""
@@ -100,6 +133,44 @@ def grads(Q, X, W0, H0, T, gW=None, gH=None):
     L.backward()
     return (Xt.grad.numpy(), W0t.grad.numpy(), H0t.grad.numpy(), float(L.detach()),
             W.detach().numpy(), H.detach().numpy())
+
+
+def trajectory_masks(Q, X, W0, H0, T):
+    """Activities (W_t > 0, H_t > 0) after each of the T sweeps of the float64
+    trajectory, as boolean numpy arrays."""
+    if torch is None:
+        raise RuntimeError("torch is needed for the reference gradients")
+    Qt, B = _t(Q), _t(Q).T @ _t(X)
+    W, Wt, H = _t(W0), _t(Q).T @ _t(W0), _t(H0)
+    out = []
+    with torch.no_grad():
+        for _ in range(T):
+            W, Wt, H = rhals_sweep_t(Qt, B, W, Wt, H)
+            out.append(((W > 0).numpy().copy(), (H > 0).numpy().copy()))
+    return out
+
+
+def grads_masked(Q, X, W0, H0, T, masks):
+    """Gradients of the loss of reading R23 through T sweeps in which sweep t
+    uses the activities masks[t] = (mW, mH) instead of its clips: the
+    derivative of the unrolled map on the piece those activities select.
+    Given the activities of a trajectory computed in another precision, it
+    is that trajectory's exact gradient, free of the clip decisions that
+    rounding moved.  Returns (gX, gW0, gH0, loss)."""
+    if torch is None:
+        raise RuntimeError("torch is needed for the reference gradients")
+    Qt = _t(Q)
+    Xt = _t(X).requires_grad_(True)
+    W0t = _t(W0).requires_grad_(True)
+    H0t = _t(H0).requires_grad_(True)
+    B = Qt.T @ Xt
+    W, Wt, H = W0t, Qt.T @ W0t, H0t
+    for t in range(T):
+        mW, mH = masks[t]
+        W, Wt, H = rhals_sweep_t_masked(Qt, B, W, Wt, H, _t(mW), _t(mH))
+    L = loss_t(Xt, W, H)
+    L.backward()
+    return Xt.grad.numpy(), W0t.grad.numpy(), H0t.grad.numpy(), float(L.detach())
 
 
 def active_sets(Q, X, W0, H0, T):

@@ -332,7 +332,7 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
     s = stats.cpu().tolist()
     _check(lib().rnmf_read_status(_ptr(w), w.numel(), _stream(Q.device)))
     if trace:
-        ts = w[1024:1024 + 8 * (13 + 2 * k)].cpu().view(torch.int64).tolist()
+        ts = w[1024:1024 + 8 * 128].cpu().view(torch.int64).tolist()
         t0 = ts[0]
         return int(s[0]), s[1], s[2], [(x - t0) / 100.0 if x else None for x in ts]
     return int(s[0]), s[1], s[2]

@@ -173,62 +173,105 @@ __device__ __forceinline__ bool allreduce_small(const SweepArgs<T>& a, Xch& x, V
   return *abort_flag == 0;
 }
 
-// All-reduce of c <= cb values of type T held in LDS `vals` (in/out).
+// All-reduce of c <= cb values of type T held in LDS `vals` (in/out), by
+// slice owners.  Every source workgroup stores its c partial sums in its
+// slot; workgroup g then owns the slice [g cs, g cs + cs) (cs = ceil(c / G)):
+// thread (group sg, element ei) loads element ei from the slots sg, sg + SG,
+// ... (up to 16 words in flight), the group sums go through LDS and are added
+// in group order, and the slice totals are stored once.  Finally every
+// workgroup reads all c totals.  Each total is formed by one workgroup in a
+// fixed order, so all workgroups receive bit-identical values.  The dedicated
+// exchange owners (no rows or columns) add nothing and store no partials.
+// `red` is LDS scratch of at least NTH values.
 template <typename T>
-__device__ __forceinline__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, int* abort_flag) {
+__device__ __forceinline__ bool allreduce_big(const SweepArgs<T>& a, Xch& x, T* vals, int c, T* red,
+                                              int* abort_flag) {
+  constexpr int W = Words<T>::n;
+  constexpr int MAXL = 16 / W;  // source slots per thread per round
   const int t = threadIdx.x;
   const unsigned e = ++x.seq;
   const unsigned par = (x.big_use++) & 1u;
-  const int cs = (c + a.GC - 1) / a.GC;
-  const int s0 = x.j * cs;
-  const int s1 = (s0 + cs < c) ? s0 + cs : c;
-  u64* P = a.xb_part;
-  u64* RS = a.xb_row + (size_t)par * a.G * a.csw;
-  u64* FN = a.xb_fin + (size_t)par * a.G * a.csw;
+  const int G = a.G, Gs = a.G - a.xown;
+  const int cs = (c + G - 1) / G;
+  const u64* P = a.xb_part;
+  u64* FN = a.xb_fin + (size_t)par * G * a.csw;  // slice totals: element v at word v * W
   bool ok = true;
-  for (int v = t; v < c; v += NTH) put<T>(P + (size_t)x.g * a.cbw, v, vals[v], e);
-  lds_sync();
-  for (int v = s0 + t; v < s1; v += NTH) {
-    T r = gather_sum<T>(P + (size_t)x.i * a.GC * a.cbw, a.cbw, a.GC, v, e, ok);
-    if (a.GR > 1) put<T>(RS + (size_t)x.g * a.csw, v - s0, r, e);
-    else put<T>(FN + (size_t)x.g * a.csw, v - s0, r, e);
-  }
-  if (a.GR > 1) {
-    for (int v = s0 + t; v < s1; v += NTH) {
-      T r = gather_sum<T>(RS + (size_t)x.j * a.csw, (size_t)a.GC * a.csw, a.GR, v - s0, e, ok);
-      put<T>(FN + (size_t)x.g * a.csw, v - s0, r, e);
-    }
-  }
-  // all-gather of the slices from the row: PB elements per thread in flight
-  constexpr int W = Words<T>::n;
-  constexpr int PB = 8;
-  for (int v0 = t; v0 < c; v0 += NTH * PB) {
-    u64 w[PB][W];
-    const u64* ad[PB];
+  if (x.g < Gs)
+    for (int v = t; v < c; v += NTH) put<T>(a.xb_part + (size_t)x.g * a.cbw, v, vals[v], e);
+  const int v0 = x.g * cs, v1 = (v0 + cs < c) ? v0 + cs : c;
+  for (int b0 = v0; b0 < v1; b0 += NTH) {
+    const int cc = (v1 - b0 < NTH) ? v1 - b0 : NTH;
+    const int sgc = NTH / cc;
+    const int ei = t % cc, sg = t / cc;
+    if (sg < sgc) {
+      T acc = (T)0;
+      for (int r0 = sg; r0 < Gs; r0 += sgc * MAXL) {
+        u64 w[MAXL][W];
 #pragma unroll
-    for (int b = 0; b < PB; ++b) {
-      const int v = v0 + b * NTH;
-      if (v < c) {
-        const int jj = v / cs;
-        ad[b] = FN + ((size_t)x.i * a.GC + jj) * a.csw + (size_t)(v - jj * cs) * W;
+        for (int q = 0; q < MAXL; ++q) {
+          const int src = r0 + q * sgc;
 #pragma unroll
-        for (int h = 0; h < W; ++h) w[b][h] = ld_ll(ad[b] + h);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < PB; ++b) {
-      const int v = v0 + b * NTH;
-      if (v < c) {
-#pragma unroll
-        for (int h = 0; h < W; ++h) {
-          long spins = 0;
-          while ((unsigned)(w[b][h] >> 32) != e) {
-            if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
-            w[b][h] = ld_ll(ad[b] + h);
-          }
+          for (int h = 0; h < W; ++h)
+            w[q][h] = src < Gs ? ld_ll(P + (size_t)src * a.cbw + (size_t)(b0 + ei) * W + h) : ((u64)e << 32);
         }
-        vals[v] = value_of<T>(w[b]);
+        long spins = 0;
+        while (true) {
+          bool all = true;
+#pragma unroll
+          for (int q = 0; q < MAXL; ++q)
+#pragma unroll
+            for (int h = 0; h < W; ++h) all = all && ((unsigned)(w[q][h] >> 32) == e);
+          if (all) break;
+          if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
+#pragma unroll
+          for (int q = 0; q < MAXL; ++q)
+#pragma unroll
+            for (int h = 0; h < W; ++h)
+              if ((unsigned)(w[q][h] >> 32) != e)
+                w[q][h] = ld_ll(P + (size_t)(r0 + q * sgc) * a.cbw + (size_t)(b0 + ei) * W + h);
+        }
+#pragma unroll
+        for (int q = 0; q < MAXL; ++q) acc += value_of<T>(w[q]);
       }
+      red[sg * cc + ei] = acc;
+    }
+    lds_sync();
+    if (t < cc) {
+      T tot = (T)0;
+      for (int q = 0; q < sgc; ++q) tot += red[q * cc + t];
+      put<T>(FN, b0 + t, tot, e);
+    }
+    lds_sync();  // red is reused
+  }
+  // all totals: PB elements per thread in flight
+  constexpr int PB = 8;
+  for (int u0 = t; u0 < c; u0 += NTH * PB) {
+    u64 w[PB][W];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int v = u0 + b * NTH;
+#pragma unroll
+      for (int h = 0; h < W; ++h) w[b][h] = v < c ? ld_ll(FN + (size_t)v * W + h) : ((u64)e << 32);
+    }
+    long spins = 0;
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int h = 0; h < W; ++h) all = all && ((unsigned)(w[b][h] >> 32) == e);
+      if (all) break;
+      if (!ok || ++spins > SPIN_LIMIT) { ok = false; break; }
+#pragma unroll
+      for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int h = 0; h < W; ++h)
+          if ((unsigned)(w[b][h] >> 32) != e) w[b][h] = ld_ll(FN + (size_t)(u0 + b * NTH) * W + h);
+    }
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int v = u0 + b * NTH;
+      if (v < c) vals[v] = value_of<T>(w[b]);
     }
   }
   if (!ok) *abort_flag = 1;
@@ -255,7 +298,7 @@ __device__ __forceinline__ T readlane(T v, int lane) {
 // lane of a group obtains the bit-identical sum.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp32(unsigned x) {
-  return (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL, typename T>
 __device__ __forceinline__ T dpp_mov(T x) {
@@ -421,8 +464,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // with the Q slab in registers, LDS also holds this workgroup's rows of W
   // and columns of B and H for the whole launch
   const int cp = a.cols_per;
-  T* Ws = Qs + (size_t)a.rows_lds * lq;           // rows_per x k   (REGQ)
-  T* Bs = Ws + (size_t)a.rows_per * k;            // l x cols_per   (REGQ)
+  T* Ws = Qs + (size_t)a.rows_lds * lq;           // (rows_per + 1) x k (REGQ; the last row is a sink)
+  T* Bs = Ws + (size_t)(a.rows_per + 1) * k;      // l x cols_per   (REGQ)
   T* Hs = Bs + (size_t)l * cp;                    // k x cols_per   (REGQ)
   const T* Bp;
   T* Hp;
@@ -580,7 +623,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       local_wgram();
     }
     if (tr_sweep) { TRACE(6 + 2 * k); }
-    return allreduce_big<T>(a, x, Sm, k * k, &abort_flag);
+    return allreduce_big<T>(a, x, Sm, k * k, red2, &abort_flag);
   };
 
   // --- T = B H^T and V = H H^T over this workgroup's columns ---------------
@@ -675,7 +718,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         }
     }
     lds_sync();
-    return allreduce_big<T>(a, x, U, l * k + k * k, &abort_flag);
+    if (tr_sweep) { TRACE(120); }
+    return allreduce_big<T>(a, x, U, l * k + k * k, red2, &abort_flag);
   };
 
   // --- H phase: this workgroup's columns of H, one wavefront per column -----
@@ -826,6 +870,9 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       while (q < k && !(Vm[q * k + q] + aw > (T)0)) ++q;
       return q;
     };
+    // entries of the update vector past l stay zero, so the lift reads all
+    // CQ entries of its column group without a per-entry predicate
+    for (int e = l + t; e < 8 * CQ; e += NTH) vec[e] = (T)0;
     int jj = next_col(-1);
     if (jj >= k) return true;
     // update vector of the first column: v = W~(:,j) + (T(:,j) - W~ V(:,j)) / V_jj
@@ -848,7 +895,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       const T shift = bw / (Vm[jj * k + jj] + aw);
       T vs[CQ];
 #pragma unroll
-      for (int s = 0; s < CQ; ++s) vs[s] = (gc * CQ + s < l) ? vec[gc * CQ + s] : (T)0;
+      for (int s = 0; s < CQ; ++s) vs[s] = vec[gc * CQ + s];
       T w[RQ];
 #pragma unroll
       for (int i = 0; i < RQ; ++i) {
@@ -862,10 +909,13 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         w[i] = clip0<T>(sum8<T>(u0 + u1) - shift);
       }
       if (gc == 0) {
+        // W is written back once, at the end; rows past the slab land in the
+        // sink row rows_per, or in rows nr .. rows_per - 1 that no one reads
+        // (a clamp instead of a predicate per row)
 #pragma unroll
         for (int i = 0; i < RQ; ++i) {
-          const int rr = ga + 64 * i;
-          if (rr < nr) Ws[rr * k + jj] = w[i];  // W is written back once, at the end
+          const int rr = min(ga + 64 * i, a.rows_per);
+          Ws[rr * k + jj] = w[i];
         }
       }
       // local map-back partials: sum_i Q(r_i, a) w_i over this thread's rows
@@ -1243,7 +1293,7 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   sh.red2_elems = (int)red2;
   // REGQ needs the W rows and the B and H columns in LDS besides the fixed part
   auto regq_extra_of = [&]() {
-    return ((size_t)sh.rows_per * k + (size_t)(l + k) * sh.cols_per) * es;
+    return ((size_t)(sh.rows_per + 1) * k + (size_t)(l + k) * sh.cols_per) * es;
   };
   auto regq_fits_of = [&]() {
     const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;

