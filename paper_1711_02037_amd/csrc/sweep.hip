@@ -291,6 +291,16 @@ __device__ __forceinline__ T readlane(T v, int lane) {
   }
 }
 
+// FP64 matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16 x 4 tile by a
+// 4 x 16 tile; lane (i, g) = (lane % 16, lane / 16) supplies A[i][g] and
+// B[g][i] and receives D[g + 4e][i] in element e (rows interleaved by 4,
+// unlike the FP32 and BF16 forms, whose element e is row 4g + e; checked on
+// gfx950 with distinct entries).
+typedef double dx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dx4 mfma_f64(double a, double b, dx4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Cross-lane sums on the VALU (no LDS round trip).  sum8: over the 8 lanes of
 // an aligned group (lane ^ 1, ^ 2, ^ 4 by DPP quad permutes and the half-row
 // mirror).  sum_stride8: over the 8 lanes with equal lane % 8 (lane ^ 8 by a
@@ -428,10 +438,11 @@ __device__ __forceinline__ void upper_block(int b, int nb, int& r, int& c) {
 }
 
 // Register-resident Q slab (REGQ): thread (wave w, lane L) owns rows
-// {8w + L/8 + 64 i : i < RQ} and columns {9 (L % 8) + s : s < CQ} of the slab.
-constexpr int RQ = 7, CQ = 9;  // at most 448 rows x 72 columns per workgroup
+// {8w + L/8 + 64 i : i < RQ} and columns {CQ (L % 8) + s : s < CQ} of the slab.
+constexpr int RQ = 7;       // at most 448 rows per workgroup
+constexpr int CQMAX = 12;   // at most 8 x 12 = 96 columns (FP32; FP64 takes 9, 72 columns)
 
-template <typename T, bool REGQ>
+template <typename T, bool REGQ, int CQ>
 __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
@@ -513,6 +524,11 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   const bool need_pg = a.tol > 0.0;
   const int RG = (NTH / l < 16) ? NTH / l : 16;
   const int kb = (k + 3) / 4, lb = (l + 3) / 4;
+  // columns per chunk of the H phase's FP64 gradient block (k x hch doubles
+  // at a pitch of hch + 1 in red2); below 8 the H phase takes the lane form
+  int hch = (int)((size_t)a.red2_elems * sizeof(T) / 8 / (size_t)k) - 1;
+  hch &= ~7;
+  if (hch > 8 * ((a.cols_per + 7) / 8)) hch = 8 * ((a.cols_per + 7) / 8);
 
   // --- S = W^T W over this workgroup's rows (4 x 4 register blocks) --------
   // Rows are staged through LDS 32 at a time; the next chunk is loaded into
@@ -630,8 +646,46 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // 4 x 4 register blocks (FP64 accumulation); B and H columns are staged
   // through LDS 8 columns at a time.
   auto tv_exchange = [&]() __attribute__((always_inline)) -> bool {
-    if constexpr (REGQ) lds_sync();
-    else __syncthreads();  // H columns written by other threads of this workgroup
+    if constexpr (REGQ) {
+      // [B; H] (l + k rows) times H^T over this workgroup's nc columns on FP64
+      // matrix cores: rows below l give T = B H^T, the rest V = H H^T (its
+      // upper triangle, mirrored); one 16 x 16 output tile per wave at a time
+      lds_sync();
+      if (tr_sweep) { TRACE(124); }
+      const int fi = lane & 15, fg = lane >> 4;
+      const int MT = (l + k + 15) / 16, NTt = (k + 15) / 16, KS = (nc + 3) / 4;
+      for (int tile = wave; tile < MT * NTt; tile += NTH / 64) {
+        const int mt = tile / NTt, nt = tile - (tile / NTt) * NTt;
+        const int ra = 16 * mt + fi, cb = 16 * nt + fi;
+        const bool aok = ra < l + k, bok = cb < k;
+        const T* arow = ra < l ? Bs + (size_t)ra * cp : Hs + (size_t)(aok ? ra - l : 0) * cp;
+        const T* brow = Hs + (size_t)(bok ? cb : 0) * cp;
+        dx4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int s4 = 0; s4 < KS; ++s4) {
+          const int cc = 4 * s4 + fg;
+          const double av = (aok && cc < nc) ? (double)arow[cc] : 0.0;
+          const double bv = (bok && cc < nc) ? (double)brow[cc] : 0.0;
+          acc = mfma_f64(av, bv, acc);
+        }
+        if (bok) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 16 * mt + fg + 4 * e;
+            if (r < l) {
+              Tm[r * k + cb] = (T)acc[e];
+            } else if (r < l + k && r - l <= cb) {
+              Vm[(r - l) * k + cb] = (T)acc[e];
+              Vm[cb * k + (r - l)] = (T)acc[e];
+            }
+          }
+        }
+      }
+      if (tr_sweep) { TRACE(125); }
+      lds_sync();
+      if (tr_sweep) { TRACE(120); }
+      return allreduce_big<T>(a, x, U, l * k + k * k, red2, &abort_flag);
+    }
+    __syncthreads();  // H columns written by other threads of this workgroup
     constexpr int CW = 8;
     const int nbt = lb * kb;                 // blocks of T
     const int nbv = kb * (kb + 1) / 2;       // upper blocks of V
@@ -662,6 +716,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         }
       }
       lds_sync();
+      if (tr_sweep) { TRACE(124); }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (isv[q] < 0) continue;
@@ -682,6 +737,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         }
       }
     }
+    if (tr_sweep) { TRACE(125); }
     lds_sync();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -750,6 +806,90 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     // chains are independent, so their latencies overlap.
     constexpr int HI = 3;
     const int jj = lane < k ? lane : 0;
+    if constexpr (REGQ) {
+      if (hch >= 8) {
+        // G = W~^T B - Snum^T H for a chunk of hch columns on FP64 matrix
+        // cores (K = l + k), kept in red2 as doubles (pitch hch + 1), then
+        // the row updates of each column in order.  Every lane forms the
+        // candidate row value of its own row; lane ii's is the update of
+        // step ii, broadcast as the change it makes.
+        lds_sync();  // red2 may still be read by the exchange that precedes
+        double* Gd = (double*)red2;
+        const int gp = hch + 1;
+        const int fi = lane & 15, fg = lane >> 4;
+        const int MT = (k + 15) / 16, KS = (l + k + 3) / 4;
+        for (int cs = 0; cs < nc; cs += hch) {
+          const int w = (nc - cs < hch) ? nc - cs : hch;
+          const int NTc = (w + 15) / 16;
+          for (int tile = wave; tile < MT * NTc; tile += NTH / 64) {
+            const int mt = tile / NTc, nt = tile - (tile / NTc) * NTc;
+            const int jr = 16 * mt + fi, cc = 16 * nt + fi;
+            const bool jok = jr < k, cok = cc < w;
+            const int jc = jok ? jr : 0, ccc = cs + (cok ? cc : 0);
+            dx4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int s4 = 0; s4 < KS; ++s4) {
+              const int kap = 4 * s4 + fg;
+              double av = 0.0, bv = 0.0;
+              if (kap < l) {
+                av = jok ? (double)Wts[kap * k + jc] : 0.0;
+                bv = cok ? (double)Bs[(size_t)kap * cp + ccc] : 0.0;
+              } else if (kap < l + k) {
+                av = jok ? -(double)Snum[(kap - l) * k + jc] : 0.0;
+                bv = cok ? (double)Hs[(size_t)(kap - l) * cp + ccc] : 0.0;
+              }
+              acc = mfma_f64(av, bv, acc);
+            }
+            if (cok) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int r = 16 * mt + fg + 4 * e;
+                if (r < k) Gd[r * gp + cc] = acc[e];
+              }
+            }
+          }
+          if (tr_sweep && cs == 0) { TRACE(121); }
+          lds_sync();
+          if (tr_sweep && cs == 0) { TRACE(122); }
+          for (int cb = wave; cb < w; cb += (NTH / 64) * HI) {
+            bool live[HI];
+            double h[HI], gs[HI], hn[HI];
+#pragma unroll
+            for (int q = 0; q < HI; ++q) {
+              const int cc = cb + (NTH / 64) * q;
+              live[q] = cc < w;
+              const int c = live[q] ? cc : cb;
+              h[q] = lane < k ? (double)Hs[(size_t)lane * cp + cs + c] : 0.0;
+              gs[q] = lane < k ? Gd[lane * gp + c] - fma(a.ah, h[q], a.bh) : 0.0;
+              hn[q] = h[q];
+            }
+            // a zero scale (rinv 0) gives the lane's own value back: change +0
+            T s_nx = Snum[jj];
+            for (int ii = 0; ii < k; ++ii) {
+              const double sij = (double)s_nx;
+              s_nx = Snum[(ii + 1 < k ? ii + 1 : ii) * k + jj];
+#pragma unroll
+              for (int q = 0; q < HI; ++q) {
+                // the new row is rounded to the storage type before it is used
+                const double cand = (double)clip0<T>((T)fma(gs[q], rinv_l, h[q]));
+                const double d = readlane<double>(cand - h[q], ii);
+                if (lane == ii) hn[q] = cand;
+                gs[q] = fma(-sij, d, gs[q]);
+              }
+            }
+            if (tr_sweep && cs == 0 && cb == wave) {
+              if (wave == 0) { TRACE(123); }
+              // wavefront 7's end of the row updates (traced launches only)
+              if (a.trace && g == 0 && wave == 7 && lane == 0) a.trace[126] = __builtin_amdgcn_s_memrealtime();
+            }
+#pragma unroll
+            for (int q = 0; q < HI; ++q)
+              if (live[q] && lane < k) Hs[(size_t)lane * cp + cs + cb + (NTH / 64) * q] = (T)hn[q];
+          }
+          lds_sync();  // the next chunk reuses red2; the H columns are read next
+        }
+        return;
+      }
+    }
     const int l0 = l < 64 ? l : 64;
     for (int cb = wave; cb < nc; cb += (NTH / 64) * HI) {
       bool live[HI];
@@ -791,6 +931,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
         for (int q = 0; q < HI; ++q) R1[q] = fma((double)readlane<T>(b1[q], aa - 64), w1, R1[q]);
       }
+      if (tr_sweep) { TRACE(121); }
       double g0[HI], g1[HI];
 #pragma unroll
       for (int q = 0; q < HI; ++q) { g0[q] = R0[q] + R1[q]; g1[q] = 0.0; }
@@ -817,6 +958,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       double gsum[HI];
 #pragma unroll
       for (int q = 0; q < HI; ++q) gsum[q] = (g0[q] + g1[q]) - fma(a.ah, h[q], a.bh);
+      if (tr_sweep) { TRACE(122); }
       // Gauss-Seidel over the rows: the scale comes from a register by lane
       // broadcast and the next S entry is loaded one step ahead, so no LDS
       // round trip sits on the chain
@@ -839,6 +981,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           gsum[q] = fma(-sij, delta, gsum[q]);
         }
       }
+      if (tr_sweep) { TRACE(123); }
 #pragma unroll
       for (int q = 0; q < HI; ++q)
         if (live[q] && lane < k) Hp[(size_t)lane * ldH + cb + (NTH / 64) * q] = (T)h[q];
@@ -858,9 +1001,10 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // separates the arrival from the next lift), and threads t >= 128 form the
   // local partial sums of S = W^T W for the finished columns.
   auto w_phase_reg = [&]() __attribute__((always_inline)) -> bool {
-    T* part = red2;                    // 8 x 72: per-wave map-back partials
-    double* spart = (double*)(red2 + 8 * 72 + 5 * LPS);  // 2 x 384: local S partial sums
-    T* ored = red2 + 8 * 72 + 5 * LPS + 768 * 8 / sizeof(T);  // 128: exchange owner's wave sums
+    constexpr int PW = 8 * CQ;         // row of the per-wave partials
+    T* part = red2;                    // 8 x PW: per-wave map-back partials
+    double* spart = (double*)(red2 + 8 * 8 * CQMAX + 5 * LPS);  // 2 x 384: local S partial sums
+    T* ored = red2 + 8 * 8 * CQMAX + 5 * LPS + 768 * 8 / sizeof(T);  // 128: exchange owner's wave sums
     const int nblk_x = (l * Words<T>::n + 15) / 16;          // 16-word blocks of the l-vector
     const int ncopy_x = a.G < 16 ? a.G : 16;                 // copies of the totals
     int jprev = -1;  // column whose S partials await their reduction
@@ -933,7 +1077,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       }
       if (lane < 8) {
 #pragma unroll
-        for (int s = 0; s < CQ; ++s) part[wave * 72 + gc * CQ + s] = pv[s];
+        for (int s = 0; s < CQ; ++s) part[wave * PW + gc * CQ + s] = pv[s];
       }
       }  // !xowner_wg
       const int nj = next_col(jj);
@@ -951,7 +1095,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       if (t < l && !xowner_wg) {
         T s = part[t];
 #pragma unroll
-        for (int wv = 1; wv < 8; ++wv) s += part[wv * 72 + t];
+        for (int wv = 1; wv < 8; ++wv) s += part[wv * PW + t];
         put<T>(P + (size_t)x.g * slot, t, s, e);
         if (nj < k) {
           // row t of W~ is private to thread t during the W phase
@@ -1286,7 +1430,7 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   size_t stage = 32 * (size_t)(4 * ((k + 3) / 4));
   if (stage > red2) red2 = stage;
   if ((size_t)(LMAX + KMAX) * 8 > red2) red2 = (size_t)(LMAX + KMAX) * 8;  // T/V column staging
-  if ((size_t)(8 * 72 + 5 * LPS) + 768 * 8 / es + 128 > red2) red2 = 8 * 72 + 5 * LPS + 768 * 8 / es + 128;  // W phase (REGQ)
+  if ((size_t)(8 * 8 * CQMAX + 5 * LPS) + 768 * 8 / es + 128 > red2) red2 = 8 * 8 * CQMAX + 5 * LPS + 768 * 8 / es + 128;  // W phase (REGQ)
 
   if ((size_t)NTH * 8 / es > red2) red2 = (size_t)NTH * 8 / es;  // pg reduction as doubles
   red2 = round_up(red2, 4);
@@ -1297,7 +1441,7 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   };
   auto regq_fits_of = [&]() {
     const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
-    return sh.rows_per <= 64 * RQ && l <= 8 * CQ && fixed2 + regq_extra_of() + 1024 <= (size_t)d.max_lds;
+    return sh.rows_per <= 64 * RQ && l <= 8 * (dt == 0 ? 9 : CQMAX) && fixed2 + regq_extra_of() + 1024 <= (size_t)d.max_lds;
   };
   bool regq_fits = regq_fits_of();
   if (!regq_fits && sh.xown) {
@@ -1355,14 +1499,15 @@ hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void*
   if (dt == 0) {
     FILL_ARGS(double);
     void* args[] = {&a};
-    const void* fn = sh.regq ? (const void*)sweep_kernel<double, true> : (const void*)sweep_kernel<double, false>;
+    const void* fn = sh.regq ? (const void*)sweep_kernel<double, true, 9> : (const void*)sweep_kernel<double, false, 1>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);
   } else {
     FILL_ARGS(float);
     void* args[] = {&a};
-    const void* fn = sh.regq ? (const void*)sweep_kernel<float, true> : (const void*)sweep_kernel<float, false>;
+    const void* fn = !sh.regq ? (const void*)sweep_kernel<float, false, 1>
+                     : (l <= 72) ? (const void*)sweep_kernel<float, true, 9> : (const void*)sweep_kernel<float, true, 12>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);

@@ -132,7 +132,8 @@ def sweep_inputs(m, n, k, l, seed, dt):
 
 @pytest.mark.parametrize("gram", ["full", "lowdim", "mixed"])
 @pytest.mark.parametrize("order", ["h_first", "w_first"])
-@pytest.mark.parametrize("m,n,k,l", [(1000, 300, 10, 30), (5003, 1711, 50, 70), (40, 33, 3, 8)])
+@pytest.mark.parametrize("m,n,k,l", [(1000, 300, 10, 30), (5003, 1711, 50, 70), (40, 33, 3, 8),
+                                     (20000, 3000, 40, 84), (3001, 1025, 50, 96)])  # Q slab of 12 columns a lane
 def test_hals_step_one_sweep_fp32(gram, order, m, n, k, l):
     Q, B, W, Wt, H = sweep_inputs(m, n, k, l, 21, np.float32)
     d = [dev(a) for a in (Q, B, W, Wt, H)]
