@@ -210,8 +210,11 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
  * the device's 100 MHz real-time counter for the first sweep (entry, Q slab
  * loaded, prologue, H phase, T/V exchange, each W column before and after its
  * exchange, W phase, local S, S exchange, sweep end, kernel end) as uint64 at
- * byte offset 1024 of ws, and at entry 120 the end of the local T/V products
- * (before their exchange).  Asynchronous. */
+ * byte offset 1024 of ws; entries 120 to 125 mark steps inside the phases for
+ * the register-slab kernel: 120 the end of the local T/V products (before
+ * their exchange), 124 and 125 the start and end of their arithmetic; 121,
+ * 122 and 123 the H phase of wavefront 0 after R = B^T W~, after the S terms
+ * and after the row updates.  Asynchronous. */
 rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
                            int32_t l, int32_t k, void* W, void* Wt, void* H,
                            int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,
@@ -371,6 +374,11 @@ typedef struct rnmf_problem {
   float* Z;            /* scratch: n x l (holds B^T during the sweeps)        */
   int64_t m, n, ldx;
   int32_t k, l;
+  int32_t prec;        /* RNMF_PREC_F32, or RNMF_PREC_BF16: the passes over X
+                          on bf16 matrix cores (X rounded to bfloat16 as it is
+                          staged, the small operand split hi + lo, FP32
+                          accumulation) with one more subspace iteration     */
+  int32_t reserved;    /* must be 0                                           */
 } rnmf_problem;
 
 /* Workspace bytes for a batch of nprob problems (descriptors, queue counter,

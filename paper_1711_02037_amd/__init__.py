@@ -64,7 +64,7 @@ class Problem(ctypes.Structure):
                 ("H0", ctypes.c_void_p), ("W", ctypes.c_void_p), ("H", ctypes.c_void_p),
                 ("Q", ctypes.c_void_p), ("B", ctypes.c_void_p), ("Z", ctypes.c_void_p),
                 ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ldx", ctypes.c_int64),
-                ("k", ctypes.c_int32), ("l", ctypes.c_int32)]
+                ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -591,9 +591,13 @@ class Batch:
     """Batched randomized HALS (rnmf_batch_*): many independent problems in one
     persistent launch.  problems: list of (X, Omega, W0, H0) FP32 device
     tensors (X m x n with unit column stride, Omega n x l, W0 m x k, H0 k x n).
+    precision: "fp32" (FP32 arithmetic) or "bf16" (X passes on bf16 matrix
+    cores from the FP32 X, one more subspace iteration).
     Holds the outputs W, H, Q, B of every problem and the workspace."""
 
-    def __init__(self, problems, autotune=False, q=2):
+    def __init__(self, problems, autotune=False, q=2, precision="fp32"):
+        if precision not in ("fp32", "bf16"):
+            raise ValueError("precision must be 'fp32' or 'bf16'")
         torch = _torch()
         self.problems = []
         descs = (Problem * len(problems))()
@@ -622,6 +626,7 @@ class Batch:
             for key in ("X", "Omega", "W0", "H0", "W", "H", "Q", "B", "Z"):
                 setattr(d, key, out[key].data_ptr())
             d.m, d.n, d.ldx, d.k, d.l = m, n, X.stride(0), k, l
+            d.prec = PREC[precision]
         self.descs = descs
         self.n = len(problems)
         self.device = problems[0][0].device

@@ -517,6 +517,9 @@ rnmf_status check_problem(const rnmf_problem& p, int i) {
   if (p.l < 1 || p.l > 64 || p.l > p.m || p.l > p.n)
     return fail(RNMF_ERR_SHAPE, "problem %d: need 1 <= l <= min(64, m, n) (l = %d)", i, p.l);
   if (p.k < 1 || p.k > 32 || p.k > p.l) return fail(RNMF_ERR_ARG, "problem %d: need 1 <= k <= min(32, l)", i);
+  if (p.prec != RNMF_PREC_F32 && p.prec != RNMF_PREC_BF16)
+    return fail(RNMF_ERR_ARG, "problem %d: prec must be RNMF_PREC_F32 or RNMF_PREC_BF16", i);
+  if (p.reserved != 0) return fail(RNMF_ERR_ARG, "problem %d: reserved must be 0", i);
   return RNMF_OK;
 }
 

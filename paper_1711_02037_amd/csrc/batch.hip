@@ -416,6 +416,244 @@ __device__ __noinline__ void xtq_pass(const float* X, int64_t ldx, int64_t m, in
   else xtq_pass_t<16>(X, ldx, m, n, Q, l, Z, Bout, scr);
 }
 
+// ---------------------------------------------------------------------------
+// X passes on bf16 matrix cores (v_mfma_f32_16x16x32_bf16): X stays FP32 in
+// memory and is rounded to bfloat16 (nearest even) as a chunk is staged in
+// LDS; the small operand (A or Q) is split into hi = bf16(a) and
+// lo = bf16(a - hi), two products per tile, so only X is rounded.  Lane
+// (i, g) = (lane % 16, lane / 16) holds row i of the A operand at k = 8g ..
+// 8g + 7 and column i of the B operand at the same k; D[4g + e][i] comes
+// back in element e.  Products accumulate in FP32 over the whole reduction.
+// Chunks are 128 x 64 elements of X (32 KB); the next chunk's loads are in
+// flight while the current one is multiplied.  Operand tiles in LDS are
+// bfloat16 rows of 64 k values at a pitch of 72 (16-byte fragments, rows
+// 144 bytes apart).
+// ---------------------------------------------------------------------------
+typedef __bf16 bfx8 __attribute__((ext_vector_type(8)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+constexpr int MKC = 64;             // k per chunk (two MFMA steps)
+constexpr int MKP = MKC + 8;        // LDS pitch (bfloat16 elements)
+constexpr int MRB = 128;            // X rows (xa) or X columns (xtq) per block
+constexpr int MXC = MRB * MKC / BT; // X values per thread per chunk
+constexpr int MAC = BLM * MKC / BT; // operand values per thread per chunk
+static_assert((MRB + 2 * BLM) * MKP * 2 <= SCR_FLOATS * 4, "bf16 chunk tiles fit the scratch");
+
+__device__ __forceinline__ unsigned short bf16_rn(float f) {
+  unsigned b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (unsigned short)(b >> 16);
+}
+__device__ __forceinline__ fx4 mfma_bf16(bfx8 a, bfx8 b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Operand chunk: rows k0 .. k0 + MKC - 1 of a packed (rows x l) matrix, stored
+// transposed (column j at Oh + j * MKP) as hi and lo planes; rows past the
+// matrix are zero.  Element e = t + s BT of the chunk is row e / l, column e % l.
+__device__ __forceinline__ void op_fetch(float (&v)[MAC], gcf* base, int64_t k0, int64_t rows, int l, int t) {
+#pragma unroll
+  for (int s = 0; s < MAC; ++s) {
+    const int e = t + s * BT;
+    const int kk = e / l, j = e - (e / l) * l;
+    int64_t r = k0 + kk;
+    if (r >= rows) r = rows - 1;
+    v[s] = (e < MKC * l) ? base[r * l + j] : 0.f;
+  }
+}
+__device__ __forceinline__ void op_store(const float (&v)[MAC], unsigned short* Oh, unsigned short* Ol, int64_t k0,
+                                         int64_t rows, int l) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < MAC; ++s) {
+    const int e = t + s * BT;
+    if (e < MKC * l) {
+      const int kk = e / l, j = e - (e / l) * l;
+      const bool ok = k0 + kk < rows;
+      const unsigned short h = bf16_rn(v[s]);
+      const unsigned short lo = bf16_rn(v[s] - __uint_as_float((unsigned)h << 16));
+      Oh[j * MKP + kk] = ok ? h : (unsigned short)0;
+      Ol[j * MKP + kk] = ok ? lo : (unsigned short)0;
+    }
+  }
+}
+
+// Y (m x l) = X (m x n) A (n x l).  Block of 128 rows: wave w owns row tiles
+// w and w + 4; chunks of 64 columns of X (and 64 rows of A) run in sequence.
+__device__ __noinline__ void xa_pass_bf16(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                          const float* __restrict__ A, int l, float* __restrict__ Y_, float* scr) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, i = lane & 15, g = lane >> 4;
+  gf* Y = GW(Y_);
+  gcf* Xg = G(X);
+  gcf* Ag = G(A);
+  unsigned short* Xs = (unsigned short*)scr;  // MRB x MKP
+  unsigned short* Oh = Xs + MRB * MKP;         // BLM x MKP
+  unsigned short* Ol = Oh + BLM * MKP;
+  const int LT = (l + 15) / 16;
+  for (int e = t; e < BLM * MKP; e += BT)
+    if (e / MKP >= l) { Oh[e] = 0; Ol[e] = 0; }  // operand columns past l, never written below
+  const int nr = (int)((m + MRB - 1) / MRB), nc = (int)((n + MKC - 1) / MKC);
+  float xv[MXC], av[MAC];
+  int64_t fr0 = 0, fc0 = 0;
+  auto fetch = [&](int qq) {
+    fr0 = (int64_t)(qq / nc) * MRB;
+    fc0 = (int64_t)(qq % nc) * MKC;
+    // an opaque copy of the thread index keeps the per-element offsets out of
+    // the loop-invariant set (they would be hoisted and spilled otherwise)
+    int tt = t;
+    __asm__ volatile("" : "+v"(tt));
+#pragma unroll
+    for (int s = 0; s < MXC; ++s) {
+      const int e = tt + s * BT;
+      int64_t r = fr0 + (e >> 6), c = fc0 + (e & 63);
+      if (r >= m) r = m - 1;
+      if (c >= n) c = n - 1;
+      xv[s] = Xg[r * ldx + c];
+    }
+    op_fetch(av, Ag, fc0, n, l, tt);
+  };
+  fetch(0);
+  fx4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = fx4{0.f, 0.f, 0.f, 0.f};
+  for (int qq = 0; qq < nr * nc; ++qq) {
+#pragma unroll
+    for (int s = 0; s < MXC; ++s) {
+      const int e = t + s * BT;
+      const bool ok = fr0 + (e >> 6) < m && fc0 + (e & 63) < n;
+      Xs[(e >> 6) * MKP + (e & 63)] = ok ? bf16_rn(xv[s]) : (unsigned short)0;
+    }
+    op_store(av, Oh, Ol, fc0, n, l);
+    const int64_t r0 = fr0;
+    lds_sync();
+    if (qq + 1 < nr * nc) fetch(qq + 1);
+#pragma unroll
+    for (int kk = 0; kk < MKC; kk += 32) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const bfx8 xa = *(const bfx8*)(Xs + (16 * (wave + 4 * rt) + i) * MKP + kk + 8 * g);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          if (ct < LT) {
+            const bfx8 h = *(const bfx8*)(Oh + (16 * ct + i) * MKP + kk + 8 * g);
+            const bfx8 lo = *(const bfx8*)(Ol + (16 * ct + i) * MKP + kk + 8 * g);
+            acc[rt][ct] = mfma_bf16(xa, h, acc[rt][ct]);
+            acc[rt][ct] = mfma_bf16(xa, lo, acc[rt][ct]);
+          }
+      }
+    }
+    lds_sync();
+    if (qq % nc == nc - 1) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t r = r0 + 16 * (wave + 4 * rt) + 4 * g + e;
+            const int c = 16 * ct + i;
+            if (ct < LT && r < m && c < l) Y[r * l + c] = acc[rt][ct][e];
+          }
+          acc[rt][ct] = fx4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  __syncthreads();  // Y is read next by other threads of the workgroup
+}
+
+// Z (n x l) = X^T Q, and optionally B = Z^T (l x n).  Block of 128 columns of
+// X: wave w owns column tiles w and w + 4; chunks of 64 rows of X (and of Q)
+// run in sequence.  The X chunk is stored transposed (column c of X at
+// Xt + c * MKP), so both operands are read as contiguous k fragments.
+__device__ __noinline__ void xtq_pass_bf16(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                           const float* __restrict__ Q, int l, float* __restrict__ Z_,
+                                           float* __restrict__ Bout_, float* scr) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, i = lane & 15, g = lane >> 4;
+  gf* Z = GW(Z_);
+  gf* Bout = Bout_ ? GW(Bout_) : nullptr;
+  gcf* Xg = G(X);
+  gcf* Qg = G(Q);
+  unsigned short* Xt = (unsigned short*)scr;  // MRB x MKP
+  unsigned short* Oh = Xt + MRB * MKP;         // BLM x MKP
+  unsigned short* Ol = Oh + BLM * MKP;
+  const int LT = (l + 15) / 16;
+  for (int e = t; e < BLM * MKP; e += BT)
+    if (e / MKP >= l) { Oh[e] = 0; Ol[e] = 0; }
+  const int ncb = (int)((n + MRB - 1) / MRB), nrb = (int)((m + MKC - 1) / MKC);
+  float xv[MXC], qv[MAC];
+  int64_t fr0 = 0, fc0 = 0;
+  // element e = t + s BT of an X chunk: row e / MRB, column e % MRB (along the row)
+  auto fetch = [&](int qq) {
+    fc0 = (int64_t)(qq / nrb) * MRB;
+    fr0 = (int64_t)(qq % nrb) * MKC;
+    int tt = t;
+    __asm__ volatile("" : "+v"(tt));
+#pragma unroll
+    for (int s = 0; s < MXC; ++s) {
+      const int e = tt + s * BT;
+      int64_t r = fr0 + e / MRB, c = fc0 + (e % MRB);
+      if (r >= m) r = m - 1;
+      if (c >= n) c = n - 1;
+      xv[s] = Xg[r * ldx + c];
+    }
+    op_fetch(qv, Qg, fr0, m, l, tt);
+  };
+  fetch(0);
+  fx4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = fx4{0.f, 0.f, 0.f, 0.f};
+  for (int qq = 0; qq < ncb * nrb; ++qq) {
+#pragma unroll
+    for (int s = 0; s < MXC; ++s) {
+      const int e = t + s * BT;
+      const int rr = e / MRB, cc = e % MRB;
+      const bool ok = fr0 + rr < m && fc0 + cc < n;
+      Xt[cc * MKP + rr] = ok ? bf16_rn(xv[s]) : (unsigned short)0;
+    }
+    op_store(qv, Oh, Ol, fr0, m, l);
+    const int64_t c0 = fc0;
+    lds_sync();
+    if (qq + 1 < ncb * nrb) fetch(qq + 1);
+#pragma unroll
+    for (int kk = 0; kk < MKC; kk += 32) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const bfx8 xa = *(const bfx8*)(Xt + (16 * (wave + 4 * rt) + i) * MKP + kk + 8 * g);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          if (ct < LT) {
+            const bfx8 h = *(const bfx8*)(Oh + (16 * ct + i) * MKP + kk + 8 * g);
+            const bfx8 lo = *(const bfx8*)(Ol + (16 * ct + i) * MKP + kk + 8 * g);
+            acc[rt][ct] = mfma_bf16(xa, h, acc[rt][ct]);
+            acc[rt][ct] = mfma_bf16(xa, lo, acc[rt][ct]);
+          }
+      }
+    }
+    lds_sync();
+    if (qq % nrb == nrb - 1) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t c = c0 + 16 * (wave + 4 * rt) + 4 * g + e;
+            const int j = 16 * ct + i;
+            if (ct < LT && c < n && j < l) {
+              Z[c * l + j] = acc[rt][ct][e];
+              if (Bout) Bout[(int64_t)j * n + c] = acc[rt][ct][e];
+            }
+          }
+          acc[rt][ct] = fx4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  __syncthreads();  // Z is read next by other threads of the workgroup
+}
+
 // Cholesky of the Gram in A (l x l, lower triangle and diagonal, in LDS,
 // pitch P1; the strict upper triangle zero) in place, with the inverse fused,
 // in blocks of 8 columns (the scheme of the single-problem factorisation).
@@ -1121,20 +1359,26 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
     const rnmf_problem& p = d.p;
     const int64_t m = p.m, n = p.n, ldx = p.ldx;
     const int k = p.k, l = p.l, tc = d.tc;
+    const bool bf = p.prec == RNMF_PREC_BF16;
+    const int qe = q + (bf ? 1 : 0);  // the BF16 form adds one subspace iteration
     unsigned st = 0;
     // range finder (Algorithm 1, steps 3-8)
-    xa_pass(p.X, ldx, m, n, p.Omega, l, p.Q, tc, scr);
+    if (bf) xa_pass_bf16(p.X, ldx, m, n, p.Omega, l, p.Q, scr);
+    else xa_pass(p.X, ldx, m, n, p.Omega, l, p.Q, tc, scr);
     st |= cholqr2(p.Q, m, l, tc, scr, &flag);
-    for (int it = 0; it < q && !(st & ST_NOT_SPD); ++it) {
-      xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, nullptr, tc, scr);
+    for (int it = 0; it < qe && !(st & ST_NOT_SPD); ++it) {
+      if (bf) xtq_pass_bf16(p.X, ldx, m, n, p.Q, l, p.Z, nullptr, scr);
+      else xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, nullptr, tc, scr);
       st |= cholqr2(p.Z, n, l, tc, scr, &flag);
       if (st & ST_NOT_SPD) break;
-      xa_pass(p.X, ldx, m, n, p.Z, l, p.Q, tc, scr);
+      if (bf) xa_pass_bf16(p.X, ldx, m, n, p.Z, l, p.Q, scr);
+      else xa_pass(p.X, ldx, m, n, p.Z, l, p.Q, tc, scr);
       st |= cholqr2(p.Q, m, l, tc, scr, &flag);
     }
     if (!(st & ST_NOT_SPD)) {
       // compression (step 9): B^T into Z for the sweeps, B for the caller
-      xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, p.B, tc, scr);
+      if (bf) xtq_pass_bf16(p.X, ldx, m, n, p.Q, l, p.Z, p.B, scr);
+      else xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, p.B, tc, scr);
       // initialisation (step 10)
       for (int e = t; e < OFF_VEC; e += BT) lds[e] = 0.f;  // W~, T, V, S zero beyond k
       copy_f(p.W, p.W0, m * k);

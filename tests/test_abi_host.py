@@ -203,12 +203,12 @@ def test_svd_init_validation():
 
 
 def test_batch_problem_layout_and_validation():
-    assert ctypes.sizeof(rn.Problem) == 104
+    assert ctypes.sizeof(rn.Problem) == 112
     L = rn.lib()
     assert L.rnmf_batch_workspace_bytes(512) > 512 * 104
     assert L.rnmf_batch_workspace_bytes(0) == 0
     good = dict(X=4096, Omega=4096, W0=4096, H0=4096, W=4096, H=4096, Q=4096, B=4096, Z=4096,
-                m=1000, n=500, ldx=500, k=10, l=20)
+                m=1000, n=500, ldx=500, k=10, l=20, prec=rn.PREC["fp32"])
 
     def plan(**kw):
         d = dict(good, **kw)
@@ -226,6 +226,8 @@ def test_batch_problem_layout_and_validation():
     assert plan(k=21) == rn.ERR_ARG
     assert plan(ldx=499) == rn.ERR_SHAPE
     assert plan(Z=0) == rn.ERR_ARG
+    assert plan(prec=0) == rn.ERR_ARG        # FP64 is not a batched precision
+    assert plan(prec=rn.PREC["bf16"], reserved=1) == rn.ERR_ARG
     assert L.rnmf_batch_run(4, 33, 10, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
     assert L.rnmf_batch_run(4, 2, -1, ctypes.c_void_p(256), 1 << 30, None) == rn.ERR_ARG
     assert L.rnmf_batch_run(4, 2, 10, ctypes.c_void_p(256), 16, None) == rn.ERR_WORKSPACE

@@ -159,6 +159,33 @@ def test_batch_autotune_picks_valid_tilings(small):
         assert abs(rel[i] - io["rel_err"]) <= 1e-4
 
 
+def test_batch_bf16_form_error_against_oracle(small):
+    # BF16 form: the X passes on bfloat16 matrix cores (X rounded to nearest
+    # even, the operand split into two bfloat16 terms, FP32 accumulation)
+    # with one more subspace iteration.  Per-step parity is unpinned for this
+    # form (X is rounded by up to 2^-9); the final error must stay within 1%
+    # of the oracle's at q + 1, the basis orthonormal and B close to Q^T X.
+    sweeps, q = 30, 2
+    b = rn.Batch([tuple(dev(a) for a in p) for p in small], precision="bf16")
+    b.run(q, sweeps)
+    rel, st = b.results()
+    assert all(x == rn.OK for x in st)
+    for i, (X, Om, W0, H0) in enumerate(small):
+        k = W0.shape[1]
+        X64 = X.astype(np.float64)
+        _, _, io = o.rhals(X64, k, Om.astype(np.float64), W0.astype(np.float64), H0.astype(np.float64),
+                           q=q + 1, max_iter=sweeps)
+        print(f"problem {i}: bf16 {rel[i]:.6f} oracle(q+1) {io['rel_err']:.6f}", flush=True)
+        assert rel[i] <= 1.01 * io["rel_err"], (i, rel[i], io["rel_err"])
+        P = b.problems[i]
+        Q, B = host(P["Q"]), host(P["B"])
+        assert np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])) <= 1e-5, i
+        # bfloat16 X: each product term is off by at most 2^-9 of |q_ij x_jc|
+        assert relf(B, Q.T @ X64) <= 4e-3, i
+        assert host(P["W"]).min() >= 0 and host(P["H"]).min() >= 0
+        assert abs(rel[i] - o.rel_error(X64, host(P["W"]), host(P["H"]))) <= 1e-6
+
+
 @pytest.mark.timeout(900)
 def test_batch_full_workload_sampled_against_oracle():
     # the 512-problem workload (m ~ U[256, 4096], n ~ U[128, 2048], k ~ U{4..32},
