@@ -340,14 +340,20 @@ __global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__
 // enter the CUs (X from HBM plus the small operand from L2) bound these
 // passes, so a workgroup of 8 waves owns a contiguous range of 16-row tiles
 // (about m / #CUs rows) and reads the small operand once per pass.  X and
-// operand fragments travel by direct global->LDS loads, one 1 KB wave
-// fragment per instruction, double-buffered by stage; the fragment a lane
-// loads is exactly the MFMA fragment it later reads back, so LDS reads are
-// conflict-free 16-byte reads.
+// operand rows travel by direct global->LDS loads, double-buffered by stage.
+// A stage covers one 128-byte line of every row (64 k in BF16, 32 in FP32):
+// a 16-row block arrives as two 1 KB loads of 8 whole lines each (a load of
+// 16 half lines streams markedly slower).  Lane L of such a load takes row
+// L / 8 and 16-byte chunk (L % 8) ^ (L / 8); the second half of a block sits
+// 16 bytes past a 1 KB boundary.  The MFMA fragment of lane (i, g) at k-step
+// u (chunk 4u + g of row i) is then read back from a bank-conflict-free
+// position.
 //   BF16: fragment = 16 rows x 32 k (8 per lane); two operand planes.
 //   FP32: fragment = 16 rows x 16 k (4 per lane: MFMA s uses k = 4g + s).
-// Stage = KU fragments along k.  Wave w owns tiles w, w + 8, ... of the range.
+// Wave w owns tiles w, w + 8, ... of the range.
 // ---------------------------------------------------------------------------
+constexpr int NN2_HALF = 1024 + 16;          // second half of a block
+constexpr int NN2_BLOCK = NN2_HALF + 1024;   // bytes of one 16-row block
 #define RNMF_GPTR(p) ((const __attribute__((address_space(1))) void*)(p))
 #define RNMF_LPTR(p) ((__attribute__((address_space(3))) void*)(p))
 
@@ -370,18 +376,24 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
   constexpr int KS = BF ? 32 : 16;       // k per fragment
   constexpr int EPC = BF ? 8 : 4;        // elements per lane chunk (16 bytes)
   constexpr int NPL = BF ? 2 : 1;        // operand planes
-  constexpr int AF = NPL * NT * KU;      // operand fragments per stage
+  static_assert(KU * KS * (int)sizeof(E) == 128, "a stage covers one 128-byte line of every row");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, gq = lane >> 4;
   const int gidx = blockIdx.x;
   const int t0 = (int)((int64_t)tiles * gidx / G), t1 = (int)((int64_t)tiles * (gidx + 1) / G);
   const int nt = t1 - t0;               // tiles of this workgroup, <= 8 * RWMAX
-  const int XF = nt * KU;               // X fragments per stage
-  const int F = XF + AF;
+  const int NB = nt + NPL * NT;         // 16-row blocks per stage (X tiles, then operand planes)
   const int64_t kb = (int64_t)blockIdx.y * klen;
   const int64_t ke = (kb + klen < n) ? kb + klen : n;
   const int nst = (int)((ke - kb + KS * KU - 1) / (KS * KU));
   const int64_t plane = (int64_t)lp_all * ldat;
+  // swizzled placement: lane L of a half-block load takes row L / 8 and the
+  // 16-byte chunk (L % 8) ^ (L / 8) of that row's 128 bytes
+  const int srow = lane >> 3, schunk = (lane & 7) ^ srow;
+  // the lane's MFMA fragment of k-step u inside a block (see the header)
+  auto frag_ofs = [&](int u) -> int {
+    return (i >> 3) * NN2_HALF + (8 * (i & 7) + ((4 * u + gq) ^ (i & 7))) * 16;
+  };
   floatx4 acc[RWMAX][NT];
 #pragma unroll
   for (int a = 0; a < RWMAX; ++a)
@@ -390,38 +402,38 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
 
   auto issue = [&](int st) {
     const int64_t k = kb + (int64_t)st * KS * KU;
-    unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
-    for (int f = wave; f < F; f += 8) {
+    unsigned char* base = nn2_lds + (size_t)(st & 1) * NB * NN2_BLOCK;
+    for (int f = wave; f < 2 * NB; f += 8) {
+      const int b = f >> 1, j = f & 1;
       const E* src;
-      if (f < XF) {
-        const int tau = f / KU, u = f - (f / KU) * KU;
-        int64_t r = (int64_t)(t0 + tau) * 16 + i;
+      if (b < nt) {
+        int64_t r = (int64_t)(t0 + b) * 16 + 8 * j + srow;
         if (r >= m) r = m - 1;
-        int64_t c = k + u * KS + gq * EPC;
+        int64_t c = k + schunk * EPC;
         if (c >= ke || c + EPC > n) c = 0;  // in-bounds address; fixed up after arrival
         src = X + r * ldx + c;
       } else {
-        const int a = f - XF;
-        const int pl = a / (NT * KU), rem = a - pl * (NT * KU);
-        const int ct = rem / KU, u = rem - (rem / KU) * KU;
-        src = At + pl * plane + (int64_t)(ct * 16 + i) * ldat + k + u * KS + gq * EPC;
+        const int a = b - nt;
+        const int pl = a / NT, ct = a - (a / NT) * NT;
+        src = At + pl * plane + (int64_t)(ct * 16 + 8 * j + srow) * ldat + k + schunk * EPC;
       }
-      __builtin_amdgcn_global_load_lds(RNMF_GPTR(src), RNMF_LPTR(base + (size_t)f * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(RNMF_GPTR(src), RNMF_LPTR(base + (size_t)b * NN2_BLOCK + j * NN2_HALF), 16,
+                                       0, 0);
     }
   };
   // tail stage: in this lane's own chunks, zero the elements at or beyond ke
   // and load element by element a chunk that runs past the end of the row
   auto patch = [&](int st) {
     const int64_t k = kb + (int64_t)st * KS * KU;
-    unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
-    for (int f = wave; f < XF; f += 8) {
-      const int tau = f / KU, u = f - (f / KU) * KU;
-      const int64_t c = k + u * KS + gq * EPC;
+    unsigned char* base = nn2_lds + (size_t)(st & 1) * NB * NN2_BLOCK;
+    for (int f = wave; f < 2 * nt; f += 8) {
+      const int b = f >> 1, j = f & 1;
+      const int64_t c = k + schunk * EPC;
       if (c + EPC > ke) {
-        int64_t r = (int64_t)(t0 + tau) * 16 + i;
+        int64_t r = (int64_t)(t0 + b) * 16 + 8 * j + srow;
         if (r >= m) r = m - 1;
         const bool reload = c < ke && c + EPC > n;
-        E* dst = (E*)(base + (size_t)f * 1024 + lane * 16);
+        E* dst = (E*)(base + (size_t)b * NN2_BLOCK + j * NN2_HALF + lane * 16);
 #pragma unroll
         for (int e = 0; e < EPC; ++e)
           if (c + e >= ke) dst[e] = (E)0;
@@ -438,21 +450,22 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
     if (k + KS * KU > ke) patch(st);
     lds_barrier();
     if (st + 1 < nst) issue(st + 1);
-    const unsigned char* base = nn2_lds + (size_t)(st & 1) * F * 1024;
+    const unsigned char* base = nn2_lds + (size_t)(st & 1) * NB * NN2_BLOCK;
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       if (k + u * KS >= ke) break;
+      const int fo = frag_ofs(u);
       if constexpr (BF) {
         bf16x8 xa[RWMAX];
 #pragma unroll
         for (int rt = 0; rt < RWMAX; ++rt) {
           const int tau = wave + 8 * rt;
-          if (tau < nt) xa[rt] = *(const bf16x8*)(base + (size_t)(tau * KU + u) * 1024 + lane * 16);
+          if (tau < nt) xa[rt] = *(const bf16x8*)(base + (size_t)tau * NN2_BLOCK + fo);
         }
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
-          const bf16x8 h = *(const bf16x8*)(base + (size_t)(XF + ct * KU + u) * 1024 + lane * 16);
-          const bf16x8 lo = *(const bf16x8*)(base + (size_t)(XF + (NT + ct) * KU + u) * 1024 + lane * 16);
+          const bf16x8 h = *(const bf16x8*)(base + (size_t)(nt + ct) * NN2_BLOCK + fo);
+          const bf16x8 lo = *(const bf16x8*)(base + (size_t)(nt + NT + ct) * NN2_BLOCK + fo);
 #pragma unroll
           for (int rt = 0; rt < RWMAX; ++rt)
             if (wave + 8 * rt < nt) {
@@ -466,7 +479,7 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
         for (int rt = 0; rt < RWMAX; ++rt) {
           const int tau = wave + 8 * rt;
           if (tau < nt) {
-            xa[rt] = *(const floatx4*)(base + (size_t)(tau * KU + u) * 1024 + lane * 16);
+            xa[rt] = *(const floatx4*)(base + (size_t)tau * NN2_BLOCK + fo);
             if (check)
 #pragma unroll
               for (int e = 0; e < 4; ++e) flag |= scan_f32(xa[rt][e]);
@@ -474,7 +487,7 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
         }
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
-          const floatx4 av = *(const floatx4*)(base + (size_t)(XF + ct * KU + u) * 1024 + lane * 16);
+          const floatx4 av = *(const floatx4*)(base + (size_t)(nt + ct) * NN2_BLOCK + fo);
 #pragma unroll
           for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -1066,8 +1079,8 @@ static void plan_nn2(XPlan& p, int64_t m, int64_t n, int l, int cdt, int cus) {
   if (!(cdt == 1 || cdt == 2) || nt > 8 || m < 16) return;
   const int lp = nt * 16;
   const int ks = (cdt == 2) ? 32 : 16, stage = ks * NN2_KU;
-  const int af = (cdt == 2 ? 2 : 1) * nt * NN2_KU;
-  int ntmax = (NN2_LDS_KB / 2 - af) / NN2_KU;
+  const int af = (cdt == 2 ? 2 : 1) * nt;  // operand blocks per stage
+  int ntmax = NN2_LDS_KB * 1024 / 2 / NN2_BLOCK - af;
   if (ntmax > 8 * NN2_RWMAX) ntmax = 8 * NN2_RWMAX;
   if (ntmax < 1) return;
   const int64_t tiles = ceil_div(m, 16);
@@ -1094,7 +1107,7 @@ static void plan_nn2(XPlan& p, int64_t m, int64_t n, int l, int cdt, int cus) {
       p.g2 = (int)g;
       p.s2 = se;
       p.klen2 = klen;
-      p.lds2 = (size_t)2 * ((size_t)ceil_div(tiles, g) * NN2_KU + af) * 1024;
+      p.lds2 = (size_t)2 * ((size_t)ceil_div(tiles, g) + af) * NN2_BLOCK;
     }
   }
 }
