@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the reverse pass through unrolled sweeps")
     ap.add_argument("--no-stack", action="store_true", help="skip the 32,256 x 2,410 image-stack workload")
     ap.add_argument("--no-orders", action="store_true", help="skip the update-order timings")
+    ap.add_argument("--no-speedup", action="store_true", help="skip the HALS/rHALS speedup study over k")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -209,8 +210,11 @@ def main():
         hals = hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev=dev)
         log(f"HALS: {hals['ms_per_sweep']:.3f} ms/sweep, rHALS {hals['rhals_ms_per_sweep']:.3f} ms/sweep, "
             f"speedup {hals['speedup_per_sweep']:.2f}x per sweep, {hals['speedup_200_sweeps']:.2f}x per run")
-        if args.speedup_ks:
-            hals["by_k"] = speedup_series(rn, torch, X, [int(v) for v in args.speedup_ks.split(",") if v], p, q)
+    # ---- speedup of rHALS over HALS for several k, both shapes of Sec. 4.4 --
+    study = None
+    if not args.no_speedup:
+        ks = [int(v) for v in args.speedup_ks.split(",") if v] or [10, 20, 30, 40, 50, 64]
+        study = speedup_study(rn, torch, synth, X, p, q, ks, dev)
 
     # ---- SVD-based initialization against the seeded uniform one -------------
     svd = None
@@ -225,7 +229,9 @@ def main():
         batch = batch_bench(rn, torch, synth, dev)
         log(f"batch: {batch['problems']} problems in {batch['ms_per_run']:.2f} ms per run "
             f"({batch['problems_per_s']:.0f} problems/s, {batch['x_GBps']:.0f} GB/s of X); one at a time "
-            f"~{batch['one_at_a_time_ms_estimate']:.0f} ms ({batch['speedup_vs_one_at_a_time']:.1f}x)")
+            f"~{batch['one_at_a_time_ms_estimate']:.0f} ms ({batch['speedup_vs_one_at_a_time']:.1f}x); "
+            f"bf16 {batch['bf16']['ms_per_run']:.2f} ms per run, error ratio to fp32 up to "
+            f"{batch['bf16']['max_ratio_to_fp32']:.4f}")
 
     # ---- reverse pass through 20 unrolled FP32 sweeps (two workloads) ---------
     back = None
@@ -281,6 +287,7 @@ def main():
         "sweeps_per_s_kernel": round(sweeps / (ms_sw * 1e-3), 1),
         "time_to_target": ttt,
         "hals_vs_rhals": hals,
+        "speedup_study": study,
         "svd_init": svd,
         "batched": batch,
         "backward": back,
@@ -595,6 +602,21 @@ def batch_bench(rn, torch, synth, dev, reps=3):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     rel, status = b.results()
+    del g
+    # the BF16 form (C4: FP32 storage, X passes on bfloat16 matrix cores, one
+    # more subspace iteration), the same problems and sweeps
+    bb = rn.Batch(probs, q=w["q"], precision="bf16")
+    gb = bb.capture(w["q"], w["sweeps"])
+    gb.replay()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        gb.replay()
+    e1.record(st)
+    e1.synchronize()
+    ms_bf = e0.elapsed_time(e1) / reps
+    rel_bf, status_bf = bb.results()
+    del gb, bb
     # the same problems one at a time through the single-problem path
     # (rnmf_factorize per problem), on a seeded sample, scaled to the batch
     pick = synth.stream(w["seed"], 98).choice(len(shapes), size=24, replace=False)
@@ -621,18 +643,29 @@ def batch_bench(rn, torch, synth, dev, reps=3):
            "speedup_vs_one_at_a_time": round(loop_ms / ms, 2),
            "rel_err_mean": float(np.mean(rel)), "rel_err_max": float(np.max(rel)),
            "arithmetic": "fp32 (FP64 Grams, Cholesky and error sums)",
+           "bf16": {"ms_per_run": round(ms_bf, 3), "problems_per_s": round(len(shapes) / (ms_bf * 1e-3), 1),
+                    "q": w["q"] + 1, "all_ok": all(x == 0 for x in status_bf),
+                    "rel_err_mean": float(np.mean(rel_bf)), "rel_err_max": float(np.max(rel_bf)),
+                    "max_ratio_to_fp32": float(np.max(np.asarray(rel_bf) / np.asarray(rel))),
+                    "arithmetic": "X passes bf16 MFMA (X rounded, operand split hi+lo), fp32 accumulate"},
            "note": "one persistent launch per run, captured in a HIP graph; per-problem range finder, "
                    "compression, sweeps and error run inside one workgroup"}
-    del b, probs, g
+    del b, probs
     torch.cuda.empty_cache()
     return out
 
 
-def speedup_series(rn, torch, X, ks, p, q, nsw=20):
-    """Per-sweep time of HALS and rHALS for several ranks k (FP32, seeded init)."""
+def speedup_series(rn, torch, X, ks, p, q, nsw=20, sweeps=200):
+    """HALS against randomized HALS for several ranks k on one X (FP32,
+    seeded uniform starts; Sec. 4.4, the figure on varying k): per-sweep time
+    of each (events over an nsw-sweep launch) and the end-to-end time of
+    `sweeps` sweeps (HALS: sweeps x its per-sweep time; rHALS: one
+    rnmf_factorize run of `sweeps` sweeps, range finder, compression and
+    final error included)."""
     out = []
     m, n = X.shape
     dev = X.device
+    st = torch.cuda.current_stream(dev)
     for k in ks:
         g = torch.Generator(device="cpu").manual_seed(1000 + k)
         W0 = torch.rand((m, k), generator=g).to(dev)
@@ -640,18 +673,40 @@ def speedup_series(rn, torch, X, ks, p, q, nsw=20):
         W, H = W0.clone(), H0.clone()
         hws = rn._workspace(rn.workspace_bytes(rn.OP_HALS, m, n, rn.make_opts(k, 0, 0)), dev)
         rn.hals(X, W, H, nsweeps=1, ws=hws)
-        st = torch.cuda.current_stream(dev)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         rn.hals(X, W, H, nsweeps=nsw, ws=hws)
         e1.record(st)
         e1.synchronize()
         h_ms = e0.elapsed_time(e1) / nsw
-        _, _, info = rn.factorize(X, k, p, q, max_iter=nsw, precision="fp32", W0=W0, H0=H0)
-        r_ms = info["ms_sweeps"] / nsw
-        out.append({"k": k, "hals_ms_per_sweep": round(h_ms, 4), "rhals_ms_per_sweep": round(r_ms, 4),
-                    "speedup_per_sweep": round(h_ms / r_ms, 3)})
-        log(f"k={k}: HALS {h_ms:.3f} ms/sweep, rHALS {r_ms:.3f} ms/sweep, {h_ms / r_ms:.2f}x")
+        del hws
+        rn.factorize(X, k, p, q, max_iter=nsw, precision="fp32", W0=W0, H0=H0)  # warm-up
+        _, _, info = rn.factorize(X, k, p, q, max_iter=sweeps, precision="fp32", W0=W0, H0=H0)
+        r_ms = info["ms_sweeps"] / sweeps
+        r_run = info["ms_qb"] + info["ms_sweeps"] + info["ms_error"]
+        out.append({"k": k, "l": info["l"], "hals_ms_per_sweep": round(h_ms, 4), "rhals_ms_per_sweep": round(r_ms, 4),
+                    "rhals_ms_qb": round(info["ms_qb"], 3), "speedup_per_sweep": round(h_ms / r_ms, 3),
+                    "hals_ms_run": round(h_ms * sweeps, 2), "rhals_ms_run": round(r_run, 2),
+                    "speedup_run": round(h_ms * sweeps / r_run, 3), "rhals_rel_err": info["rel_err"]})
+        log(f"{m}x{n} k={k}: HALS {h_ms:.3f} ms/sweep, rHALS {r_ms:.3f} ms/sweep ({h_ms / r_ms:.2f}x), "
+            f"{sweeps}-sweep runs {h_ms * sweeps:.1f} vs {r_run:.1f} ms ({h_ms * sweeps / r_run:.2f}x)")
+        torch.cuda.empty_cache()
+    return out
+
+
+def speedup_study(rn, torch, synth, X, p, q, ks, dev):
+    """The speedup study of Sec. 4.4 on both of its matrix shapes: the
+    benchmark's 100,000 x 5,000 X and a 25,000 x 25,000 rank-50 product."""
+    out = {"ks": ks, "sweeps": 200, "precision": "fp32",
+           "tall_100000x5000": speedup_series(rn, torch, X, ks, p, q)}
+    Xs, _, _, _, _ = synth.make("square_25000x25000", threads=min(16, os.cpu_count() or 1))
+    Xd = torch.from_numpy(Xs).to(dev)
+    del Xs
+    out["square_25000x25000"] = speedup_series(rn, torch, Xd, ks, p, q)
+    del Xd
+    torch.cuda.empty_cache()
+    out["note"] = ("per sweep: HALS streams X twice, rHALS sweeps on B; run: HALS sweeps x its per-sweep time "
+                   "against one rnmf_factorize of the same sweeps (range finder and error included)")
     return out
 
 

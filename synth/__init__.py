@@ -42,6 +42,11 @@ WORKLOADS = {
     "tall_100000x5000": dict(m=100000, n=5000, rank=50, k=50, p=20, q=2,
                              sweeps=200, noise_abs=0.05, noise_rel=0.0,
                              density=1.0, seed=103, dtype="f32"),
+    # square synthetic matrix of the performance study (Sec. 4.4):
+    # 25,000 x 25,000, rank-50 uniform product, absolute noise 0.05
+    "square_25000x25000": dict(m=25000, n=25000, rank=50, k=50, p=20, q=2,
+                               sweeps=200, noise_abs=0.05, noise_rel=0.0,
+                               density=1.0, seed=106, dtype="f32"),
     # differentiation workload: 8,192 x 2,048, rank-32 uniform product, 1%
     # relative noise; T = 20 unrolled sweeps ("sweeps"), checkpoints every 5
     "diff_8192x2048": dict(m=8192, n=2048, rank=32, k=32, p=16, q=2, sweeps=20,
