@@ -333,15 +333,21 @@ rnmf_status qr_pass(const void* in, int64_t rows, int l, void* out, const QrBufs
 }
 
 // Thin QR by Cholesky QR2 (plus a third pass when the first needed a shift).
-// `in` is overwritten.  Result in `out`.
+// `in` is overwritten.  Result in `out`.  With passes = 1 (the iterates inside
+// the subspace iteration, whose span is all the next product uses) one pass,
+// plus a second only when the first needed a shift: a Cholesky QR pass
+// spans exactly the span of its input, and the final basis still gets two.
 rnmf_status cholqr(void* in, int64_t rows, int l, void* out, void* tmp, const QrBufs& qb, const Mode& md,
-                   unsigned* ctl, int allow_shift, unsigned* status, const Dev& d) {
+                   unsigned* ctl, int allow_shift, unsigned* status, const Dev& d, int passes = 2) {
   HIPCHK(launch_fill_u32(ctl, 1, 0u, d.stream));
   rnmf_status r;
-  (void)in;
   // allow_shift: 0 never shift, 1 shift a pass whose Gram is not numerically
   // positive definite, 2 also shift the first pass unconditionally
   const int later = allow_shift ? 1 : 0;
+  if (passes == 1) {
+    if ((r = qr_pass(in, rows, l, out, qb, md, 0, ctl, allow_shift, status, d, nullptr)) != RNMF_OK) return r;
+    return qr_pass(out, rows, l, out, qb, md, 1, ctl, later, status, d, ctl);
+  }
   if ((r = qr_pass(in, rows, l, tmp, qb, md, 0, ctl, allow_shift, status, d, nullptr)) != RNMF_OK) return r;
   if ((r = qr_pass(tmp, rows, l, out, qb, md, 0, ctl, later, status, d, nullptr)) != RNMF_OK) return r;
   // third pass, in place, only after a shifted pass (decided on the device)
@@ -366,10 +372,10 @@ rnmf_status run_sketch(const void* Xc, int64_t m, int64_t n, int64_t ldx, const 
   const int q = q_effective(o);
   for (int it = 0; it < q; ++it) {
     // Q = qr(Y); Z = X^T Q; Q = qr(Z); Y = X Q
-    if ((r = cholqr(b.y, m, l, b.y2, Q, b.qy, md, h.ctl, allow_shift, h.status, d)) != RNMF_OK) return r;
+    if ((r = cholqr(b.y, m, l, b.y2, Q, b.qy, md, h.ctl, allow_shift, h.status, d, 1)) != RNMF_OK) return r;
     HIPCHK(launch_pack_t(b.y2, md.dt, m, l, lp, b.ldp, b.at, md.cdt, s));
     HIPCHK(launch_tn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.z, 0, b.part, b.tn, s));
-    if ((r = cholqr(b.z, n, l, b.z2, b.z3, b.qz, md, h.ctl, allow_shift, h.status, d)) != RNMF_OK) return r;
+    if ((r = cholqr(b.z, n, l, b.z2, b.z3, b.qz, md, h.ctl, allow_shift, h.status, d, 1)) != RNMF_OK) return r;
     HIPCHK(launch_pack_t(b.z2, md.dt, n, l, lp, b.ldp, b.at, md.cdt, s));
     HIPCHK(launch_nn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.y, b.part, b.nn, h.status, 0, s));
   }

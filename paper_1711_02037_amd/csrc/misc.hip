@@ -139,32 +139,47 @@ __device__ __forceinline__ void or_status(unsigned* status, unsigned f) {
   }
 }
 
-__global__ void cast_bf16_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
-                                 bf16_t* __restrict__ Xb, int64_t ldb, unsigned* status, int check) {
-  // one row-chunk of 4 elements per thread; pad columns [n, ldb) are zeroed
-  const int64_t qpr = (ldb + 3) / 4;  // quads per row of the destination
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// A workgroup takes whole rows (no index division per element).  Rows whose
+// source and destination are 16-byte aligned move 8 elements per thread and
+// step (two 16-byte loads, one 16-byte store, two steps in flight); the rest
+// of a row, and unaligned rows, element by element.  Pad columns [n, ldb) are
+// zeroed.
+__global__ __launch_bounds__(256) void cast_bf16_kernel(const float* __restrict__ X, int64_t m, int64_t n,
+                                                        int64_t ldx, bf16_t* __restrict__ Xb, int64_t ldb,
+                                                        unsigned* status, int check, int vec) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
   unsigned flag = 0;
-  for (; i < m * qpr; i += stride) {
-    int64_t r = i / qpr, c0 = (i - r * qpr) * 4;
+  const int64_t n8 = vec ? n / 8 : 0;
+  const int t = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
     const float* src = X + r * ldx;
-    bf16_t o[4];
+    bf16_t* dst = Xb + r * ldb;
+    auto conv8 = [&](const f32x4 a, const f32x4 b) -> u32x4 {
+      float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      unsigned h[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int64_t c = c0 + e;
-      float v = c < n ? src[c] : 0.0f;
-      if (check) flag |= scan_bits(v);
-      o[e] = f32_to_bf16_rne(v);
+      for (int e = 0; e < 8; ++e) {
+        if (check) flag |= scan_bits(v[e]);
+        h[e] = f32_to_bf16_rne(v[e]);
+      }
+      return u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+    };
+    int64_t g = t;
+    for (; g + 256 < n8; g += 512) {
+      const f32x4 a0 = ((const f32x4*)src)[2 * g], b0 = ((const f32x4*)src)[2 * g + 1];
+      const f32x4 a1 = ((const f32x4*)src)[2 * (g + 256)], b1 = ((const f32x4*)src)[2 * (g + 256) + 1];
+      ((u32x4*)dst)[g] = conv8(a0, b0);
+      ((u32x4*)dst)[g + 256] = conv8(a1, b1);
     }
-    bf16_t* dst = Xb + r * ldb + c0;
-    if (c0 + 4 <= ldb && ((uintptr_t)dst & 7u) == 0) {
-      uint2 w;
-      w.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
-      w.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
-      *(uint2*)dst = w;
-    } else {
-      for (int e = 0; e < 4 && c0 + e < ldb; ++e) dst[e] = o[e];
+    for (; g < n8; g += 256) {
+      const f32x4 a0 = ((const f32x4*)src)[2 * g], b0 = ((const f32x4*)src)[2 * g + 1];
+      ((u32x4*)dst)[g] = conv8(a0, b0);
+    }
+    for (int64_t c = 8 * n8 + t; c < ldb; c += 256) {
+      const float v = c < n ? src[c] : 0.0f;
+      if (check) flag |= scan_bits(v);
+      dst[c] = f32_to_bf16_rne(v);
     }
   }
   if (check) or_status(status, flag);
@@ -172,12 +187,11 @@ __global__ void cast_bf16_kernel(const float* __restrict__ X, int64_t m, int64_t
 
 hipError_t launch_cast_bf16(const float* X, int64_t m, int64_t n, int64_t ldx, bf16_t* Xb,
                             int64_t ldb, unsigned* status, int check, hipStream_t s) {
-  int64_t work = m * ((ldb + 3) / 4);
-  if (work == 0) return hipSuccess;
-  int64_t blocks = (work + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
+  if (m <= 0 || ldb <= 0) return hipSuccess;
+  const int vec = (ldx % 4 == 0 && ((uintptr_t)X % 16) == 0 && ldb % 8 == 0 && ((uintptr_t)Xb % 16) == 0) ? 1 : 0;
+  const int64_t blocks = m < 8192 ? m : 8192;
   hipLaunchKernelGGL(cast_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, m, n, ldx, Xb,
-                     ldb, status, check);
+                     ldb, status, check, vec);
   return hipGetLastError();
 }
 
