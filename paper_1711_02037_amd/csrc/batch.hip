@@ -1169,106 +1169,129 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
 }
 
 // Columns of W (Algorithm 1): update vector in the compressed space, lift and
-// clip on all rows (Q streamed in RQ-row tiles; the next tile's loads are in
-// flight while the current one is used), map back with FP64 sums.  A tile is
-// fetched with one lane per column of Q (2^LG >= l lanes per row, BT >> LG
-// rows per pass) and held in LDS at pitch 2^LG + 1: 256 rows when l <= 32,
-// 128 otherwise, so that every thread lifts at most one row and maps back 32.
-// Lanes past column l and rows past m load a valid element of Q (column
-// l - 1, row m - 1) into LDS slots that the lift and the map-back never read
-// with a nonzero weight, so the loads need no selects and all of a tile's
-// loads are in flight together.
-template <int LG>
+// clip on all rows, map back.  Each wavefront owns a contiguous quarter of
+// the rows and walks it in chunks of 32 rows with no workgroup barrier.  A
+// chunk of Q (32 l contiguous floats) arrives by coalesced 256-byte loads,
+// one chunk ahead, and is laid out in the wavefront's own LDS tile at an odd
+// pitch; lane i of half h then reads row i over the columns of half h, lifts
+// it (the halves' partial dot products are exchanged by a lane swap), clips,
+// stores W(row, j) and accumulates Q(row, c) w(row) for its columns in
+// registers.  Per column the 32 rows of a half are summed by lane
+// butterflies, then the four wavefronts in FP64 through LDS, in a fixed
+// order.  Reads past the chunk return zero (buffer loads) or land in the
+// tile's slack and are weighted by zero.
+template <int NL>  // coalesced loads per lane per chunk: NL >= ceil(32 l / 64)
 __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k,
-                                       float* Wts, const float* Ts, const float* Vs, float* vec, float* ws,
-                                       double* red, float* scr) {
-  constexpr int C = 1 << LG;             // lanes per row of the tile
-  constexpr int PQ = C + 1;              // LDS pitch
-  constexpr int RQ = LG == 5 ? 256 : 128;  // rows per tile
-  constexpr int RP = BT >> LG;           // rows per pass, and map-back groups
-  constexpr int CNT = RQ / RP;           // loads per thread per tile
-  static_assert(CNT * RP == RQ && RQ <= RQW && RQ * PQ <= SCR_FLOATS && RP * BLM <= 2 * BT, "tile shape");
-  const int t = threadIdx.x;
-  float* Qs = scr;  // RQ x PQ
-  const int c = t & (C - 1), i0 = t >> LG;  // fetch lane; map-back column c, group i0
-  const int cq = c < l ? c : l - 1;
-  float* qst = Qs + i0 * PQ + c;
-  const int ntile = (int)((m + RQ - 1) / RQ);
-  gcf* Qg = G(Q);
-  auto fetch = [&](float(&v)[CNT], int64_t r0) {
-    const int64_t left = m - 1 - r0;
-    const int lim = left < RQ - 1 ? (int)left : RQ - 1;  // last row of the tile
-    gcf* base = Qg + r0 * l;                              // the same for every lane
+                                       float* Wts, const float* Ts, const float* Vs, float* vec, double* red,
+                                       float* scr) {
+  constexpr int CR = 32;             // rows per chunk
+  constexpr int NH = BLM / 2;        // columns of a half, at most
+  constexpr int WT = CR * (BLM + 1) + BLM;  // LDS floats per wavefront tile
+  static_assert(4 * WT <= SCR_FLOATS, "four wavefront tiles fit the scratch");
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int h = lane >> 5, i = lane & 31;
+  const int L2 = (l + 1) / 2;
+  const int c0 = h ? L2 : 0, nh = h ? l - L2 : L2;
+  const int P = l | 1;               // odd pitch: rows of a half on distinct banks
+  float* Qw = scr + wave * WT;
+  const int64_t rw0 = m * wave / 4, rw1 = m * (wave + 1) / 4;
+  const int nch = (int)((rw1 - rw0 + CR - 1) / CR);
+  gf* Wg = GW(W);
+  // Q through a buffer resource (m l floats): a position past the end reads 0.
+  // (The arguments of a non-inlined function arrive in vector registers: the
+  // base and size are made wavefront-uniform so the resource sits in scalars.)
+  const uint64_t qa = (uint64_t)(uintptr_t)Q;
+  const unsigned qlo = __builtin_amdgcn_readfirstlane((unsigned)qa);
+  const unsigned qhi = __builtin_amdgcn_readfirstlane((unsigned)(qa >> 32));
+  const int qbytes = __builtin_amdgcn_readfirstlane((int)(m * l * (int64_t)sizeof(float)));
+  const __amdgpu_buffer_rsrc_t qrs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(uintptr_t)(((uint64_t)qhi << 32) | qlo), (short)0, qbytes, 0x00020000);
+  // LDS position of this lane's element e = lane + 64 s of a chunk (row e / l,
+  // column e % l), the same for every chunk; elements past the chunk go to
+  // the tile's slack
+  int pos[NL];
 #pragma unroll
-    for (int s = 0; s < CNT; ++s) {
-      const int i = i0 + s * RP;
-      v[s] = base[(unsigned)((i < lim ? i : lim) * l + cq)];
-    }
+  for (int s2 = 0; s2 < NL; ++s2) {
+    const int e = lane + 64 * s2;
+    pos[s2] = e < CR * l ? (e / l) * P + (e - (e / l) * l) : CR * P + lane;
+  }
+  // rows past the wave's range: the chunk is read from the wave's own rows
+  // only up to rw1 (the rest reads Q's next rows or zeros) and weighted 0
+  auto fetch = [&](float (&v)[NL], int ch) __attribute__((always_inline)) {
+    const int vo = (int)(((rw0 + (int64_t)ch * CR) * l + lane) * (int64_t)sizeof(float));
+#pragma unroll
+    for (int s2 = 0; s2 < NL; ++s2)
+      v[s2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(qrs, vo, 256 * s2, 0));
   };
   for (int j = 0; j < k; ++j) {
     const float d = Vs[j * BKM + j];
-    if (!(d > 0.f)) continue;
-    if (t < BLM) {
-      float v = 0.f;
-      if (t < l) {
-        float s0 = Ts[t * BKM + j], s1 = 0.f;
-        int i = 0;
-        for (; i + 2 <= k; i += 2) {
-          s0 = fmaf(-Wts[t * BKM + i], Vs[i * BKM + j], s0);
-          s1 = fmaf(-Wts[t * BKM + i + 1], Vs[(i + 1) * BKM + j], s1);
-        }
-        for (; i < k; ++i) s0 = fmaf(-Wts[t * BKM + i], Vs[i * BKM + j], s0);
-        v = Wts[t * BKM + j] + (s0 + s1) / d;
-      }
-      vec[t] = v;
-    }
-    float qv[CNT];
-    fetch(qv, 0);
-    double macc = 0.0;
-    for (int ti = 0; ti < ntile; ++ti) {
-      const int64_t r0 = (int64_t)ti * RQ;
-#pragma unroll
-      for (int s = 0; s < CNT; ++s) qst[s * RP * PQ] = qv[s];
-      lds_sync();  // Qs (and, the first time, vec) visible
-      if (ti + 1 < ntile) fetch(qv, r0 + RQ);
-      if (t < RQ) {
-        float u0 = 0.f, u1 = 0.f;
-        int cc = 0;
-        for (; cc + 2 <= l; cc += 2) {
-          u0 = fmaf(Qs[t * PQ + cc], vec[cc], u0);
-          u1 = fmaf(Qs[t * PQ + cc + 1], vec[cc + 1], u1);
-        }
-        for (; cc < l; ++cc) u0 = fmaf(Qs[t * PQ + cc], vec[cc], u0);
-        const float w = (r0 + t < m) ? clipf(u0 + u1) : 0.f;
-        ws[t] = w;
-        if (r0 + t < m) GW(W)[(r0 + t) * k + j] = w;
-      }
-      lds_sync();
-      if (c < l) {
-        float p = 0.f;
-        for (int rr = i0; rr < RQ; rr += RP) p = fmaf(Qs[rr * PQ + c], ws[rr], p);
-        macc += (double)p;
-      }
-      lds_sync();  // Qs and ws are overwritten next
-    }
-    red[i0 * BLM + c] = macc;
-    lds_sync();
+    if (!(d > 0.f)) continue;  // uniform: V is shared by the workgroup
     if (t < l) {
-      double v = (red[t] + red[BLM + t]) + (red[2 * BLM + t] + red[3 * BLM + t]);
-      if (RP == 8)
-        v += (red[4 * BLM + t] + red[5 * BLM + t]) + (red[6 * BLM + t] + red[7 * BLM + t]);
-      Wts[t * BKM + j] = (float)v;
+      float s0 = Ts[t * BKM + j], s1 = 0.f;
+      int ii = 0;
+      for (; ii + 2 <= k; ii += 2) {
+        s0 = fmaf(-Wts[t * BKM + ii], Vs[ii * BKM + j], s0);
+        s1 = fmaf(-Wts[t * BKM + ii + 1], Vs[(ii + 1) * BKM + j], s1);
+      }
+      for (; ii < k; ++ii) s0 = fmaf(-Wts[t * BKM + ii], Vs[ii * BKM + j], s0);
+      vec[t] = Wts[t * BKM + j] + (s0 + s1) / d;
     }
+    lds_sync();
+    float vv[NH], acc[NH];
+#pragma unroll
+    for (int c = 0; c < NH; ++c) {
+      vv[c] = c < nh ? vec[c0 + c] : 0.f;
+      acc[c] = 0.f;
+    }
+    float qn[NL];
+    if (nch > 0) fetch(qn, 0);
+    for (int ch = 0; ch < nch; ++ch) {
+      // lay the chunk out in the tile (the previous chunk's reads are done:
+      // LDS operations of a wavefront complete in order)
+#pragma unroll
+      for (int s2 = 0; s2 < NL; ++s2) Qw[pos[s2]] = qn[s2];
+      if (ch + 1 < nch) fetch(qn, ch + 1);
+      float q[NH];
+#pragma unroll
+      for (int c = 0; c < NH; ++c) q[c] = Qw[i * P + c0 + c];
+      float u0 = 0.f, u1 = 0.f;
+#pragma unroll
+      for (int c = 0; c < NH; c += 2) {
+        u0 = fmaf(q[c], vv[c], u0);
+        u1 = fmaf(q[c + 1], vv[c + 1], u1);
+      }
+      const float part = u0 + u1;
+      const float other = __shfl_xor(part, 32);
+      const int64_t r = rw0 + (int64_t)ch * CR + i;
+      // the same sum on both halves: half 0's part first
+      const float tot = h ? other + part : part + other;
+      const float w = r < rw1 ? clipf(tot) : 0.f;
+      if (h == 0 && r < rw1) Wg[r * k + j] = w;
+#pragma unroll
+      for (int c = 0; c < NH; ++c) acc[c] = fmaf(q[c], w, acc[c]);
+    }
+    // sums over the 32 rows of each half (every lane of the half gets them)
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+#pragma unroll
+      for (int c = 0; c < NH; ++c) acc[c] += __shfl_xor(acc[c], o);
+    }
+    float mine = 0.f;
+#pragma unroll
+    for (int c = 0; c < NH; ++c) mine = (c == i) ? acc[c] : mine;
+    if (i < nh) red[wave * BLM + c0 + i] = (double)mine;
+    lds_sync();
+    if (t < l) Wts[t * BKM + j] = (float)((red[t] + red[BLM + t]) + (red[2 * BLM + t] + red[3 * BLM + t]));
     lds_sync();
   }
   __syncthreads();  // W is read next by other threads of the workgroup
 }
 __device__ __forceinline__ void w_phase(const float* Q, float* W, int64_t m, int l, int k, float* Wts, const float* Ts,
-                                        const float* Vs, float* vec, float* ws, double* red, float* scr) {
-  if (l <= 32)
-    w_phase_t<5>(Q, W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
-  else
-    w_phase_t<6>(Q, W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
+                                        const float* Vs, float* vec, double* red, float* scr) {
+  if (l <= 16) w_phase_t<8>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 32) w_phase_t<16>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 48) w_phase_t<24>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else w_phase_t<32>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
 }
 
 // ||X - W H||_F^2 and ||X||_F^2 (FP64 sums, fixed order) for thread 0.
@@ -1346,7 +1369,6 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
   float* Vs = lds + OFF_V;
   float* Ss = lds + OFF_S;
   float* vec = lds + OFF_VEC;
-  float* ws = lds + OFF_WS;
   double* red = (double*)(lds + OFF_RED);
   float* scr = lds + OFF_SCR;
   while (true) {
@@ -1390,7 +1412,7 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
         gram_w(p.W, m, k, Ss, scr);
         h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr);
         tv_phase(p.Z, p.H, n, l, k, Ts, Vs, scr);
-        w_phase(p.Q, p.W, m, l, k, Wts, Ts, Vs, vec, ws, red, scr);
+        w_phase(p.Q, p.W, m, l, k, Wts, Ts, Vs, vec, red, scr);
       }
       double out[2];
       rel_err(p.X, ldx, m, n, p.W, p.H, k, scr, red, out);
