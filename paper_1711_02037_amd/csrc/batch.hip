@@ -916,13 +916,16 @@ __device__ __noinline__ void gram_w(const float* __restrict__ W, int64_t m, int 
       valid = (int)((left < GT ? left : GT) * k);
       fetch(r0 + GT, valid);
     }
+    // entries past k are read from the row's padding and feed only sums
+    // that are never stored: the loads carry no condition (a load under a
+    // condition is waited for inside its own branch)
     for (int rr = 0; rr < GT; ++rr) {
       double a[2], b[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = gi + 16 * u, j = gj + 16 * u;
-        a[u] = i < k ? (double)Wsh[rr * (BKM + 1) + i] : 0.0;
-        b[u] = j < k ? (double)Wsh[rr * (BKM + 1) + j] : 0.0;
+        a[u] = (double)Wsh[rr * (BKM + 1) + i];
+        b[u] = (double)Wsh[rr * (BKM + 1) + j];
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
@@ -955,18 +958,12 @@ __device__ __noinline__ void init_wt(const float* __restrict__ Q, const float* _
     rows_load<16>(Qsh, P1, G(Q), r0, m, GT, l);
     rows_load<8>(Wsh, BKM + 1, G(W), r0, m, GT, k);
     lds_sync();
-    for (int rr = 0; rr < GT; ++rr) {
+    for (int rr = 0; rr < GT; ++rr) {  // (padding entries feed unstored sums)
       double qa[4], wj[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int a = ga + 16 * i;
-        qa[i] = a < l ? (double)Qsh[rr * P1 + a] : 0.0;
-      }
+      for (int i = 0; i < 4; ++i) qa[i] = (double)Qsh[rr * P1 + ga + 16 * i];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int j = gj + 16 * u;
-        wj[u] = j < k ? (double)Wsh[rr * (BKM + 1) + j] : 0.0;
-      }
+      for (int u = 0; u < 2; ++u) wj[u] = (double)Wsh[rr * (BKM + 1) + gj + 16 * u];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1107,18 +1104,12 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
       for (int u = 0; u < 4; ++u) s[i][u] = 0.f;
     if (t < 128) {
       const int ga = t % 16, gj = t / 16;
-      for (int c = 0; c < 64; ++c) {
+      for (int c = 0; c < 64; ++c) {  // (padding entries feed unstored sums)
         float za[4], hj[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int a = ga + 16 * i;
-          za[i] = a < l ? Zs[c * P1 + a] : 0.f;
-        }
+        for (int i = 0; i < 4; ++i) za[i] = Zs[c * P1 + ga + 16 * i];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = gj + 8 * u;
-          hj[u] = j < k ? Hs[j * 65 + c] : 0.f;
-        }
+        for (int u = 0; u < 4; ++u) hj[u] = Hs[(gj + 8 * u) * 65 + c];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1126,13 +1117,12 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
       }
     } else if (t < 192) {
       const int v = t - 128, vi = v % 8, vj = v / 8;
-      for (int c = 0; c < 64; ++c) {
+      for (int c = 0; c < 64; ++c) {  // (padding entries feed unstored sums)
         float hi[4], hj[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int a = vi + 8 * i, b = vj + 8 * i;
-          hi[i] = a < k ? Hs[a * 65 + c] : 0.f;
-          hj[i] = b < k ? Hs[b * 65 + c] : 0.f;
+          hi[i] = Hs[(vi + 8 * i) * 65 + c];
+          hj[i] = Hs[(vj + 8 * i) * 65 + c];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
