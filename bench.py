@@ -35,6 +35,8 @@ if ROOT not in sys.path:
 METRIC = "rHALS iters/s + s to rel-err≤1.01×FP32 (100k×5k,k=50): BF16 vs FP32; HBM GB/s"
 WORKLOAD = "tall_100000x5000"
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X published dense FP32 matrix peak
+PEAK_BF16_TFLOPS = 2500.0         # MI355X published dense BF16 matrix peak
 PEAK_HBM_GBPS = 8000.0            # MI355X published HBM3E bandwidth
 SWEEP_SRC = os.path.join(ROOT, "paper_1711_02037_amd", "csrc", "sweep.hip")
 
@@ -83,6 +85,8 @@ def main():
     ap.add_argument("--no-stack", action="store_true", help="skip the 32,256 x 2,410 image-stack workload")
     ap.add_argument("--no-orders", action="store_true", help="skip the update-order timings")
     ap.add_argument("--no-speedup", action="store_true", help="skip the HALS/rHALS speedup study over k")
+    ap.add_argument("--no-kernel-profile", action="store_true",
+                    help="skip the per-kernel X-pass timing (torch.profiler; off under rocprofv3)")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
                     "speedup series (Sec. 4.4 figure), e.g. 10,20,50")
     args = ap.parse_args()
@@ -189,15 +193,13 @@ def main():
 
     gb32, ms32 = pass_gbps(X, Q32, "fp32")
     gb16, ms16 = pass_gbps(Xb, Qb, "bf16")
-    rs = read_stream_gbps(torch, X, dev)
     xpass = {"fp32_compress_GBps": round(gb32, 1), "fp32_compress_ms": round(ms32, 4),
              "bf16_compress_GBps": round(gb16, 1), "bf16_compress_ms": round(ms16, 4),
              "frac_of_8TBps": {"fp32": round(gb32 / PEAK_HBM_GBPS, 4), "bf16": round(gb16 / PEAK_HBM_GBPS, 4)},
-             "read_stream_GBps": round(rs, 1),
-             "frac_of_read_stream": {"fp32": round(gb32 / rs, 4), "bf16": round(gb16 / rs, 4)},
-             "note": "one rnmf_compress call = pack Q + one pass over X + split reduce; read_stream_GBps is "
-                     "torch's sum over the same FP32 X (a plain read stream of 2 GB)"}
-    log(f"X pass: fp32 {gb32:.0f} GB/s, bf16 {gb16:.0f} GB/s (read stream {rs:.0f} GB/s)")
+             "note": "one rnmf_compress call = pack Q + one pass over X + split reduce, timed with events"}
+    if not args.no_kernel_profile:
+        xpass["per_kernel"] = xpass_kernels(rn, torch, step, m, n, l)
+    log(f"X pass: fp32 {gb32:.0f} GB/s, bf16 {gb16:.0f} GB/s; per kernel {xpass.get('per_kernel')}")
 
     # ---- time to 1.01 x FP32 final error --------------------------------------
     ttt = None
@@ -298,20 +300,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def read_stream_gbps(torch, X, dev, reps=10):
-    """GB/s of torch's sum over X: a plain read stream of the same bytes the
-    X passes read, timed with events."""
-    st = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    X.sum()
-    e0.record(st)
-    for _ in range(reps):
-        X.sum()
-    e1.record(st)
-    e1.synchronize()
-    return X.numel() * X.element_size() / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
 
 
 def c2_bench(rn, torch, synth, dev, steps=2):
@@ -652,6 +640,54 @@ def batch_bench(rn, torch, synth, dev, reps=3):
                    "compression, sweeps and error run inside one workgroup"}
     del b, probs
     torch.cuda.empty_cache()
+    return out
+
+
+def xpass_kernels(rn, torch, step, m, n, l):
+    """Device time of each X-pass kernel in one factorize step of each form,
+    from torch.profiler (the HIP runtime's kernel records): GB/s of X moved
+    per pass, fraction of 8 TB/s, and the matrix cores' utilisation against
+    the dense peak of the arithmetic they run (executed products: the BF16
+    form's split operand doubles them)."""
+    from torch.profiler import profile, ProfilerActivity
+    lp = ((l + 15) // 16) * 16
+    kinds = {
+        "nn_bf16": ("nn2_kernel<unsigned short", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "tn_bf16": ("tn2_kernel<unsigned short", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "nn_fp32": ("nn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
+        "tn_fp32": ("tn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
+        "cast_bf16": ("cast_bf16_kernel", 6, 0, None),
+    }
+    times = {key: [] for key in kinds}
+    try:
+        for prec in ("bf16", "fp32"):
+            torch.cuda.synchronize()
+            with profile(activities=[ProfilerActivity.CUDA]) as prof:
+                step(prec, 1)
+                torch.cuda.synchronize()
+            for e in prof.events():
+                dt = getattr(e, "device_time", 0.0) or 0.0
+                if dt <= 0.0:
+                    continue
+                for key, (pat, _, _, _) in kinds.items():
+                    if pat in e.name:
+                        times[key].append(dt)
+    except Exception as ex:  # the profiler is optional context for the line
+        return {"error": str(ex)[:200]}
+    out = {}
+    for key, (pat, es, flops, peak) in kinds.items():
+        if not times[key]:
+            continue
+        us = statistics.mean(times[key])
+        gbps = m * n * es / (us * 1e-6) / 1e9
+        d = {"calls": len(times[key]), "us": round(us, 1), "x_GBps": round(gbps, 1),
+             "frac_of_8TBps": round(gbps / PEAK_HBM_GBPS, 4)}
+        if peak:
+            d["mfma_TFLOPs"] = round(flops / (us * 1e-6) / 1e12, 2)
+            d["frac_of_mfma_peak"] = round(flops / (us * 1e-6) / 1e12 / peak, 4)
+        out[key] = d
+    out["note"] = ("bytes: X once per pass (cast: 4 B read + 2 B written per element); MFMA flops as executed "
+                   f"(l = {l} padded to {lp} columns; BF16 hi + lo operand planes)")
     return out
 
 

@@ -764,13 +764,12 @@ __device__ __noinline__ void gram_y(const float* __restrict__ Y, int64_t rows, i
       const int64_t left = rows - (r0 + GT);
       flat_fetch<16>(yv, G(Y + (r0 + GT) * l), (int)((left < GT ? left : GT) * l));
     }
-    for (int rr = 0; rr < GT; ++rr) {
+    for (int rr = 0; rr < GT; ++rr) {  // (padding entries feed unstored sums)
       double ya[4], yb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int a = ga + 16 * i, b = gb + 16 * i;
-        ya[i] = a < l ? (double)Ys[rr * P1 + a] : 0.0;
-        yb[i] = b < l ? (double)Ys[rr * P1 + b] : 0.0;
+        ya[i] = (double)Ys[rr * P1 + ga + 16 * i];
+        yb[i] = (double)Ys[rr * P1 + gb + 16 * i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -847,10 +846,7 @@ __device__ __noinline__ int cholqr_pass(float* __restrict__ Y_, int64_t rows, in
 #pragma unroll
         for (int i = 0; i < 4; ++i) yr[i] = Ys[(ti + tr * i) * pa + a];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = tj * 4 + u;
-          ar[u] = c < l ? At[a * BLM + c] : 0.f;
-        }
+        for (int u = 0; u < 4; ++u) ar[u] = At[a * BLM + tj * 4 + u];  // (padding: unstored sums)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
