@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-stack", action="store_true", help="skip the 32,256 x 2,410 image-stack workload")
     ap.add_argument("--no-orders", action="store_true", help="skip the update-order timings")
     ap.add_argument("--no-speedup", action="store_true", help="skip the HALS/rHALS speedup study over k")
+    ap.add_argument("--timeline", default="",
+                    help="write the traced sweep's per-column timeline (markdown table) to this file")
     ap.add_argument("--no-kernel-profile", action="store_true",
                     help="skip the per-kernel X-pass timing (torch.profiler; off under rocprofv3)")
     ap.add_argument("--speedup-ks", default="", help="comma-separated ranks for a per-sweep HALS/rHALS "
@@ -169,7 +171,7 @@ def main():
 
     # ---- passes over X: compression = one X pass ------------------------------
     Q32 = rn.sketch(X, k, p, q, omega=Om)
-    split = sweep_split(rn, torch, X, Q32, W0, H0, k)
+    split = sweep_split(rn, torch, X, Q32, W0, H0, k, timeline=args.timeline)
     roofline["limited_by"] = ("latency of the k-long chain of device-wide exchanges (one per W column); "
                               "the FLOP fraction is reported against the FP32 vector peak")
     roofline["per_sweep_us"] = split
@@ -410,7 +412,7 @@ def hals_compare(rn, torch, X, W0, H0, sweeps, reps_f, ws_dev):
             "note": "HALS streams X twice per sweep; rHALS streams it (2q+2) times once, then sweeps on B"}
 
 
-def sweep_split(rn, torch, X, Q, W0, H0, k):
+def sweep_split(rn, torch, X, Q, W0, H0, k, timeline=None):
     """Where a sweep's time goes: one traced two-sweep launch (phase timestamps
     of workgroup 0 in the first sweep, from the device's 100 MHz counter) on
     this workload's Q and B = Q^T X.  Per W column: the device-wide exchange
@@ -426,6 +428,21 @@ def sweep_split(rn, torch, X, Q, W0, H0, k):
         return None
     ex = [b - a for a, b in zip(pre, post)]
     loc = [pre[j] - post[j - 1] for j in range(1, k)]
+    if timeline:
+        # per-column timeline of the traced sweep (microseconds from the
+        # sweep's start), for the record under profiles/
+        t0 = ts[2]
+        rows = ["| column | start of exchange | totals arrived | exchange | local work before it |",
+                "|---:|---:|---:|---:|---:|"]
+        for j in range(k):
+            lw = pre[j] - (post[j - 1] if j > 0 else ts[4])
+            rows.append(f"| {j} | {pre[j] - t0:.2f} | {post[j] - t0:.2f} | {ex[j]:.2f} | {lw:.2f} |")
+        phases = [("H phase", ts[2], ts[3]), ("T/V products and exchange", ts[3], ts[4]),
+                  ("W phase (all columns)", ts[4], ts[5 + 2 * k]),
+                  ("S products and exchange", ts[5 + 2 * k], ts[7 + 2 * k]), ("whole sweep", ts[2], ts[8 + 2 * k])]
+        head = ["| phase | us |", "|---|---:|"] + [f"| {nm} | {b_ - a_:.2f} |" for nm, a_, b_ in phases]
+        with open(timeline, "w") as f:
+            f.write("\n".join(head) + "\n\n" + "\n".join(rows) + "\n")
     return {"sweep": round(ts[8 + 2 * k] - ts[2], 2), "h_phase": round(ts[3] - ts[2], 2),
             "tv_products_and_exchange": round(ts[4] - ts[3], 2), "w_phase": round(ts[5 + 2 * k] - ts[4], 2),
             "s_products_and_exchange": round(ts[7 + 2 * k] - ts[5 + 2 * k], 2),
