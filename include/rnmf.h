@@ -371,7 +371,8 @@ typedef struct rnmf_problem {
   float* H;            /* out: k x n                                          */
   float* Q;            /* out: m x l orthonormal basis                        */
   float* B;            /* out: l x n compressed matrix Q^T X                  */
-  float* Z;            /* scratch: n x l (holds B^T during the sweeps)        */
+  float* Z;            /* scratch: n l + k m floats (B^T, n x l, then W held
+                          by columns, k x m, during the sweeps)              */
   int64_t m, n, ldx;
   int32_t k, l;
   int32_t prec;        /* RNMF_PREC_F32, or RNMF_PREC_BF16: the passes over X

@@ -881,37 +881,39 @@ __device__ __noinline__ unsigned cholqr2(float* Y, int64_t rows, int l, int tc, 
   return st;
 }
 
-// S = W^T W (k x k, FP64 sums) into Ss (pitch BKM).
-__device__ __noinline__ void gram_w(const float* __restrict__ W, int64_t m, int k, float* Ss, float* scr) {
+// S = W^T W (k x k, FP64 sums) into Ss (pitch BKM); W is held by columns
+// (Wc: k x m, column c at Wc + c m).
+__device__ __noinline__ void gram_w(const float* __restrict__ Wc, int64_t m, int k, float* Ss, float* scr) {
   const int t = threadIdx.x;
   float* Wsh = scr;  // GT x (BKM + 1)
   const int gi = t % 16, gj = t / 16;
   double s[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  // The next tile's loads are in flight while the current one is used.  A
-  // load past the tile's last valid element reads that element instead and
-  // is zeroed when stored, so no value is consumed before the next store.
-  float wv[8];
-  int valid = (int)((m < GT ? m : GT) * k);
-  auto fetch = [&](int64_t r0, int cnt) {
-    gcf* base = G(W + r0 * k);
+  gcf* W = G(Wc);
+  // element e = t + u BT of a tile: column e / GT, row r0 + e % GT (GT
+  // consecutive floats of one column per 64 lanes).  The next tile's loads
+  // are in flight while the current one is used; a position past the rows or
+  // columns reads a valid element instead and is zeroed when stored.
+  constexpr int NU = GT * BKM / BT;
+  float wv[NU];
+  auto fetch = [&](int64_t r0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NU; ++u) {
       const int e = t + u * BT;
-      wv[u] = base[e < cnt ? e : cnt - 1];
+      const int c = e / GT;
+      const int64_t r = r0 + (e % GT);
+      wv[u] = W[(int64_t)(c < k ? c : k - 1) * m + (r < m ? r : m - 1)];
     }
   };
-  fetch(0, valid);
+  fetch(0);
   for (int64_t r0 = 0; r0 < m; r0 += GT) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (t + u * BT >= valid) wv[u] = 0.f;
-    flat_store<8>(wv, Wsh, BKM + 1, k, GT * k);
-    lds_sync();
-    if (r0 + GT < m) {
-      const int64_t left = m - (r0 + GT);
-      valid = (int)((left < GT ? left : GT) * k);
-      fetch(r0 + GT, valid);
+    for (int u = 0; u < NU; ++u) {
+      const int e = t + u * BT;
+      const int c = e / GT, r = e % GT;
+      Wsh[r * (BKM + 1) + c] = (c < k && r0 + r < m) ? wv[u] : 0.f;
     }
+    lds_sync();
+    if (r0 + GT < m) fetch(r0 + GT);
     // entries past k are read from the row's padding and feed only sums
     // that are never stored: the loads carry no condition (a load under a
     // condition is waited for inside its own branch)
@@ -938,6 +940,42 @@ __device__ __noinline__ void gram_w(const float* __restrict__ W, int64_t m, int 
       if (i < k && j < k) Ss[i * BKM + j] = (float)s[u][v];
     }
   lds_sync();
+}
+
+// W (m x k, rows) <-> Wc (k x m, columns), in tiles of GT rows through LDS so
+// that both sides are read and written along contiguous runs.
+__device__ __noinline__ void w_to_columns(float* __restrict__ Wc, const float* __restrict__ W, int64_t m, int k,
+                                          float* scr) {
+  const int t = threadIdx.x;
+  float* Wsh = scr;  // GT x (BKM + 1)
+  gf* D = GW(Wc);
+  for (int64_t r0 = 0; r0 < m; r0 += GT) {
+    rows_load<8>(Wsh, BKM + 1, G(W), r0, m, GT, k);
+    lds_sync();
+    for (int e = t; e < GT * k; e += BT) {
+      const int c = e / GT, r = e % GT;
+      if (r0 + r < m) D[(int64_t)c * m + r0 + r] = Wsh[r * (BKM + 1) + c];
+    }
+    lds_sync();
+  }
+}
+__device__ __noinline__ void w_from_columns(float* __restrict__ W, const float* __restrict__ Wc, int64_t m, int k,
+                                            float* scr) {
+  const int t = threadIdx.x;
+  float* Wsh = scr;  // GT x (BKM + 1)
+  gcf* S = G(Wc);
+  gf* D = GW(W);
+  for (int64_t r0 = 0; r0 < m; r0 += GT) {
+    for (int e = t; e < GT * k; e += BT) {
+      const int c = e / GT, r = e % GT;
+      if (r0 + r < m) Wsh[r * (BKM + 1) + c] = S[(int64_t)c * m + r0 + r];
+    }
+    lds_sync();
+    const int64_t left = m - r0;
+    const int cnt = (int)((left < GT ? left : GT) * k);
+    for (int e = t; e < cnt; e += BT) D[r0 * k + e] = Wsh[(e / k) * (BKM + 1) + (e % k)];
+    lds_sync();
+  }
 }
 
 // W~ = Q^T W (l x k, FP64 sums) into Wts (pitch BKM).
@@ -1165,9 +1203,10 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
 // registers.  Per column the 32 rows of a half are summed by lane
 // butterflies, then the four wavefronts in FP64 through LDS, in a fixed
 // order.  Reads past the chunk return zero (buffer loads) or land in the
-// tile's slack and are weighted by zero.
+// tile's slack and are weighted by zero.  W is held by columns (Wc: k x m), so
+// the 32 rows of a chunk store one contiguous run of column j.
 template <int NL>  // coalesced loads per lane per chunk: NL >= ceil(32 l / 64)
-__device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ W, int64_t m, int l, int k,
+__device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ Wc, int64_t m, int l, int k,
                                        float* Wts, const float* Ts, const float* Vs, float* vec, double* red,
                                        float* scr) {
   constexpr int CR = 32;             // rows per chunk
@@ -1182,7 +1221,7 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
   float* Qw = scr + wave * WT;
   const int64_t rw0 = m * wave / 4, rw1 = m * (wave + 1) / 4;
   const int nch = (int)((rw1 - rw0 + CR - 1) / CR);
-  gf* Wg = GW(W);
+  gf* Wg = GW(Wc);
   // Q through a buffer resource (m l floats): a position past the end reads 0.
   // (The arguments of a non-inlined function arrive in vector registers: the
   // base and size are made wavefront-uniform so the resource sits in scalars.)
@@ -1252,7 +1291,7 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
       // the same sum on both halves: half 0's part first
       const float tot = h ? other + part : part + other;
       const float w = r < rw1 ? clipf(tot) : 0.f;
-      if (h == 0 && r < rw1) Wg[r * k + j] = w;
+      if (h == 0 && r < rw1) Wg[(int64_t)j * m + r] = w;
 #pragma unroll
       for (int c = 0; c < NH; ++c) acc[c] = fmaf(q[c], w, acc[c]);
     }
@@ -1272,12 +1311,12 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
   }
   __syncthreads();  // W is read next by other threads of the workgroup
 }
-__device__ __forceinline__ void w_phase(const float* Q, float* W, int64_t m, int l, int k, float* Wts, const float* Ts,
+__device__ __forceinline__ void w_phase(const float* Q, float* Wc, int64_t m, int l, int k, float* Wts, const float* Ts,
                                         const float* Vs, float* vec, double* red, float* scr) {
-  if (l <= 16) w_phase_t<8>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else if (l <= 32) w_phase_t<16>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else if (l <= 48) w_phase_t<24>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else w_phase_t<32>(Q, W, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  if (l <= 16) w_phase_t<8>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 32) w_phase_t<16>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 48) w_phase_t<24>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
+  else w_phase_t<32>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
 }
 
 // ||X - W H||_F^2 and ||X||_F^2 (FP64 sums, fixed order) for thread 0.
@@ -1388,18 +1427,23 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
       if (bf) xtq_pass_bf16(p.X, ldx, m, n, p.Q, l, p.Z, p.B, scr);
       else xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, p.B, tc, scr);
       // initialisation (step 10)
+      // W is held by columns during the sweeps (Wc: k x m after B^T in Z), so
+      // the W phase stores each column as contiguous runs
+      float* Wc = p.Z + n * (int64_t)l;
       for (int e = t; e < OFF_VEC; e += BT) lds[e] = 0.f;  // W~, T, V, S zero beyond k
-      copy_f(p.W, p.W0, m * k);
+      w_to_columns(Wc, p.W0, m, k, scr);
       copy_f(p.H, p.H0, (int64_t)k * n);
       __syncthreads();
-      init_wt(p.Q, p.W, m, l, k, Wts, scr);
+      init_wt(p.Q, p.W0, m, l, k, Wts, scr);
       // sweeps (steps 11-22): H rows, then W columns
       for (int s = 0; s < nsweeps; ++s) {
-        gram_w(p.W, m, k, Ss, scr);
+        gram_w(Wc, m, k, Ss, scr);
         h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr);
         tv_phase(p.Z, p.H, n, l, k, Ts, Vs, scr);
-        w_phase(p.Q, p.W, m, l, k, Wts, Ts, Vs, vec, red, scr);
+        w_phase(p.Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
       }
+      w_from_columns(p.W, Wc, m, k, scr);
+      __syncthreads();
       double out[2];
       rel_err(p.X, ldx, m, n, p.W, p.H, k, scr, red, out);
       if (t == 0) {
