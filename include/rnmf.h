@@ -215,6 +215,15 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
  * their exchange), 124 and 125 the start and end of their arithmetic; 121,
  * 122 and 123 the H phase of wavefront 0 after R = B^T W~, after the S terms
  * and after the row updates.  Asynchronous. */
+/* Launch plan of rnmf_hals_step for this shape on the current device (host
+ * only; nothing is launched).  out: 8 int32 = {workgroups, W rows per
+ * workgroup, H columns per workgroup, 1 if the Q slab is held in registers,
+ * 1 if (with the register slab) the W rows stay in global memory instead of
+ * LDS, dedicated exchange-owner workgroups, LDS bytes per workgroup, rows of
+ * Q staged in LDS (LDS-slab path)}.  opts: prec and tol are used.  Errors:
+ * RNMF_ERR_ARG / ERR_SHAPE for bad arguments, RNMF_ERR_HIP without a device. */
+rnmf_status rnmf_sweep_plan(int64_t m, int64_t n, int32_t l, int32_t k, const rnmf_opts* opts, int32_t* out);
+
 rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n,
                            int32_t l, int32_t k, void* W, void* Wt, void* H,
                            int32_t nsweeps, const rnmf_opts* opts, double* dev_stats,

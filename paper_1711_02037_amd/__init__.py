@@ -45,7 +45,7 @@ EXPORTS = [
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
     "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
     "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered", "rnmf_random", "rnmf_philox4x32_10",
-    "rnmf_hals_step_noalloc",
+    "rnmf_hals_step_noalloc", "rnmf_sweep_plan",
 ]
 
 
@@ -95,6 +95,8 @@ def lib():
         L.rnmf_hals_step_noalloc.argtypes = [vp, vp, i64, i64, i32, i32, vp, vp, vp, i32, ctypes.POINTER(Opts),
                                              vp, vp, vp]
         L.rnmf_hals_step_noalloc.restype = ctypes.c_int
+        L.rnmf_sweep_plan.argtypes = [i64, i64, i32, i32, ctypes.POINTER(Opts), vp]
+        L.rnmf_sweep_plan.restype = ctypes.c_int
         L.rnmf_random.argtypes = [vp, ctypes.c_int, i64, i64, ctypes.c_uint64, ctypes.c_uint32, i32, vp]
         L.rnmf_random.restype = ctypes.c_int
         L.rnmf_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
@@ -336,6 +338,19 @@ def hals_step(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", 
         t0 = ts[0]
         return int(s[0]), s[1], s[2], [(x - t0) / 100.0 if x else None for x in ts]
     return int(s[0]), s[1], s[2]
+
+
+def sweep_plan(m, n, l, k, precision="fp32", tol=0.0):
+    """Launch plan rnmf_hals_step would use for this shape on the current
+    device (rnmf_sweep_plan): dict with the workgroup count, W rows and H
+    columns per workgroup, the Q-slab path ("registers" or "lds"), whether
+    the W rows stay in global memory, the exchange owners and the LDS bytes."""
+    o = make_opts(k, l - k, 0, tol=tol, precision=precision)
+    out = (ctypes.c_int32 * 8)()
+    _check(lib().rnmf_sweep_plan(int(m), int(n), int(l), int(k), ctypes.byref(o), out))
+    return dict(workgroups=out[0], rows_per=out[1], cols_per=out[2],
+                q_slab="registers" if out[3] else "lds", w_global=bool(out[4]), owners=out[5],
+                lds_bytes=out[6], q_rows_in_lds=out[7])
 
 
 def hals_step_noalloc(Q, B, W, Wt, H, nsweeps=1, tol=0.0, gram="full", order="h_first", precision=None, reg=None):

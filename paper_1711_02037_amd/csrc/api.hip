@@ -852,6 +852,27 @@ rnmf_status rnmf_compress(const void* X, int xt, int64_t m, int64_t n, int64_t l
   return run_compress(Xc, m, n, ldc, Q, l, B, b, md, d);
 }
 
+rnmf_status rnmf_sweep_plan(int64_t m, int64_t n, int32_t l, int32_t k, const rnmf_opts* o, int32_t* out) {
+  g_err.clear();
+  if (!o || !out) return fail(RNMF_ERR_ARG, "opts and out must be non-NULL");
+  if (m < 1 || n < 1 || m > 0x7fffffffLL || n > 0x7fffffffLL) return fail(RNMF_ERR_SHAPE, "bad m or n");
+  if (k < 1 || k > KMAX) return fail(RNMF_ERR_ARG, "need 1 <= k <= %d", KMAX);
+  if (l < k || l > LMAX || l > m) return fail(RNMF_ERR_SHAPE, "need k <= l <= min(m, %d)", LMAX);
+  if (o->prec < 0 || o->prec > 2) return fail(RNMF_ERR_ARG, "unknown precision mode");
+  Dev d;
+  if (!get_dev(d, nullptr)) return fail(RNMF_ERR_HIP, "no usable HIP device");
+  const SweepShape sh = plan_sweep(m, n, l, k, mode_of(o).dt, d, o->tol > 0.0);
+  out[0] = sh.G;
+  out[1] = sh.rows_per;
+  out[2] = sh.cols_per;
+  out[3] = sh.regq;
+  out[4] = sh.wglobal;
+  out[5] = sh.xown;
+  out[6] = (int32_t)sh.lds_bytes;
+  out[7] = sh.regq ? 0 : sh.rows_lds;
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_hals_step(const void* Q, const void* B, int64_t m, int64_t n, int32_t l, int32_t k, void* W,
                            void* Wt, void* H, int32_t nsweeps, const rnmf_opts* o, double* dev_stats, void* ws,
                            size_t ws_bytes, void* stream) {

@@ -189,6 +189,7 @@ hipError_t launch_chol(double* G, int l, int64_t rows, void* RinvT, int lp, int 
 struct SweepShape {
   int G, GR, GC, rows_per, cols_per, rows_lds, cb, nt, red2_elems, alias_sv, regq;
   int xown;  // dedicated exchange-owner workgroups (the last xown of G; no rows or columns)
+  int wglobal;  // register-Q path with the W rows in global memory instead of LDS
   size_t lds_bytes;
 };
 SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, bool need_pg);

@@ -442,7 +442,12 @@ __device__ __forceinline__ void upper_block(int b, int nb, int& r, int& c) {
 constexpr int RQ = 7;       // at most 448 rows per workgroup
 constexpr int CQMAX = 12;   // at most 8 x 12 = 96 columns (FP32; FP64 takes 9, 72 columns)
 
-template <typename T, bool REGQ, int CQ>
+// WG (with REGQ): the W rows stay in global memory (each workgroup owns rows
+// r0 .. r0 + nr - 1 of W, which no other workgroup touches during the
+// launch); the W phase stores W(r, j) there and S = W^T W is formed after the
+// W phase from those rows, like the LDS-slab path.  This frees the LDS the
+// rows would take, for tall inputs at larger k.
+template <typename T, bool REGQ, int CQ, bool WG>
 __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = (T*)smem_raw;
@@ -476,7 +481,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
   // and columns of B and H for the whole launch
   const int cp = a.cols_per;
   T* Ws = Qs + (size_t)a.rows_lds * lq;           // (rows_per + 1) x k (REGQ; the last row is a sink)
-  T* Bs = Ws + (size_t)(a.rows_per + 1) * k;      // l x cols_per   (REGQ)
+  T* Bs = Ws + (WG ? (size_t)0 : (size_t)(a.rows_per + 1) * k);  // l x cols_per   (REGQ)
   T* Hs = Bs + (size_t)l * cp;                    // k x cols_per   (REGQ)
   const T* Bp;
   T* Hp;
@@ -500,7 +505,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         const int rr = ga + 64 * i, aa = gc * CQ + s;
         qreg[i][s] = (rr < nr && aa < l) ? a.Q[(size_t)(r0 + rr) * l + aa] : (T)0;
       }
-    for (int e = t; e < nr * k; e += NTH) Ws[e] = a.W[(size_t)r0 * k + e];
+    if constexpr (!WG)
+      for (int e = t; e < nr * k; e += NTH) Ws[e] = a.W[(size_t)r0 * k + e];
     for (int e = t; e < l * cp; e += NTH) {
       const int r = e / cp, cc = e - (e / cp) * cp;
       Bs[e] = cc < nc ? a.B[(size_t)r * n + c0 + cc] : (T)0;
@@ -555,12 +561,13 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         pf[q] = (e < RC * kp && cstart + rr < nr && cc < k) ? a.W[(size_t)(r0 + cstart + rr) * k + cc] : (T)0;
       }
     };
-    if constexpr (!REGQ) fetch(0);
-    // REGQ: rows come straight from the LDS copy Ws (leading dimension k)
-    const int lds_ld = REGQ ? k : kp;
+    constexpr bool WLDS = REGQ && !WG;  // rows in the LDS copy Ws
+    if constexpr (!WLDS) fetch(0);
+    // rows come straight from the LDS copy Ws (leading dimension k) when it exists
+    const int lds_ld = WLDS ? k : kp;
     for (int cs = 0; cs < nr; cs += RC) {
       const T* rows;
-      if constexpr (REGQ) {
+      if constexpr (WLDS) {
         rows = Ws + (size_t)cs * k;
       } else {
         rows = red2;
@@ -580,8 +587,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int c1 = 4 * ba + q, c2 = 4 * bb + q;
-            u[q] = (REGQ && c1 >= k) ? 0.0 : (double)rows[rr * lds_ld + c1];
-            w[q] = (REGQ && c2 >= k) ? 0.0 : (double)rows[rr * lds_ld + c2];
+            u[q] = (WLDS && c1 >= k) ? 0.0 : (double)rows[rr * lds_ld + c1];
+            w[q] = (WLDS && c2 >= k) ? 0.0 : (double)rows[rr * lds_ld + c2];
           }
 #pragma unroll
           for (int p = 0; p < 4; ++p)
@@ -1053,13 +1060,21 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
         w[i] = clip0<T>(sum8<T>(u0 + u1) - shift);
       }
       if (gc == 0) {
-        // W is written back once, at the end; rows past the slab land in the
-        // sink row rows_per, or in rows nr .. rows_per - 1 that no one reads
-        // (a clamp instead of a predicate per row)
+        if constexpr (WG) {
 #pragma unroll
-        for (int i = 0; i < RQ; ++i) {
-          const int rr = min(ga + 64 * i, a.rows_per);
-          Ws[rr * k + jj] = w[i];
+          for (int i = 0; i < RQ; ++i) {
+            const int rr = ga + 64 * i;
+            if (rr < nr) a.W[(size_t)(r0 + rr) * k + jj] = w[i];
+          }
+        } else {
+          // W is written back once, at the end; rows past the slab land in the
+          // sink row rows_per, or in rows nr .. rows_per - 1 that no one reads
+          // (a clamp instead of a predicate per row)
+#pragma unroll
+          for (int i = 0; i < RQ; ++i) {
+            const int rr = min(ga + 64 * i, a.rows_per);
+            Ws[rr * k + jj] = w[i];
+          }
         }
       }
       // local map-back partials: sum_i Q(r_i, a) w_i over this thread's rows
@@ -1112,7 +1127,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           cs = (c0 + c1) + (c2 + c3);
         }
       } else if (t >= 128) {
-        if (need_S) {
+        if (need_S && !WG) {
           // local S(i, j) = sum_r W(r, i) W(r, j) for i <= j (columns i < j
           // are final): entry i, rows r = p, p + P, ... in part p
           const int h = t - 128, np = 384 / (jj + 1);
@@ -1155,7 +1170,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
           vec[t] = wo + ((Tm[t * k + nj] - s) - aw * wo) / (Vm[nj * k + nj] + aw);
         }
       }
-      s_cols |= 1ull << jj;
+      if constexpr (!WG) s_cols |= 1ull << jj;
       if (!ok) abort_flag = 1;
       if (tr_sweep) { TRACE(6 + 2 * jj); }
       lds_sync();
@@ -1163,7 +1178,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       jprev = jj;
       jj = nj;
     }
-    if (need_S && jprev >= 0) {
+    if (need_S && !WG && jprev >= 0) {
       const int h = t - 128;
       if (h >= 0 && h <= jprev) {
         const int npp = 384 / (jprev + 1);
@@ -1270,7 +1285,7 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();  // W and H written by other threads of this workgroup
     double s = 0.0;
     const T* Wrows;
-    if constexpr (REGQ) Wrows = Ws;
+    if constexpr (REGQ && !WG) Wrows = Ws;
     else Wrows = a.W + (size_t)r0 * k;
     for (int e = t; e < nr * k; e += NTH) {
       int rr = e / k, cc = e % k;
@@ -1390,7 +1405,8 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
       const int r = e / nc, cc = e - (e / nc) * nc;
       a.H[(size_t)r * n + c0 + cc] = Hs[r * cp + cc];
     }
-    for (int e = t; e < nr * k; e += NTH) a.W[(size_t)r0 * k + e] = Ws[e];
+    if constexpr (!WG)
+      for (int e = t; e < nr * k; e += NTH) a.W[(size_t)r0 * k + e] = Ws[e];
   }
   if (g == 0) {
     for (int e = t; e < l * k; e += NTH) a.Wt[e] = Wts[e];
@@ -1436,23 +1452,30 @@ SweepShape plan_sweep(int64_t m, int64_t n, int l, int k, int dt, const Dev& d, 
   red2 = round_up(red2, 4);
   sh.red2_elems = (int)red2;
   // REGQ needs the W rows and the B and H columns in LDS besides the fixed part
-  auto regq_extra_of = [&]() {
-    return ((size_t)(sh.rows_per + 1) * k + (size_t)(l + k) * sh.cols_per) * es;
+  // (without the W rows when they stay in global memory)
+  auto regq_extra_of = [&](bool wg) {
+    return ((wg ? (size_t)0 : (size_t)(sh.rows_per + 1) * k) + (size_t)(l + k) * sh.cols_per) * es;
   };
-  auto regq_fits_of = [&]() {
+  auto regq_fits_of = [&](bool wg) {
     const size_t fixed2 = ((size_t)l * k + (size_t)l * k + 2 * (size_t)k * k + LPS + sh.rows_per + red2) * es;
-    return sh.rows_per <= 64 * RQ && l <= 8 * (dt == 0 ? 9 : CQMAX) && fixed2 + regq_extra_of() + 1024 <= (size_t)d.max_lds;
+    return sh.rows_per <= 64 * RQ && l <= 8 * (dt == 0 ? 9 : CQMAX) && fixed2 + regq_extra_of(wg) + 1024 <= (size_t)d.max_lds;
   };
-  bool regq_fits = regq_fits_of();
+  sh.wglobal = 0;
+  bool regq_fits = regq_fits_of(false);
+  // the W-global variant exists for FP32 with the 12-column Q slab (l > 72)
+  if (!regq_fits && dt != 0 && l > 72 && regq_fits_of(true)) {
+    regq_fits = true;
+    sh.wglobal = 1;
+  }
   if (!regq_fits && sh.xown) {
     // without the owners the rows spread over all workgroups; the LDS-slab
     // path exchanges by the two-hop scheme over all workgroups
     sh.xown = 0;
     sh.rows_per = ceil_div(m, G);
     sh.cols_per = ceil_div(n, G);
-    regq_fits = regq_fits_of();
+    regq_fits = regq_fits_of(false);
   }
-  const size_t regq_extra = regq_extra_of();
+  const size_t regq_extra = regq_extra_of(sh.wglobal != 0);
   sh.alias_sv = (need_pg || regq_fits) ? 0 : 1;
   size_t fixed = ((size_t)l * k + (size_t)l * k + (size_t)(sh.alias_sv ? 1 : 2) * k * k + LPS + sh.rows_per + red2) * es;
   size_t budget = (size_t)d.max_lds - 1024;  // static shared + alignment slack
@@ -1499,15 +1522,17 @@ hipError_t launch_sweep(const SweepShape& sh, int dt, const void* Q, const void*
   if (dt == 0) {
     FILL_ARGS(double);
     void* args[] = {&a};
-    const void* fn = sh.regq ? (const void*)sweep_kernel<double, true, 9> : (const void*)sweep_kernel<double, false, 1>;
+    const void* fn = sh.regq ? (const void*)sweep_kernel<double, true, 9, false> : (const void*)sweep_kernel<double, false, 1, false>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);
   } else {
     FILL_ARGS(float);
     void* args[] = {&a};
-    const void* fn = !sh.regq ? (const void*)sweep_kernel<float, false, 1>
-                     : (l <= 72) ? (const void*)sweep_kernel<float, true, 9> : (const void*)sweep_kernel<float, true, 12>;
+    const void* fn = !sh.regq ? (const void*)sweep_kernel<float, false, 1, false>
+                     : (l <= 72) ? (const void*)sweep_kernel<float, true, 9, false>
+                     : sh.wglobal ? (const void*)sweep_kernel<float, true, 12, true>
+                                  : (const void*)sweep_kernel<float, true, 12, false>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bytes);
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(fn, dim3(sh.G), dim3(NTH), args, (unsigned)sh.lds_bytes, s);

@@ -163,6 +163,36 @@ def test_hals_step_lds_slab_path(m, n, k, l, tol):
     assert relf(host(d[4]), a[4]) <= 2e-5
 
 
+@pytest.mark.parametrize("gram,tol", [("full", 0.0), ("lowdim", 0.0), ("mixed", 0.0), ("full", 1e-12)])
+@pytest.mark.parametrize("m,n,k,l", [(100000, 600, 64, 84), (99991, 257, 60, 80)])
+def test_hals_step_w_global_path(gram, tol, m, n, k, l):
+    # Q slab in registers with the W rows in global memory: the rows of W
+    # (about 400 per workgroup at this k) do not fit in LDS beside the rest
+    plan = rn.sweep_plan(m, n, l, k, tol=tol)
+    assert plan["q_slab"] == "registers" and plan["w_global"], plan
+    Q, B, W, Wt, H = sweep_inputs(m, n, k, l, 23, np.float32)
+    d = [dev(a) for a in (Q, B, W, Wt, H)]
+    done, _, _ = rn.hals_step(*d, nsweeps=2, gram=gram, tol=tol)
+    assert done == 2
+    a = tuple(x.astype(np.float64) for x in (Q, B, W, Wt, H))
+    for _ in range(2):
+        a = a[:2] + o.rhals_sweep(*a, gram_mode=rn.GRAM[gram])
+    assert relf(host(d[2]), a[2]) <= 2e-5
+    assert relf(host(d[3]), a[3]) <= 2e-5
+    assert relf(host(d[4]), a[4]) <= 2e-5
+    assert host(d[2]).min() >= 0 and host(d[4]).min() >= 0
+
+
+def test_sweep_plan_paths():
+    # the headline shape keeps W in LDS; the LDS-slab path beyond 448 rows
+    p = rn.sweep_plan(100000, 5000, 70, 50)
+    assert p["q_slab"] == "registers" and not p["w_global"] and p["owners"] > 0
+    p = rn.sweep_plan(120000, 200, 16, 8)
+    assert p["q_slab"] == "lds"
+    p = rn.sweep_plan(100000, 5000, 84, 64)
+    assert p["q_slab"] == "registers" and p["w_global"]
+
+
 @pytest.mark.parametrize("gram", ["full", "lowdim", "mixed"])
 def test_hals_step_fp64_ten_sweeps(gram):
     Q, B, W, Wt, H = sweep_inputs(500, 400, 10, 30, 22, np.float64)
