@@ -417,13 +417,25 @@ rnmf_status rnmf_batch_run(int32_t nprob, int32_t q, int32_t nsweeps, void* ws, 
 rnmf_status rnmf_batch_results(int32_t nprob, void* ws, size_t ws_bytes, double* rel_err, int32_t* status,
                                void* stream);
 
-/* Times each X-pass tiling on the planned batch (q subspace iterations, no
- * sweeps), keeps the fastest per sketch-width class in the library's
- * autotune table (the only library-global state) and re-plans the batch with
- * it.  tiling_out (host, 4 entries, may be NULL) receives the table: column
- * groups for l <= 16, <= 32, <= 48, <= 64.  Synchronises the stream. */
+/* Tunes the batch per sketch-width class (l <= 16, <= 32, <= 48, <= 64), on
+ * that class's own problems: times each X-pass tiling (q subspace
+ * iterations and compression, no sweeps), then, with the chosen tiling, each
+ * H-phase tile width that fits (64, 128 or 256 columns of B^T staged per
+ * tile; 8 sweeps).  Keeps the fastest in the library's autotune table (the
+ * only library-global state) and re-plans the batch with it.  tiling_out
+ * (host, 8 entries, may be NULL) receives the table: column groups for the
+ * four classes, then the H-phase tile widths.  Synchronises the stream. */
 rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_t q, void* ws,
                                 size_t ws_bytes, int32_t* tiling_out, void* stream);
+
+/* The autotune table (8 int32, the layout rnmf_batch_autotune reports):
+ * read it, or set it, for instance from an earlier tuning run.  Set checks
+ * every entry (column groups 4, 8 or 16; tile widths 64, 128 or 256) and
+ * changes nothing on error (RNMF_ERR_ARG).  rnmf_batch_plan uses the table
+ * current at its call; a problem whose sketch is wider than an entry allows
+ * takes the next wider tiling or narrower tile.  Host only. */
+rnmf_status rnmf_batch_set_tuning(const int32_t* table);
+rnmf_status rnmf_batch_get_tuning(int32_t* table);
 
 /* nsweeps sweeps of deterministic HALS (Sec. 3.1, residual-free block rules)
  * on X itself, in place; randomized HALS is this algorithm run on the

@@ -45,7 +45,7 @@ EXPORTS = [
     "rnmf_batch_workspace_bytes", "rnmf_batch_plan", "rnmf_batch_run", "rnmf_batch_results",
     "rnmf_batch_autotune", "rnmf_backward_workspace_bytes", "rnmf_backward", "rnmf_unroll",
     "rnmf_hals_ordered_workspace_bytes", "rnmf_hals_ordered", "rnmf_random", "rnmf_philox4x32_10",
-    "rnmf_hals_step_noalloc", "rnmf_sweep_plan",
+    "rnmf_hals_step_noalloc", "rnmf_sweep_plan", "rnmf_batch_set_tuning", "rnmf_batch_get_tuning",
 ]
 
 
@@ -602,6 +602,18 @@ def rand_hals_fn():
     return _rand_hals
 
 
+def batch_tuning(table=None):
+    """The batch autotune table (8 ints: X-pass column groups for l <= 16,
+    32, 48, 64, then the H-phase tile widths); with table given, set it first
+    (rnmf_batch_set_tuning).  Returns the table now in force."""
+    if table is not None:
+        t = (ctypes.c_int32 * 8)(*[int(x) for x in table])
+        _check(lib().rnmf_batch_set_tuning(t))
+    out = (ctypes.c_int32 * 8)()
+    _check(lib().rnmf_batch_get_tuning(out))
+    return list(out)
+
+
 class Batch:
     """Batched randomized HALS (rnmf_batch_*): many independent problems in one
     persistent launch.  problems: list of (X, Omega, W0, H0) FP32 device
@@ -651,7 +663,7 @@ class Batch:
         self.keep, self.ws = _workspace(nb, self.device)
         self.tiling = None
         if autotune:
-            tab = (ctypes.c_int32 * 4)()
+            tab = (ctypes.c_int32 * 8)()
             _check(lib().rnmf_batch_autotune(descs, self.n, int(q), _ptr(self.ws), self.ws.numel(), tab,
                                              _stream(self.device)))
             self.tiling = list(tab)

@@ -507,10 +507,11 @@ BatchLayout batch_layout(void* ws, int nprob) {
   return L;
 }
 
-// X-pass column groups per sketch-width class (l <= 16, 32, 48, 64): the
-// autotune table, the library's only global state.
+// Per sketch-width class (l <= 16, 32, 48, 64): X-pass column groups
+// (entries 0-3) and H-phase tile widths (entries 4-7).  The autotune table,
+// the library's only global state.
 std::mutex g_batch_mu;
-int g_batch_tc[4] = {4, 8, 16, 16};
+int g_batch_tc[8] = {4, 8, 16, 16, 256, 256, 128, 128};
 
 int l_class(int l) { return l <= 16 ? 0 : (l <= 32 ? 1 : (l <= 48 ? 2 : 3)); }
 
@@ -547,7 +548,9 @@ rnmf_status upload_plan(const rnmf_problem* probs, int nprob, const BatchLayout&
     const rnmf_problem& p = probs[order[j]];
     int tc = table[l_class(p.l)];
     while (4 * tc < p.l) tc *= 2;
-    batch_fill_desc(host.data() + (size_t)j * db, p, order[j], tc);
+    int hct = table[4 + l_class(p.l)];
+    while (!batch_hct_ok(hct, p.l) && hct > 64) hct /= 2;
+    batch_fill_desc(host.data() + (size_t)j * db, p, order[j], tc, hct);
   }
   HIPCHK(hipMemcpyAsync(L.descs, host.data(), host.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1171,7 +1174,7 @@ rnmf_status rnmf_batch_plan(const rnmf_problem* probs, int32_t nprob, void* ws, 
   if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
-  int table[4];
+  int table[8];
   {
     std::lock_guard<std::mutex> g(g_batch_mu);
     std::memcpy(table, g_batch_tc, sizeof(table));
@@ -1217,6 +1220,28 @@ rnmf_status rnmf_batch_results(int32_t nprob, void* ws, size_t ws_bytes, double*
   return RNMF_OK;
 }
 
+rnmf_status rnmf_batch_set_tuning(const int32_t* table) {
+  g_err.clear();
+  if (!table) return fail(RNMF_ERR_ARG, "table is NULL");
+  for (int c = 0; c < 4; ++c) {
+    if (table[c] != 4 && table[c] != 8 && table[c] != 16)
+      return fail(RNMF_ERR_ARG, "entry %d: column groups must be 4, 8 or 16", c);
+    if (table[4 + c] != 64 && table[4 + c] != 128 && table[4 + c] != 256)
+      return fail(RNMF_ERR_ARG, "entry %d: H-phase tile width must be 64, 128 or 256", 4 + c);
+  }
+  std::lock_guard<std::mutex> g(g_batch_mu);
+  std::memcpy(g_batch_tc, table, sizeof(g_batch_tc));
+  return RNMF_OK;
+}
+
+rnmf_status rnmf_batch_get_tuning(int32_t* table) {
+  g_err.clear();
+  if (!table) return fail(RNMF_ERR_ARG, "table is NULL");
+  std::lock_guard<std::mutex> g(g_batch_mu);
+  std::memcpy(table, g_batch_tc, sizeof(g_batch_tc));
+  return RNMF_OK;
+}
+
 rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_t q, void* ws, size_t ws_bytes,
                                 int32_t* tiling_out, void* stream) {
   g_err.clear();
@@ -1231,7 +1256,7 @@ rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_
   if ((r = check_ws(ws, ws_bytes, L.bytes)) != RNMF_OK) return r;
   Dev d;
   if (!get_dev(d, (hipStream_t)stream)) return fail(RNMF_ERR_HIP, "no usable HIP device");
-  int table[4];
+  int table[8];
   {
     std::lock_guard<std::mutex> g(g_batch_mu);
     std::memcpy(table, g_batch_tc, sizeof(table));
@@ -1247,8 +1272,26 @@ rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_
   } guard{&e0, &e1};
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // each sketch-width class separately: its problems only, every tiling that
-  // covers the class's widest sketch, the range finder and compression only
+  // one timed launch (after a warm-up) of a sub-batch with a forced table
+  auto time_run = [&](const std::vector<rnmf_problem>& sub, const int* forced, int nsw, float* ms) -> rnmf_status {
+    const int ns = (int)sub.size();
+    const BatchLayout S = batch_layout(ws, ns);
+    rnmf_status rr;
+    if ((rr = upload_plan(sub.data(), ns, S, forced, nullptr, d.stream)) != RNMF_OK) return rr;
+    const int grid = ns < 2 * d.cus ? ns : 2 * d.cus;
+    HIPCHK(launch_batch(S.descs, ns, q, nsw, S.counter, S.err, S.status, grid, d.stream));  // warm-up
+    HIPCHK(hipEventRecord(e0, d.stream));
+    HIPCHK(launch_batch(S.descs, ns, q, nsw, S.counter, S.err, S.status, grid, d.stream));
+    HIPCHK(hipEventRecord(e1, d.stream));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return RNMF_OK;
+  };
+  // each sketch-width class separately, on its own problems: first every
+  // X-pass tiling that covers the class's widest sketch (range finder and
+  // compression only), then every H-phase tile width that fits it (with
+  // TUNE_SWEEPS sweeps, the X-pass tiling just chosen)
+  constexpr int TUNE_SWEEPS = 8;
   for (int cls = 0; cls < 4; ++cls) {
     std::vector<rnmf_problem> sub;
     int lmax = 0;
@@ -1262,24 +1305,30 @@ rnmf_status rnmf_batch_autotune(const rnmf_problem* probs, int32_t nprob, int32_
     int best = table[cls];
     for (int tc : {4, 8, 16}) {
       if (4 * tc < lmax) continue;
-      int forced[4] = {tc, tc, tc, tc};
-      const int ns = (int)sub.size();
-      const BatchLayout S = batch_layout(ws, ns);
-      if ((r = upload_plan(sub.data(), ns, S, forced, nullptr, d.stream)) != RNMF_OK) return r;
-      const int grid = ns < 2 * d.cus ? ns : 2 * d.cus;
-      HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));  // warm-up
-      HIPCHK(hipEventRecord(e0, d.stream));
-      HIPCHK(launch_batch(S.descs, ns, q, 0, S.counter, S.err, S.status, grid, d.stream));
-      HIPCHK(hipEventRecord(e1, d.stream));
-      HIPCHK(hipEventSynchronize(e1));
+      int forced[8];
+      for (int c = 0; c < 4; ++c) { forced[c] = tc; forced[4 + c] = table[4 + c]; }
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if ((r = time_run(sub, forced, 0, &ms)) != RNMF_OK) return r;
       if (best_ms == 0.f || ms < best_ms) {
         best_ms = ms;
         best = tc;
       }
     }
     table[cls] = best;
+    best_ms = 0.f;
+    int best_h = table[4 + cls];
+    for (int hct : {64, 128, 256}) {
+      if (!batch_hct_ok(hct, lmax)) continue;
+      int forced[8];
+      for (int c = 0; c < 4; ++c) { forced[c] = table[c]; forced[4 + c] = hct; }
+      float ms = 0.f;
+      if ((r = time_run(sub, forced, TUNE_SWEEPS, &ms)) != RNMF_OK) return r;
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best_h = hct;
+      }
+    }
+    table[4 + cls] = best_h;
   }
   {
     std::lock_guard<std::mutex> g(g_batch_mu);

@@ -55,6 +55,7 @@ struct BDesc {
   rnmf_problem p;
   int32_t idx;  // position in the caller's array
   int32_t tc;   // X-pass column groups: 4, 8 or 16 (4 x 4 per thread)
+  int32_t hct;  // H-phase tile: columns of B^T staged per tile (64, 128 or 256)
 };
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
@@ -1021,15 +1022,17 @@ __device__ __noinline__ void init_wt(const float* __restrict__ Q, const float* _
 // H are independent); W~, S and the reciprocal scales are LDS broadcasts.
 // KB >= k: W~ and S are zero beyond k, so the extra rows have scale zero and
 // are skipped like any zero-scale row.  B^T is staged through LDS in tiles of
-// NCT columns (256 when l <= 32, else 128).  FP64 gradient; H entries are
-// FP32 values (every update is rounded to FP32 before it is used).
+// NCT columns (64, 128 or 256: a tuning choice per sketch-width class, with
+// NCT (l + 1) <= SCR_FLOATS; one lane per column, so NCT < BT leaves lanes
+// idle while a wider tile takes two rounds of loads).  FP64 gradient; H
+// entries are FP32 values (every update is rounded to FP32 before it is
+// used).
 template <int KB>
 __device__ __noinline__ void h_phase_t(const float* __restrict__ Bt, float* __restrict__ H, int64_t n, int l, int k,
-                                       const float* Wts, const float* Ss, double* rinv, float* scr) {
+                                       const float* Wts, const float* Ss, double* rinv, float* scr, int NCT) {
   const int t = threadIdx.x;
   gcf* Hg = G(H);
   gf* Hw = GW(H);
-  const int NCT = (l <= 32) ? 256 : 128;  // NCT * l <= 32 * BT: the tile fits the 32 loads per thread
   const int pz = l + 1;
   float* Zs = scr;  // NCT x (l + 1)
   if (t < KB) {
@@ -1046,8 +1049,12 @@ __device__ __noinline__ void h_phase_t(const float* __restrict__ Bt, float* __re
       asm volatile("" : "+v"(tt));
       float zv[32];
       const int64_t left = n - c0;
-      flat_fetch<32>(zv, G(Bt + c0 * l), (int)((left < NCT ? left : NCT) * l), tt);
-      flat_store<32>(zv, Zs, pz, l, NCT * l, tt);
+      const int valid = (int)((left < NCT ? left : NCT) * l);
+      // rounds of 32 loads per thread (two at most: NCT l <= SCR_FLOATS)
+      for (int e0 = 0; e0 < valid; e0 += 32 * BT) {
+        flat_fetch<32>(zv, G(Bt + c0 * l + e0), valid - e0, tt);
+        flat_store<32>(zv, Zs, pz, l, NCT * l, tt + e0);
+      }
     }
     lds_sync();
     const int64_t c = c0 + t;
@@ -1096,11 +1103,11 @@ __device__ __noinline__ void h_phase_t(const float* __restrict__ Bt, float* __re
 }
 
 __device__ __noinline__ void h_phase(const float* Bt, float* H, int64_t n, int l, int k, const float* Wts,
-                                     const float* Ss, double* rinv, float* scr) {
-  if (k <= 8) h_phase_t<8>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
-  else if (k <= 16) h_phase_t<16>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
-  else if (k <= 24) h_phase_t<24>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
-  else h_phase_t<32>(Bt, H, n, l, k, Wts, Ss, rinv, scr);
+                                     const float* Ss, double* rinv, float* scr, int nct) {
+  if (k <= 8) h_phase_t<8>(Bt, H, n, l, k, Wts, Ss, rinv, scr, nct);
+  else if (k <= 16) h_phase_t<16>(Bt, H, n, l, k, Wts, Ss, rinv, scr, nct);
+  else if (k <= 24) h_phase_t<24>(Bt, H, n, l, k, Wts, Ss, rinv, scr, nct);
+  else h_phase_t<32>(Bt, H, n, l, k, Wts, Ss, rinv, scr, nct);
 }
 
 // T = B H^T (l x k) and V = H H^T (k x k) over 64-column tiles: FP32 within a
@@ -1438,7 +1445,7 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
       // sweeps (steps 11-22): H rows, then W columns
       for (int s = 0; s < nsweeps; ++s) {
         gram_w(Wc, m, k, Ss, scr);
-        h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr);
+        h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr, d.hct);
         tv_phase(p.Z, p.H, n, l, k, Ts, Vs, scr);
         w_phase(p.Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
       }
@@ -1466,11 +1473,16 @@ size_t batch_lds_bytes() { return (size_t)LDS_FLOATS * sizeof(float); }
 
 // descs: device array of nprob descriptors (BDesc layout, filled by the host
 // from batch_fill_desc).
-void batch_fill_desc(void* dst, const rnmf_problem& p, int idx, int tc) {
+bool batch_hct_ok(int hct, int l) {
+  return (hct == 64 || hct == 128 || hct == 256) && hct * (l + 1) <= SCR_FLOATS;
+}
+
+void batch_fill_desc(void* dst, const rnmf_problem& p, int idx, int tc, int hct) {
   BDesc d;
   d.p = p;
   d.idx = idx;
   d.tc = tc;
+  d.hct = hct;
   *(BDesc*)dst = d;
 }
 

@@ -169,7 +169,8 @@ struct SvdBufs {
 // Batched randomized HALS (batch.hip).
 size_t batch_desc_bytes();
 size_t batch_lds_bytes();
-void batch_fill_desc(void* dst, const ::rnmf_problem& p, int idx, int tc);
+void batch_fill_desc(void* dst, const ::rnmf_problem& p, int idx, int tc, int hct);
+bool batch_hct_ok(int hct, int l);  // H-phase tile width valid for sketch width l
 hipError_t launch_batch(const void* descs, int nprob, int q, int nsweeps, unsigned* counter, double* err,
                         unsigned* status, int grid, hipStream_t s);
 

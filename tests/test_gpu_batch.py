@@ -140,15 +140,45 @@ def test_batch_graph_replays_match_eager(small):
             assert torch.equal(w, P["W"]) and torch.equal(h, P["H"]), rep
 
 
+def test_batch_h_tile_width_does_not_change_results(small):
+    # each lane updates one column of H whatever the tile width: bit-identical
+    saved = rn.batch_tuning()
+    try:
+        outs = []
+        for hct in (64, 128, 256):
+            rn.batch_tuning([4, 8, 16, 16, hct, hct, hct, hct])
+            b = rn.Batch([tuple(dev(a) for a in p) for p in small])
+            b.run(2, 12)
+            rel, st = b.results()
+            assert all(x == rn.OK for x in st)
+            outs.append([(P["W"].clone(), P["H"].clone()) for P in b.problems])
+        for other in outs[1:]:
+            for (w0, h0), (w1, h1) in zip(outs[0], other):
+                assert torch.equal(w0, w1) and torch.equal(h0, h1)
+    finally:
+        rn.batch_tuning(saved)
+
+
+def test_batch_tuning_table_is_checked():
+    saved = rn.batch_tuning()
+    with pytest.raises(rn.RnmfError):
+        rn.batch_tuning([4, 8, 16, 16, 256, 256, 128, 100])
+    assert rn.batch_tuning() == saved
+
+
 def test_batch_autotune_picks_valid_tilings(small):
     b = rn.Batch([tuple(dev(a) for a in p) for p in small], autotune=True, q=2)
-    assert len(b.tiling) == 4
+    assert len(b.tiling) == 8
     widest = [0, 0, 0, 0]
     for (_, _, _, l) in SHAPES:
         c = 0 if l <= 16 else (1 if l <= 32 else (2 if l <= 48 else 3))
         widest[c] = max(widest[c], l)
-    for tc, lw in zip(b.tiling, widest):
+    for tc, lw in zip(b.tiling[:4], widest):
         assert tc in (4, 8, 16) and 4 * tc >= lw   # each class's tiling covers its widest sketch
+    for hct, lw in zip(b.tiling[4:], widest):
+        # H-phase tile: B^T tile of hct x (l + 1) floats within the LDS scratch
+        assert hct in (64, 128, 256) and (lw == 0 or hct * (lw + 1) <= 12672)
+    assert rn.batch_tuning() == b.tiling
     b.run(2, 30)
     rel, st = b.results()
     assert all(x == rn.OK for x in st)
