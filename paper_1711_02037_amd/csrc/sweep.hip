@@ -2,7 +2,9 @@
 // cooperative kernel: every sweep of the call runs inside a single launch.
 //
 // Work split (G workgroups, one per compute unit, arranged as GR x GC):
-//   - rows of Q and W are split into G slabs (the Q slab lives in LDS);
+//   - rows of Q and W are split into G slabs (the Q slab lives in registers,
+//     or in LDS when it is too tall or wide for them; the W rows live in LDS,
+//     or stay in global memory when they do not fit there);
 //   - columns of B and H are split into G slabs;
 //   - the small replicated state (W~: l x k, T: l x k, V and S: k x k) is held
 //     by every workgroup in LDS.
@@ -21,12 +23,14 @@
 //
 // Device-wide all-reduce: partials are written as 64-bit words (32-bit payload
 // | 32-bit epoch) with agent-scope relaxed atomic stores, so every word carries
-// its own readiness and no separate barrier is needed.  Workgroup (i, j) first
-// adds the partials of its row i, publishes the row sum, then adds the row
-// sums of its column j.  Every sum runs in a fixed order, so every workgroup
-// obtains bit-identical results and the kernel is deterministic.  Large
-// vectors (T, V, S) use reduce-scatter by slice, a column reduce, then an
-// all-gather.  Every wait is bounded: past the spin limit the kernel records
+// its own readiness and no separate barrier is needed.  The per-column
+// l-vector of the W phase goes through block owners (one workgroup sums each
+// 16-word block over all partial slots and publishes copies of the totals);
+// large vectors (T, V, S) through slice owners (reduce-scatter, then every
+// workgroup reads all totals); the projected-gradient sum through a row, then
+// column, two-hop scheme.  Every sum runs in a fixed order, so every
+// workgroup obtains bit-identical results and the kernel is deterministic.
+// Every wait is bounded: past the spin limit the kernel records
 // RNMF_ERR_DEVICE_TIMEOUT and all workgroups leave.
 #include "rnmf_common.h"
 
