@@ -440,9 +440,11 @@ int relerr_parts(int64_t m, int64_t n) { return ceil_div(m, 64) * ceil_div(n, 64
 hipError_t launch_relerr(const void* X, int xt, int dt, int64_t m, int64_t n, int64_t ldx,
                          const void* W, const void* H, int k, double* part, int nparts_max,
                          double* out, hipStream_t s) {
-  if (dt == 1 && xt != 2 && k <= 64) {
-    // one workgroup per CU over balanced 16-row tiles, at most 32 tiles each
-    const int64_t tiles = ceil_div(m, 16);
+  // one workgroup per CU over balanced 16-row tiles, at most 32 tiles each;
+  // a short matrix (the compressed l x n error) would leave a few workgroups
+  // streaming whole rows, so it takes the 64 x 64 tiled kernel instead
+  const int64_t tiles = ceil_div(m, 16);
+  if (dt == 1 && xt != 2 && k <= 64 && tiles >= 128) {
     int64_t g = 256;
     if (g > tiles) g = tiles;
     if (g < ceil_div(tiles, 32)) g = ceil_div(tiles, 32);
