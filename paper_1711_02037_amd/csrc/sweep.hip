@@ -1020,10 +1020,16 @@ __global__ __launch_bounds__(NTH) void sweep_kernel(SweepArgs<T> a) {
     const int ncopy_x = a.G < 16 ? a.G : 16;                 // copies of the totals
     int jprev = -1;  // column whose S partials await their reduction
     const T aw = (T)a.aw, bw = (T)a.bw;
+    // columns with a positive scale V_jj + alpha_w, as a wave-uniform bit set
+    // (every wave reads the same diagonal), so that finding the next column
+    // costs no LDS round trip inside the column loop
+    const unsigned long long vmask =
+        __builtin_amdgcn_ballot_w64(lane < k && Vm[(lane < k ? lane : 0) * (k + 1)] + aw > (T)0);
     auto next_col = [&](int j) __attribute__((always_inline)) -> int {
-      int q = j + 1;
-      while (q < k && !(Vm[q * k + q] + aw > (T)0)) ++q;
-      return q;
+      const int q0 = j + 1;
+      if (q0 >= k) return k;
+      const unsigned long long rest = vmask >> q0;
+      return rest ? q0 + __builtin_ctzll(rest) : k;
     };
     // entries of the update vector past l stay zero, so the lift reads all
     // CQ entries of its column group without a per-entry predicate
