@@ -380,8 +380,10 @@ typedef struct rnmf_problem {
   float* H;            /* out: k x n                                          */
   float* Q;            /* out: m x l orthonormal basis                        */
   float* B;            /* out: l x n compressed matrix Q^T X                  */
-  float* Z;            /* scratch: n l + k m floats (B^T, n x l, then W held
-                          by columns, k x m, during the sweeps)              */
+  float* Z;            /* scratch: n l + k ceil(m / 32) 32 + 32 floats (B^T,
+                          n x l, then W held by columns during the sweeps:
+                          k columns of m rounded up to 32 floats, from the
+                          next 128-byte boundary)                           */
   int64_t m, n, ldx;
   int32_t k, l;
   int32_t prec;        /* RNMF_PREC_F32, or RNMF_PREC_BF16: the passes over X

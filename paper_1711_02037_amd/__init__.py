@@ -647,7 +647,8 @@ class Batch:
                        H=torch.empty((k, n), dtype=torch.float32, device=dev),
                        Q=torch.empty((m, l), dtype=torch.float32, device=dev),
                        B=torch.empty((l, n), dtype=torch.float32, device=dev),
-                       Z=torch.empty(n * l + k * m, dtype=torch.float32, device=dev))
+                       Z=torch.empty(n * l + k * ((m + 31) // 32) * 32 + 32, dtype=torch.float32,
+                                     device=dev))
             self.problems.append(out)
             d = descs[i]
             for key in ("X", "Omega", "W0", "H0", "W", "H", "Q", "B", "Z"):

@@ -883,8 +883,9 @@ __device__ __noinline__ unsigned cholqr2(float* Y, int64_t rows, int l, int tc, 
 }
 
 // S = W^T W (k x k, FP64 sums) into Ss (pitch BKM); W is held by columns
-// (Wc: k x m, column c at Wc + c m).
-__device__ __noinline__ void gram_w(const float* __restrict__ Wc, int64_t m, int k, float* Ss, float* scr) {
+// (Wc: k x m, column c at Wc + c ldw).
+__device__ __noinline__ void gram_w(const float* __restrict__ Wc, int64_t m, int64_t ldw, int k, float* Ss,
+                                    float* scr) {
   const int t = threadIdx.x;
   float* Wsh = scr;  // GT x (BKM + 1)
   const int gi = t % 16, gj = t / 16;
@@ -902,7 +903,7 @@ __device__ __noinline__ void gram_w(const float* __restrict__ Wc, int64_t m, int
       const int e = t + u * BT;
       const int c = e / GT;
       const int64_t r = r0 + (e % GT);
-      wv[u] = W[(int64_t)(c < k ? c : k - 1) * m + (r < m ? r : m - 1)];
+      wv[u] = W[(int64_t)(c < k ? c : k - 1) * ldw + (r < m ? r : m - 1)];
     }
   };
   fetch(0);
@@ -945,8 +946,8 @@ __device__ __noinline__ void gram_w(const float* __restrict__ Wc, int64_t m, int
 
 // W (m x k, rows) <-> Wc (k x m, columns), in tiles of GT rows through LDS so
 // that both sides are read and written along contiguous runs.
-__device__ __noinline__ void w_to_columns(float* __restrict__ Wc, const float* __restrict__ W, int64_t m, int k,
-                                          float* scr) {
+__device__ __noinline__ void w_to_columns(float* __restrict__ Wc, const float* __restrict__ W, int64_t m,
+                                          int64_t ldw, int k, float* scr) {
   const int t = threadIdx.x;
   float* Wsh = scr;  // GT x (BKM + 1)
   gf* D = GW(Wc);
@@ -955,13 +956,13 @@ __device__ __noinline__ void w_to_columns(float* __restrict__ Wc, const float* _
     lds_sync();
     for (int e = t; e < GT * k; e += BT) {
       const int c = e / GT, r = e % GT;
-      if (r0 + r < m) D[(int64_t)c * m + r0 + r] = Wsh[r * (BKM + 1) + c];
+      if (r0 + r < m) D[(int64_t)c * ldw + r0 + r] = Wsh[r * (BKM + 1) + c];
     }
     lds_sync();
   }
 }
-__device__ __noinline__ void w_from_columns(float* __restrict__ W, const float* __restrict__ Wc, int64_t m, int k,
-                                            float* scr) {
+__device__ __noinline__ void w_from_columns(float* __restrict__ W, const float* __restrict__ Wc, int64_t m,
+                                            int64_t ldw, int k, float* scr) {
   const int t = threadIdx.x;
   float* Wsh = scr;  // GT x (BKM + 1)
   gcf* S = G(Wc);
@@ -969,7 +970,7 @@ __device__ __noinline__ void w_from_columns(float* __restrict__ W, const float* 
   for (int64_t r0 = 0; r0 < m; r0 += GT) {
     for (int e = t; e < GT * k; e += BT) {
       const int c = e / GT, r = e % GT;
-      if (r0 + r < m) Wsh[r * (BKM + 1) + c] = S[(int64_t)c * m + r0 + r];
+      if (r0 + r < m) Wsh[r * (BKM + 1) + c] = S[(int64_t)c * ldw + r0 + r];
     }
     lds_sync();
     const int64_t left = m - r0;
@@ -1210,10 +1211,13 @@ __device__ __noinline__ void tv_phase(const float* __restrict__ Bt, const float*
 // registers.  Per column the 32 rows of a half are summed by lane
 // butterflies, then the four wavefronts in FP64 through LDS, in a fixed
 // order.  Reads past the chunk return zero (buffer loads) or land in the
-// tile's slack and are weighted by zero.  W is held by columns (Wc: k x m), so
-// the 32 rows of a chunk store one contiguous run of column j.
+// tile's slack and are weighted by zero.  W is held by columns (Wc: k x m,
+// columns ldw floats apart, a multiple of 32 from a 128-byte boundary) and the
+// wavefronts' row ranges start on multiples of 32, so the 32 rows of a chunk
+// store exactly one 128-byte line of column j.
 template <int NL>  // coalesced loads per lane per chunk: NL >= ceil(32 l / 64)
-__device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ Wc, int64_t m, int l, int k,
+__device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __restrict__ Wc, int64_t m, int64_t ldw,
+                                       int l, int k,
                                        float* Wts, const float* Ts, const float* Vs, float* vec, double* red,
                                        float* scr) {
   constexpr int CR = 32;             // rows per chunk
@@ -1226,7 +1230,8 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
   const int c0 = h ? L2 : 0, nh = h ? l - L2 : L2;
   const int P = l | 1;               // odd pitch: rows of a half on distinct banks
   float* Qw = scr + wave * WT;
-  const int64_t rw0 = m * wave / 4, rw1 = m * (wave + 1) / 4;
+  const int64_t rw0 = wave == 0 ? 0 : ((m * wave / 4) & ~(int64_t)(CR - 1));
+  const int64_t rw1 = wave == 3 ? m : ((m * (wave + 1) / 4) & ~(int64_t)(CR - 1));
   const int nch = (int)((rw1 - rw0 + CR - 1) / CR);
   gf* Wg = GW(Wc);
   // Q through a buffer resource (m l floats): a position past the end reads 0.
@@ -1298,7 +1303,7 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
       // the same sum on both halves: half 0's part first
       const float tot = h ? other + part : part + other;
       const float w = r < rw1 ? clipf(tot) : 0.f;
-      if (h == 0 && r < rw1) Wg[(int64_t)j * m + r] = w;
+      if (h == 0 && r < rw1) Wg[(int64_t)j * ldw + r] = w;
 #pragma unroll
       for (int c = 0; c < NH; ++c) acc[c] = fmaf(q[c], w, acc[c]);
     }
@@ -1318,12 +1323,12 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
   }
   __syncthreads();  // W is read next by other threads of the workgroup
 }
-__device__ __forceinline__ void w_phase(const float* Q, float* Wc, int64_t m, int l, int k, float* Wts, const float* Ts,
-                                        const float* Vs, float* vec, double* red, float* scr) {
-  if (l <= 16) w_phase_t<8>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else if (l <= 32) w_phase_t<16>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else if (l <= 48) w_phase_t<24>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
-  else w_phase_t<32>(Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
+__device__ __forceinline__ void w_phase(const float* Q, float* Wc, int64_t m, int64_t ldw, int l, int k, float* Wts,
+                                        const float* Ts, const float* Vs, float* vec, double* red, float* scr) {
+  if (l <= 16) w_phase_t<8>(Q, Wc, m, ldw, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 32) w_phase_t<16>(Q, Wc, m, ldw, l, k, Wts, Ts, Vs, vec, red, scr);
+  else if (l <= 48) w_phase_t<24>(Q, Wc, m, ldw, l, k, Wts, Ts, Vs, vec, red, scr);
+  else w_phase_t<32>(Q, Wc, m, ldw, l, k, Wts, Ts, Vs, vec, red, scr);
 }
 
 // ||X - W H||_F^2 and ||X||_F^2 (FP64 sums, fixed order) for thread 0.
@@ -1434,22 +1439,24 @@ __global__ __launch_bounds__(BT, 2) void batch_kernel(const BDesc* __restrict__ 
       if (bf) xtq_pass_bf16(p.X, ldx, m, n, p.Q, l, p.Z, p.B, scr);
       else xtq_pass(p.X, ldx, m, n, p.Q, l, p.Z, p.B, tc, scr);
       // initialisation (step 10)
-      // W is held by columns during the sweeps (Wc: k x m after B^T in Z), so
-      // the W phase stores each column as contiguous runs
-      float* Wc = p.Z + n * (int64_t)l;
+      // W is held by columns during the sweeps (Wc: k x m after B^T in Z, from
+      // the next 128-byte boundary, columns ldw = m rounded up to 32 floats
+      // apart), so the W phase stores each column as whole cache lines
+      float* Wc = (float*)(((uintptr_t)(p.Z + n * (int64_t)l) + 127) & ~(uintptr_t)127);
+      const int64_t ldw = (m + 31) & ~(int64_t)31;
       for (int e = t; e < OFF_VEC; e += BT) lds[e] = 0.f;  // W~, T, V, S zero beyond k
-      w_to_columns(Wc, p.W0, m, k, scr);
+      w_to_columns(Wc, p.W0, m, ldw, k, scr);
       copy_f(p.H, p.H0, (int64_t)k * n);
       __syncthreads();
       init_wt(p.Q, p.W0, m, l, k, Wts, scr);
       // sweeps (steps 11-22): H rows, then W columns
       for (int s = 0; s < nsweeps; ++s) {
-        gram_w(Wc, m, k, Ss, scr);
+        gram_w(Wc, m, ldw, k, Ss, scr);
         h_phase(p.Z, p.H, n, l, k, Wts, Ss, red, scr, d.hct);
         tv_phase(p.Z, p.H, n, l, k, Ts, Vs, scr);
-        w_phase(p.Q, Wc, m, l, k, Wts, Ts, Vs, vec, red, scr);
+        w_phase(p.Q, Wc, m, ldw, l, k, Wts, Ts, Vs, vec, red, scr);
       }
-      w_from_columns(p.W, Wc, m, k, scr);
+      w_from_columns(p.W, Wc, m, ldw, k, scr);
       __syncthreads();
       double out[2];
       rel_err(p.X, ldx, m, n, p.W, p.H, k, scr, red, out);
