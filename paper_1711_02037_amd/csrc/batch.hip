@@ -1243,6 +1243,12 @@ __device__ __noinline__ void w_phase_t(const float* __restrict__ Q, float* __res
   const int qbytes = __builtin_amdgcn_readfirstlane((int)(m * l * (int64_t)sizeof(float)));
   const __amdgpu_buffer_rsrc_t qrs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(uintptr_t)(((uint64_t)qhi << 32) | qlo), (short)0, qbytes, 0x00020000);
+  // The lift reads every entry of a row's half up to NH columns, so entries
+  // that no chunk writes (a row's padding, the slack) are multiplied by zero
+  // weights: they must hold finite values, not what an earlier kernel left in
+  // LDS.  The wavefront clears its own tile once (its LDS operations complete
+  // in order, so no barrier is needed before the first chunk lands).
+  for (int e = lane; e < WT; e += 64) Qw[e] = 0.f;
   // LDS position of this lane's element e = lane + 64 s of a chunk (row e / l,
   // column e % l), the same for every chunk; elements past the chunk go to
   // the tile's slack
