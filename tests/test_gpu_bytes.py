@@ -67,7 +67,10 @@ def special_floats():
     return np.array(bits, dtype=np.uint32).view(np.float32)
 
 
-@pytest.mark.parametrize("m,n,ld", [(1, 25, 25), (7, 1003, 1003), (64, 1031, 1040), (129, 4096, 4099)])
+# ragged rows, strided rows, and whole 8-element groups (packed, strided and
+# a tall-wide case)
+@pytest.mark.parametrize("m,n,ld", [(1, 25, 25), (7, 1003, 1003), (64, 1031, 1040), (129, 4096, 4099),
+                                    (100, 1024, 1024), (33, 512, 520), (2100, 8192, 8192)])
 def test_bf16_cast_is_round_to_nearest_even_bit_for_bit(m, n, ld):
     rng = np.random.default_rng(m * 100003 + n)
     bits = rng.integers(0, 2**32, size=(m, ld), dtype=np.uint64).astype(np.uint32)

@@ -368,6 +368,10 @@ def test_negative_and_nonfinite_input_are_reported():
     with pytest.raises(rn.RnmfError) as e:
         rn.factorize(dev(Xf), 4, 4, 1, max_iter=2, precision="bf16")
     assert e.value.status == rn.ERR_NONFINITE
+    # the BF16 form scans X while it makes the bfloat16 copy
+    with pytest.raises(rn.RnmfError) as e:
+        rn.factorize(dev(Xn), 4, 4, 1, max_iter=2, precision="bf16")
+    assert e.value.status == rn.ERR_NEGATIVE_INPUT
 
 
 def test_exactly_low_rank_input_gives_a_valid_basis():
