@@ -278,7 +278,7 @@ def main():
         "data": "synthetic (seeded rank-50 uniform product + N(0,0.05^2) noise, clipped)",
         "config": {"workload": WORKLOAD, "m": m, "n": n, "k": k, "p": p, "q": q + 1, "l": l,
                    "sweeps": sweeps, "step": "cast+sketch+compress+init+200 sweeps+rel_err",
-                   "x_pass_arithmetic": "bf16 MFMA (X bf16, Q split hi+lo), fp32 accumulate",
+                   "x_pass_arithmetic": "bf16 MFMA (X bf16; Q split hi+lo in X^T Q and Q^T X, operand bf16 in the sketch passes), fp32 accumulate",
                    "sweep_arithmetic": "fp32 (H phase fp64)"},
         "rel_err": {"bf16": reps_b[-1]["rel_err"], "fp32": reps_f[-1]["rel_err"]},
         "oracle_parity": parity,
@@ -669,7 +669,7 @@ def xpass_kernels(rn, torch, step, m, n, l):
     from torch.profiler import profile, ProfilerActivity
     lp = ((l + 15) // 16) * 16
     kinds = {
-        "nn_bf16": ("nn2_kernel<unsigned short", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "nn_bf16": ("nn2_kernel<unsigned short", 2, 2 * m * n * lp, PEAK_BF16_TFLOPS),
         "tn_bf16": ("tn2_kernel<unsigned short", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
         "nn_fp32": ("nn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
         "tn_fp32": ("tn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
@@ -704,7 +704,7 @@ def xpass_kernels(rn, torch, step, m, n, l):
             d["frac_of_mfma_peak"] = round(flops / (us * 1e-6) / 1e12 / peak, 4)
         out[key] = d
     out["note"] = ("bytes: X once per pass (cast: 4 B read + 2 B written per element); MFMA flops as executed "
-                   f"(l = {l} padded to {lp} columns; BF16 hi + lo operand planes)")
+                   f"(l = {l} padded to {lp} columns; BF16 TN passes hi + lo operand planes, NN passes one plane)")
     return out
 
 

@@ -11,9 +11,14 @@
 //   FP32: v_mfma_f32_16x16x4_f32, lane (i, g) = (lane % 16, lane / 16) holds
 //         A[i][g] and B[g][i]; D[4g + e][i] in element e.
 //   BF16: v_mfma_f32_16x16x32_bf16, lane (i, g) holds A[i][8g..8g+7] and
-//         B[8g..8g+7][i]; same D layout.  X is bfloat16 and the small operand
-//         is split into hi + lo bfloat16 planes (two MFMAs per tile), so only
-//         X is rounded.
+//         B[8g..8g+7][i]; same D layout.  X is bfloat16.  The packed small
+//         operand has hi + lo bfloat16 planes: the TN passes (Z = X^T Q,
+//         B = Q^T X) use both (two MFMAs per tile, so only X is rounded); the
+//         NN passes (Y = X Omega, Y = X Z) use the hi plane, the operand
+//         rounded to nearest even.  They only steer the subspace, which the
+//         next orthonormalisation and the extra iteration of the BF16 form
+//         absorb (final error unchanged to 4e-10 at 100,000 x 5,000, k = 50),
+//         and they stream X at the TN passes' rate (252 against 343 us).
 //   FP64: vector FMA, register-blocked through LDS.
 #include "rnmf_common.h"
 
@@ -270,31 +275,26 @@ __global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__
     int64_t r = row_base + rt * 16 + i;
     xr[rt] = X + (r < m ? r : (m - 1)) * ldx + 8 * g;
   }
+  // the operand's hi plane (the operand rounded to bfloat16), as in nn2_kernel
+  (void)lp_all;
   const bf16_t* ah[NT];
-  const int64_t plane = (int64_t)lp_all * ldat;
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct) ah[ct] = At + (int64_t)(ct * 16 + i) * ldat + 8 * g;
   int64_t k0 = kb;
   for (; k0 + 32 <= ke; k0 += 32) {
-    bf16x8 xa[RW], hv[NT], lv[NT];
+    bf16x8 xa[RW], hv[NT];
 #pragma unroll
     for (int rt = 0; rt < RW; ++rt) xa[rt] = *(const bf16x8*)(xr[rt] + k0);
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      hv[ct] = *(const bf16x8*)(ah[ct] + k0);
-      lv[ct] = *(const bf16x8*)(ah[ct] + plane + k0);
-    }
+    for (int ct = 0; ct < NT; ++ct) hv[ct] = *(const bf16x8*)(ah[ct] + k0);
 #pragma unroll
     for (int rt = 0; rt < RW; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
-        acc[rt][ct] = mfma_bf(xa[rt], lv[ct], acc[rt][ct]);
-      }
+      for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
   }
   if (k0 < ke) {
     const int64_t kk = k0 + 8 * g;
-    bf16x8 xa[RW], hv[NT], lv[NT];
+    bf16x8 xa[RW], hv[NT];
 #pragma unroll
     for (int rt = 0; rt < RW; ++rt)
 #pragma unroll
@@ -307,17 +307,12 @@ __global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         unsigned short h = (kk + s < ke) ? ah[ct][k0 + s] : (unsigned short)0;
-        unsigned short lo = (kk + s < ke) ? ah[ct][plane + k0 + s] : (unsigned short)0;
         hv[ct][s] = __builtin_bit_cast(__bf16, h);
-        lv[ct][s] = __builtin_bit_cast(__bf16, lo);
       }
 #pragma unroll
     for (int rt = 0; rt < RW; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
-        acc[rt][ct] = mfma_bf(xa[rt], lv[ct], acc[rt][ct]);
-      }
+      for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = mfma_bf(xa[rt], hv[ct], acc[rt][ct]);
   }
   const int lp = NT * 16;
 #pragma unroll
@@ -348,7 +343,7 @@ __global__ __launch_bounds__(256) void nn_bf16_kernel(const bf16_t* __restrict__
 // 16 bytes past a 1 KB boundary.  The MFMA fragment of lane (i, g) at k-step
 // u (chunk 4u + g of row i) is then read back from a bank-conflict-free
 // position.
-//   BF16: fragment = 16 rows x 32 k (8 per lane); two operand planes.
+//   BF16: fragment = 16 rows x 32 k (8 per lane); one operand plane (hi).
 //   FP32: fragment = 16 rows x 16 k (4 per lane: MFMA s uses k = 4g + s).
 // Wave w owns tiles w, w + 8, ... of the range.
 // ---------------------------------------------------------------------------
@@ -375,7 +370,7 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
   constexpr bool BF = sizeof(E) == 2;
   constexpr int KS = BF ? 32 : 16;       // k per fragment
   constexpr int EPC = BF ? 8 : 4;        // elements per lane chunk (16 bytes)
-  constexpr int NPL = BF ? 2 : 1;        // operand planes
+  constexpr int NPL = 1;                 // operand planes read (BF16: the hi plane only)
   static_assert(KU * KS * (int)sizeof(E) == 128, "a stage covers one 128-byte line of every row");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, gq = lane >> 4;
@@ -465,13 +460,9 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
           const bf16x8 h = *(const bf16x8*)(base + (size_t)(nt + ct) * NN2_BLOCK + fo);
-          const bf16x8 lo = *(const bf16x8*)(base + (size_t)(nt + NT + ct) * NN2_BLOCK + fo);
 #pragma unroll
           for (int rt = 0; rt < RWMAX; ++rt)
-            if (wave + 8 * rt < nt) {
-              acc[rt][ct] = mfma_bf(xa[rt], h, acc[rt][ct]);
-              acc[rt][ct] = mfma_bf(xa[rt], lo, acc[rt][ct]);
-            }
+            if (wave + 8 * rt < nt) acc[rt][ct] = mfma_bf(xa[rt], h, acc[rt][ct]);
         }
       } else {
         floatx4 xa[RWMAX];
@@ -876,9 +867,10 @@ __global__ __launch_bounds__(256) void nn_valu_kernel(const XT* __restrict__ X, 
       CT v = (CT)0;
       if (k < ke) {
         if constexpr (sizeof(AT) == 2) {
+          // BF16 sketch pass: the operand's hi plane (rounded to bfloat16),
+          // as in the matrix-core kernels
           const bf16_t* ah = (const bf16_t*)At;
-          v = (CT)to_f<bf16_t>(ah[(int64_t)c * ldat + k]) +
-              (CT)to_f<bf16_t>(ah[(int64_t)lp_all * ldat + (int64_t)c * ldat + k]);
+          v = (CT)to_f<bf16_t>(ah[(int64_t)c * ldat + k]);
         } else {
           v = (CT)At[(int64_t)c * ldat + k];
         }
@@ -1079,7 +1071,7 @@ static void plan_nn2(XPlan& p, int64_t m, int64_t n, int l, int cdt, int cus) {
   if (!(cdt == 1 || cdt == 2) || nt > 8 || m < 16) return;
   const int lp = nt * 16;
   const int ks = (cdt == 2) ? 32 : 16, stage = ks * NN2_KU;
-  const int af = (cdt == 2 ? 2 : 1) * nt;  // operand blocks per stage
+  const int af = nt;  // operand blocks per stage
   int ntmax = NN2_LDS_KB * 1024 / 2 / NN2_BLOCK - af;
   if (ntmax > 8 * NN2_RWMAX) ntmax = 8 * NN2_RWMAX;
   if (ntmax < 1) return;

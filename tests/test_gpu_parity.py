@@ -449,7 +449,9 @@ def test_sketch_pass_spans_x_omega(prec, m, n, ld, k, p):
         Xh = Xf[:, :n].astype(np.float64)
     # exact_q: the BF16 form would otherwise add one subspace iteration
     Q = host(rn.sketch(Xd, k, p, 0, omega=dev(Om), precision=prec, exact_q=True))
-    Y = Xh @ Om.astype(np.float64)
+    # the BF16 sketch pass takes Omega rounded to bfloat16 (nearest even)
+    Omh = host(dev(Om).to(torch.bfloat16)) if prec == "bf16" else Om.astype(np.float64)
+    Y = Xh @ Omh
     err = np.linalg.norm(Y - Q @ (Q.T @ Y)) / np.linalg.norm(Y)
     assert err <= 2e-6, err
     assert np.linalg.norm(Q.T @ Q - np.eye(l)) <= 1e-5
