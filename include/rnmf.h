@@ -66,10 +66,11 @@ typedef enum rnmf_dtype { RNMF_F64 = 0, RNMF_F32 = 1, RNMF_BF16 = 2 } rnmf_dtype
 
 /* Arithmetic of the passes over X.  F64 and F32 compute in that type.  BF16
  * stores X as bfloat16 (cast once, round to nearest even) and runs the X
- * passes on bf16 matrix cores with FP32 accumulation.  In the passes
- * Z = X^T Q and B = Q^T X the small operand Q is split into two bfloat16
- * terms, so only X is rounded; in the sketch passes Y = X Omega and Y = X Z,
- * which only steer the subspace, the operand is rounded to bfloat16 too.
+ * passes on bf16 matrix cores with FP32 accumulation.  In the compression
+ * B = Q^T X the small operand Q is split into two bfloat16 terms, so only X
+ * is rounded; in the passes that only steer the subspace (Y = X Omega,
+ * Z = X^T Q and Y = X Z of the subspace iterations) the operand is rounded
+ * to bfloat16 too.
  * The orthonormalisation (Gram and Cholesky in FP64), the sweeps (FP32) and
  * the final error (FP64 accumulation) are the same as in F32. */
 typedef enum rnmf_prec { RNMF_PREC_F64 = 0, RNMF_PREC_F32 = 1, RNMF_PREC_BF16 = 2 } rnmf_prec;

@@ -373,8 +373,10 @@ rnmf_status run_sketch(const void* Xc, int64_t m, int64_t n, int64_t ldx, const 
   for (int it = 0; it < q; ++it) {
     // Q = qr(Y); Z = X^T Q; Q = qr(Z); Y = X Q
     if ((r = cholqr(b.y, m, l, b.y2, Q, b.qy, md, h.ctl, allow_shift, h.status, d, 1)) != RNMF_OK) return r;
-    HIPCHK(launch_pack_t(b.y2, md.dt, m, l, lp, b.ldp, b.at, md.cdt, s));
-    HIPCHK(launch_tn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.z, 0, b.part, b.tn, s));
+    // the half-step Z = X^T Q only steers the subspace: in the BF16 form its
+    // operand is Q rounded to bfloat16 (one plane), as in the sketch passes
+    HIPCHK(launch_pack_t(b.y2, md.dt, m, l, lp, b.ldp, b.at, md.cdt, s, 1));
+    HIPCHK(launch_tn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.z, 0, b.part, b.tn, s, 1));
     if ((r = cholqr(b.z, n, l, b.z2, b.z3, b.qz, md, h.ctl, allow_shift, h.status, d, 1)) != RNMF_OK) return r;
     HIPCHK(launch_pack_t(b.z2, md.dt, n, l, lp, b.ldp, b.at, md.cdt, s));
     HIPCHK(launch_nn(Xc, md.cdt, m, n, ldx, b.at, b.ldp, l, b.y, b.part, b.nn, h.status, 0, s));

@@ -78,9 +78,10 @@ int relerr_parts(int64_t m, int64_t n);
 // xpass.hip: passes over X.
 // Small operand packing: src (rows x cols, ld = cols, dtype dt) -> dst, the
 // transpose (lp x ldp, ldp >= rows) in the compute dtype; rows i >= cols are
-// zero.  For bf16 the destination holds hi then lo planes.
+// zero.  For bf16 the destination holds hi then lo planes (lo zero when
+// hi_only: the operand rounded to bfloat16).
 hipError_t launch_pack_t(const void* src, int dt, int64_t rows, int cols, int lp, int64_t ldp,
-                         void* dst, int cdt, hipStream_t s);
+                         void* dst, int cdt, hipStream_t s, int hi_only = 0);
 // Y (m x l) = X (m x n) * A, with At = A^T packed (lp x ldat).  Output in dt
 // (float or double).  Split-K partials in `part` (float or double) if needed.
 struct XPlan {
@@ -97,10 +98,12 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
                      int64_t ldat, int l, void* Y, void* part, const XPlan& pl,
                      unsigned* status, int check, hipStream_t s,
                      const unsigned* skip = nullptr);
-// Z = X^T Q: writes Z (n x l) if !transposed, else Z^T (l x n).
+// Z = X^T Q: writes Z (n x l) if !transposed, else Z^T (l x n).  bf16 with
+// one_plane: the streamed kernel reads only the hi plane of Qt (whose lo
+// plane the other kernels then read as zeros, see launch_pack_t's hi_only).
 hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt,
                      int64_t ldqt, int l, void* Z, int transposed, void* part,
-                     const XPlan& pl, hipStream_t s);
+                     const XPlan& pl, hipStream_t s, int one_plane = 0);
 
 // qr.hip: Cholesky QR pass pieces.
 int gram_splits(int64_t rows, int cus);

@@ -12,13 +12,14 @@
 //         A[i][g] and B[g][i]; D[4g + e][i] in element e.
 //   BF16: v_mfma_f32_16x16x32_bf16, lane (i, g) holds A[i][8g..8g+7] and
 //         B[8g..8g+7][i]; same D layout.  X is bfloat16.  The packed small
-//         operand has hi + lo bfloat16 planes: the TN passes (Z = X^T Q,
-//         B = Q^T X) use both (two MFMAs per tile, so only X is rounded); the
-//         NN passes (Y = X Omega, Y = X Z) use the hi plane, the operand
-//         rounded to nearest even.  They only steer the subspace, which the
-//         next orthonormalisation and the extra iteration of the BF16 form
-//         absorb (final error unchanged to 4e-10 at 100,000 x 5,000, k = 50),
-//         and they stream X at the TN passes' rate (252 against 343 us).
+//         operand has hi + lo bfloat16 planes: the compression B = Q^T X
+//         uses both (two MFMAs per tile, so only X is rounded); the passes
+//         inside the subspace iteration (Y = X Omega, Z = X^T Q, Y = X Z) use
+//         the hi plane, the operand rounded to nearest even.  They only steer
+//         the subspace, which the next orthonormalisation and the extra
+//         iteration of the BF16 form absorb (final error unchanged to 2e-6
+//         relative at 100,000 x 5,000, k = 50), with half the operand blocks
+//         and products (NN 252 against 343 us, TN 232 against 247 us).
 //   FP64: vector FMA, register-blocked through LDS.
 #include "rnmf_common.h"
 
@@ -102,7 +103,8 @@ __global__ __launch_bounds__(256) void pack_t_kernel(const ST* __restrict__ src,
 
 template <typename ST>
 __global__ __launch_bounds__(256) void pack_t_bf16_kernel(const ST* __restrict__ src, int64_t rows, int cols,
-                                                          int lp, int64_t ldp, unsigned short* __restrict__ dst) {
+                                                          int lp, int64_t ldp, unsigned short* __restrict__ dst,
+                                                          int hi_only) {
   __shared__ float tile[32][33];
   const int64_t r0 = (int64_t)blockIdx.x * 32;
   const int i0 = blockIdx.y * 32;
@@ -122,21 +124,21 @@ __global__ __launch_bounds__(256) void pack_t_bf16_kernel(const ST* __restrict__
       unsigned short h = bf16_rne(x);
       float hf = __uint_as_float(((unsigned)h) << 16);
       dst[(int64_t)i * ldp + r] = h;
-      lo[(int64_t)i * ldp + r] = bf16_rne(x - hf);
+      lo[(int64_t)i * ldp + r] = hi_only ? (unsigned short)0 : bf16_rne(x - hf);
     }
   }
 }
 
 hipError_t launch_pack_t(const void* src, int dt, int64_t rows, int cols, int lp, int64_t ldp,
-                         void* dst, int cdt, hipStream_t s) {
+                         void* dst, int cdt, hipStream_t s, int hi_only) {
   dim3 grid((unsigned)ceil_div(ldp, 32), (unsigned)ceil_div(lp, 32));
   if (cdt == 2) {
     if (dt == 0)
       hipLaunchKernelGGL(pack_t_bf16_kernel<double>, grid, dim3(256), 0, s, (const double*)src, rows,
-                         cols, lp, ldp, (unsigned short*)dst);
+                         cols, lp, ldp, (unsigned short*)dst, hi_only);
     else
       hipLaunchKernelGGL(pack_t_bf16_kernel<float>, grid, dim3(256), 0, s, (const float*)src, rows,
-                         cols, lp, ldp, (unsigned short*)dst);
+                         cols, lp, ldp, (unsigned short*)dst, hi_only);
   } else if (cdt == 1) {
     if (dt == 0)
       hipLaunchKernelGGL((pack_t_kernel<double, float>), grid, dim3(256), 0, s, (const double*)src,
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(512) void nn2_kernel(const E* __restrict__ X, int64
 //   FP32: two MFMA groups of 16 rows; the lane reads rows 4g + s (s < 4) x 4
 //         columns with 16-byte LDS reads; each value is one MFMA operand.
 // ---------------------------------------------------------------------------
-template <typename E, int NT>
+template <typename E, int NT, int NPL>  // NPL: operand planes read (BF16: 2 = hi + lo, 1 = hi)
 __global__ __launch_bounds__(512) void tn2_kernel(const E* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                   const E* __restrict__ Qt, int64_t ldqt, int lp_all,
                                                   float* __restrict__ part, int64_t mlen) {
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(512) void tn2_kernel(const E* __restrict__ X, int64
   constexpr int RB = 512 * (int)sizeof(E);     // bytes of one row of the block
   constexpr int PITCH = RB + 16;               // LDS row pitch
   constexpr int XI = SR * (RB / 1024);         // X load instructions per stage
-  constexpr int QF = (BF ? 2 : 1) * NT * (BF ? 1 : 2);  // Q fragments per stage (1 KB each)
+  constexpr int QF = (BF ? NPL : 1) * NT * (BF ? 1 : 2);  // Q fragments per stage (1 KB each)
   constexpr int FI = XI + QF;
   constexpr int SLOT = SR * PITCH + QF * 1024;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -625,11 +627,16 @@ __global__ __launch_bounds__(512) void tn2_kernel(const E* __restrict__ X, int64
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bf16x8 h = *(const bf16x8*)(qb + (size_t)t * 1024 + lane * 16);
-        const bf16x8 lo = *(const bf16x8*)(qb + (size_t)(NT + t) * 1024 + lane * 16);
+        if constexpr (NPL == 2) {
+          const bf16x8 lo = *(const bf16x8*)(qb + (size_t)(NT + t) * 1024 + lane * 16);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[t][j] = mfma_bf(h, b[j], acc[t][j]);
-          acc[t][j] = mfma_bf(lo, b[j], acc[t][j]);
+          for (int j = 0; j < 4; ++j) {
+            acc[t][j] = mfma_bf(h, b[j], acc[t][j]);
+            acc[t][j] = mfma_bf(lo, b[j], acc[t][j]);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[t][j] = mfma_bf(h, b[j], acc[t][j]);
         }
       }
     } else {
@@ -1298,8 +1305,8 @@ hipError_t launch_nn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
 
 template <typename E, int NT>
 static hipError_t launch_tn2_t(dim3 grid, const XPlan& pl, hipStream_t s, const E* X, int64_t m, int64_t n,
-                               int64_t ldx, const E* Qt, int64_t ldqt, int lp, float* part) {
-  auto fn = tn2_kernel<E, NT>;
+                               int64_t ldx, const E* Qt, int64_t ldqt, int lp, float* part, int one_plane) {
+  auto fn = (sizeof(E) == 2 && one_plane) ? tn2_kernel<E, NT, 1> : tn2_kernel<E, NT, 2>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds2);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, grid, dim3(512), pl.lds2, s, X, m, n, ldx, Qt, ldqt, lp, part, pl.klen2);
@@ -1307,7 +1314,7 @@ static hipError_t launch_tn2_t(dim3 grid, const XPlan& pl, hipStream_t s, const 
 }
 
 hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, const void* Qt, int64_t ldqt,
-                     int l, void* Z, int transposed, void* part, const XPlan& pl, hipStream_t s) {
+                     int l, void* Z, int transposed, void* part, const XPlan& pl, hipStream_t s, int one_plane) {
   const int ntile = ceil_div(l, 16);
   const int lp = ntile * 16;
   const int splits = pl.splits;
@@ -1317,10 +1324,10 @@ hipError_t launch_tn(const void* X, int cdt, int64_t m, int64_t n, int64_t ldx, 
     hipError_t e0;
     if (cdt == 1) {
       NT_SWITCH(ntile, e0 = (launch_tn2_t<float, NT>)(grid, pl, s, (const float*)X, m, n, ldx, (const float*)Qt,
-                                                    ldqt, lp, (float*)part));
+                                                    ldqt, lp, (float*)part, 0));
     } else {
       NT_SWITCH(ntile, e0 = (launch_tn2_t<bf16_t, NT>)(grid, pl, s, (const bf16_t*)X, m, n, ldx, (const bf16_t*)Qt,
-                                                     ldqt, lp, (float*)part));
+                                                     ldqt, lp, (float*)part, one_plane));
     }
     if (e0 != hipSuccess) return e0;
     return launch_reduce<float, float>((const float*)part, pl.s2, n, l, lp, (float*)Z, transposed, s);
