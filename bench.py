@@ -278,7 +278,7 @@ def main():
         "data": "synthetic (seeded rank-50 uniform product + N(0,0.05^2) noise, clipped)",
         "config": {"workload": WORKLOAD, "m": m, "n": n, "k": k, "p": p, "q": q + 1, "l": l,
                    "sweeps": sweeps, "step": "cast+sketch+compress+init+200 sweeps+rel_err",
-                   "x_pass_arithmetic": "bf16 MFMA (X bf16; Q split hi+lo in X^T Q and Q^T X, operand bf16 in the sketch passes), fp32 accumulate",
+                   "x_pass_arithmetic": "bf16 MFMA (X bf16; Q split hi+lo in the compression Q^T X, operand bf16 in the subspace-iteration passes), fp32 accumulate",
                    "sweep_arithmetic": "fp32 (H phase fp64)"},
         "rel_err": {"bf16": reps_b[-1]["rel_err"], "fp32": reps_f[-1]["rel_err"]},
         "oracle_parity": parity,
@@ -665,15 +665,17 @@ def xpass_kernels(rn, torch, step, m, n, l):
     from torch.profiler (the HIP runtime's kernel records): GB/s of X moved
     per pass, fraction of 8 TB/s, and the matrix cores' utilisation against
     the dense peak of the arithmetic they run (executed products: the BF16
-    form's split operand doubles them)."""
+    compression's split operand doubles them)."""
+    import re
     from torch.profiler import profile, ProfilerActivity
     lp = ((l + 15) // 16) * 16
     kinds = {
-        "nn_bf16": ("nn2_kernel<unsigned short", 2, 2 * m * n * lp, PEAK_BF16_TFLOPS),
-        "tn_bf16": ("tn2_kernel<unsigned short", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
-        "nn_fp32": ("nn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
-        "tn_fp32": ("tn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
-        "cast_bf16": ("cast_bf16_kernel", 6, 0, None),
+        "nn_bf16": (r"nn2_kernel<unsigned short", 2, 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "tn_bf16_one_plane": (r"tn2_kernel<unsigned short, \d+, 1>", 2, 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "tn_bf16_hi_lo": (r"tn2_kernel<unsigned short, \d+, 2>", 2, 2 * 2 * m * n * lp, PEAK_BF16_TFLOPS),
+        "nn_fp32": (r"nn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
+        "tn_fp32": (r"tn2_kernel<float", 4, 2 * m * n * lp, PEAK_FP32_MFMA_TFLOPS),
+        "cast_bf16": (r"cast_bf16_kernel", 6, 0, None),
     }
     times = {key: [] for key in kinds}
     try:
@@ -687,7 +689,7 @@ def xpass_kernels(rn, torch, step, m, n, l):
                 if dt <= 0.0:
                     continue
                 for key, (pat, _, _, _) in kinds.items():
-                    if pat in e.name:
+                    if re.search(pat, e.name):
                         times[key].append(dt)
     except Exception as ex:  # the profiler is optional context for the line
         return {"error": str(ex)[:200]}
@@ -704,7 +706,8 @@ def xpass_kernels(rn, torch, step, m, n, l):
             d["frac_of_mfma_peak"] = round(flops / (us * 1e-6) / 1e12 / peak, 4)
         out[key] = d
     out["note"] = ("bytes: X once per pass (cast: 4 B read + 2 B written per element); MFMA flops as executed "
-                   f"(l = {l} padded to {lp} columns; BF16 TN passes hi + lo operand planes, NN passes one plane)")
+                   f"(l = {l} padded to {lp} columns; the BF16 compression B = Q^T X reads hi + lo operand planes, "
+                   "the passes of the subspace iteration one plane)")
     return out
 
 
