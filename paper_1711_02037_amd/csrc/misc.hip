@@ -325,14 +325,18 @@ __global__ __launch_bounds__(1024) void sum_pairs_kernel(const double* __restric
 
 // FP32 X: ||X - W H||_F^2 and ||X||_F^2 with W H on FP32 matrix cores
 // (v_mfma_f32_16x16x4_f32: lane (i, g) holds A[i][g], B[g][i], and D[4g + e][i]
-// in element e).  A workgroup owns a balanced range of 16-row tiles (wave w:
-// tiles w, w + 8, ...) and keeps their W fragments in registers; H passes
-// through LDS 64 columns at a time (register prefetch, double buffer), and X
-// is read once, in the layout of the MFMA result.  Squared differences are
-// added per tile in FP32 and across tiles in FP64.
+// in element e).  The product is formed transposed, D = H^T W^T, so that lane
+// (i, g) holds W H at row i and the 4 adjacent columns 4g .. 4g + 3 of a
+// 16 x 16 tile: the lane reads its X values with one 16-byte load (VEC: n and
+// ldx multiples of 4, X 16-byte aligned; otherwise element by element).  A
+// workgroup owns a balanced range of 16-row tiles (wave w: tiles w, w + 8,
+// ...) and keeps their W fragments in registers; H passes through LDS 64
+// columns at a time (register prefetch, double buffer).  X is read once, one
+// tile ahead of the products that consume it.  Squared differences are added
+// per tile in FP32 and across tiles in FP64.
 typedef float rfloatx4 __attribute__((ext_vector_type(4)));
 
-template <int RWMAX>
+template <int RWMAX, bool VEC>
 __global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n,
                                                           int64_t ldx, const float* __restrict__ W,
                                                           const float* __restrict__ H, int k, int tiles, int G,
@@ -378,25 +382,40 @@ __global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restric
       hs[buf][((((kk >> 2) * 4) + (c >> 4)) * 4 + (kk & 3)) * 16 + (c & 15)] = pre[q];
     }
   };
+  // X of column tile ct of block cb: lane (i, g), row tile tau -> row
+  // 16 tau + i, columns 64 cb + 16 ct + 4 g + e (zero outside X)
+  auto load_x = [&](int64_t cb, int ct, rfloatx4 (&xv)[RWMAX]) {
+    const int64_t col = cb * 64 + ct * 16 + 4 * gq;
+#pragma unroll
+    for (int rt = 0; rt < RWMAX; ++rt) {
+      const int tau = wave + 8 * rt;
+      const int64_t row = (int64_t)(t0 + tau) * 16 + i;
+      const bool live = tau < nt && row < m;
+      rfloatx4 v = rfloatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (VEC) {
+        if (live && col < n) v = *(const rfloatx4*)(X + row * ldx + col);  // n % 4 == 0: all 4 inside
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (live && col + e < n) v[e] = X[row * ldx + col + e];
+      }
+      xv[rt] = v;
+    }
+  };
   double se = 0.0, sx = 0.0;
+  rfloatx4 xa[RWMAX], xb[RWMAX];
+  load_x(0, 0, xa);
   fetch(0);
   store(0);
   __syncthreads();
   for (int64_t cb = 0; cb < nb; ++cb) {
     const int buf = (int)(cb & 1);
     if (cb + 1 < nb) fetch(cb + 1);
+#pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
-      const int64_t col = cb * 64 + ct * 16 + i;
-      float xv[RWMAX][4];
-#pragma unroll
-      for (int rt = 0; rt < RWMAX; ++rt) {
-        const int tau = wave + 8 * rt;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t row = (int64_t)(t0 + tau) * 16 + 4 * gq + e;
-          xv[rt][e] = (tau < nt && row < m && col < n) ? X[row * ldx + col] : 0.0f;
-        }
-      }
+      // the next tile's X is in flight while this tile's products run
+      if (ct < 3) load_x(cb, ct + 1, xb);
+      else if (cb + 1 < nb) load_x(cb + 1, 0, xb);
       float hf[KSM];
 #pragma unroll
       for (int s = 0; s < KSM; ++s) hf[s] = (s < ks) ? hs[buf][(s * 4 + ct) * 64 + lane] : 0.0f;
@@ -406,17 +425,19 @@ __global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restric
         rfloatx4 d = rfloatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KSM; ++s)
-          if (s < ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(wf[rt][s], hf[s], d, 0, 0, 0);
+          if (s < ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(hf[s], wf[rt][s], d, 0, 0, 0);
         float le = 0.0f, lx = 0.0f;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float df = xv[rt][e] - d[e];  // rows and columns outside X hold x = 0 and d = 0
+          const float df = xa[rt][e] - d[e];  // rows and columns outside X hold x = 0 and d = 0
           le = fmaf(df, df, le);
-          lx = fmaf(xv[rt][e], xv[rt][e], lx);
+          lx = fmaf(xa[rt][e], xa[rt][e], lx);
         }
         se += (double)le;
         sx += (double)lx;
       }
+#pragma unroll
+      for (int rt = 0; rt < RWMAX; ++rt) xa[rt] = xb[rt];
     }
     if (cb + 1 < nb) store(buf ^ 1);
     __syncthreads();
@@ -449,8 +470,13 @@ hipError_t launch_relerr(const void* X, int xt, int dt, int64_t m, int64_t n, in
     if (g > tiles) g = tiles;
     if (g < ceil_div(tiles, 32)) g = ceil_div(tiles, 32);
     if (g <= nparts_max) {
-      hipLaunchKernelGGL(relerr_mfma_kernel<4>, dim3((unsigned)g), dim3(512), 0, s, (const float*)X, m, n, ldx,
-                         (const float*)W, (const float*)H, k, (int)tiles, (int)g, part);
+      const bool vec = n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0;
+      if (vec)
+        hipLaunchKernelGGL((relerr_mfma_kernel<4, true>), dim3((unsigned)g), dim3(512), 0, s, (const float*)X, m, n,
+                           ldx, (const float*)W, (const float*)H, k, (int)tiles, (int)g, part);
+      else
+        hipLaunchKernelGGL((relerr_mfma_kernel<4, false>), dim3((unsigned)g), dim3(512), 0, s, (const float*)X, m, n,
+                           ldx, (const float*)W, (const float*)H, k, (int)tiles, (int)g, part);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, part, (int)g, out);

@@ -477,8 +477,12 @@ def test_compress_streamed_shapes(prec, m, n, ld, l):
     assert relf(B, Bo) <= 1e-5
 
 
+# n % 4 == 0 takes the 16-byte loads of X in the matrix-core kernel (at least
+# 128 row tiles), the other widths its element loads, the small shapes the
+# tiled kernel
 @pytest.mark.parametrize("m,n,k", [(1000, 300, 10), (3001, 2411, 50), (20007, 333, 7), (100000, 130, 64),
-                                   (50, 40, 3)])
+                                   (50, 40, 3), (3001, 2412, 50), (4099, 1000, 33), (100000, 132, 64),
+                                   (2048, 4, 1)])
 def test_rel_error_matches_fp64(m, n, k):
     g = s.stream(71, m, n)
     X = g.random((m, n), dtype=np.float32)
