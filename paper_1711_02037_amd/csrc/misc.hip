@@ -1,6 +1,7 @@
 // Small kernels: fills, the Philox test-matrix generator, the BF16 cast and
 // input scan, and the relative reconstruction error.
 #include "rnmf_common.h"
+#include <type_traits>
 
 namespace rnmf {
 
@@ -351,6 +352,9 @@ __global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restric
   const int t0 = (int)((int64_t)tiles * gidx / G), t1 = (int)((int64_t)tiles * (gidx + 1) / G);
   const int nt = t1 - t0;
   const int ks = (k + 3) >> 2;
+  // row tiles of this wave: wave + 8 rt < nt for rt < nrt
+  int nrt = nt > wave ? (nt - wave + 7) / 8 : 0;
+  if (nrt > RWMAX) nrt = RWMAX;
   float wf[RWMAX][KSM];
 #pragma unroll
   for (int rt = 0; rt < RWMAX; ++rt) {
@@ -419,22 +423,39 @@ __global__ __launch_bounds__(512) void relerr_mfma_kernel(const float* __restric
       float hf[KSM];
 #pragma unroll
       for (int s = 0; s < KSM; ++s) hf[s] = (s < ks) ? hs[buf][(s * 4 + ct) * 64 + lane] : 0.0f;
+      // the wave's live row tiles are rt < nrt; their product chains are
+      // interleaved (one compile-time form per count) so that the matrix
+      // cores never wait on the previous product of the same chain
+      auto products = [&](auto R) __attribute__((always_inline)) {
+        constexpr int NR = decltype(R)::value;
+        rfloatx4 d[NR];
 #pragma unroll
-      for (int rt = 0; rt < RWMAX; ++rt) {
-        if (wave + 8 * rt >= nt) continue;
-        rfloatx4 d = rfloatx4{0.f, 0.f, 0.f, 0.f};
+        for (int rt = 0; rt < NR; ++rt) d[rt] = rfloatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KSM; ++s)
-          if (s < ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(hf[s], wf[rt][s], d, 0, 0, 0);
-        float le = 0.0f, lx = 0.0f;
+          if (s < ks)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float df = xa[rt][e] - d[e];  // rows and columns outside X hold x = 0 and d = 0
-          le = fmaf(df, df, le);
-          lx = fmaf(xa[rt][e], xa[rt][e], lx);
+            for (int rt = 0; rt < NR; ++rt) d[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(hf[s], wf[rt][s], d[rt], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          float le = 0.0f, lx = 0.0f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float df = xa[rt][e] - d[rt][e];  // rows and columns outside X hold x = 0 and d = 0
+            le = fmaf(df, df, le);
+            lx = fmaf(xa[rt][e], xa[rt][e], lx);
+          }
+          se += (double)le;
+          sx += (double)lx;
         }
-        se += (double)le;
-        sx += (double)lx;
+      };
+      static_assert(RWMAX == 4, "one products form per live tile count");
+      switch (nrt) {
+        case 4: products(std::integral_constant<int, 4>{}); break;
+        case 3: products(std::integral_constant<int, 3>{}); break;
+        case 2: products(std::integral_constant<int, 2>{}); break;
+        case 1: products(std::integral_constant<int, 1>{}); break;
+        default: break;
       }
 #pragma unroll
       for (int rt = 0; rt < RWMAX; ++rt) xa[rt] = xb[rt];
