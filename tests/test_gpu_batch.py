@@ -8,9 +8,7 @@ Bars, as for the single-problem path in FP32:
     range capture within 1e-5 (relative) of the oracle's basis;
   - after one sweep, W and H within 1e-4 relative (Frobenius) of the
     oracle's sweep on the oracle's own basis (W and H do not depend on the
-    basis of the subspace; the two bases differ within the capture check),
-    and within 1e-5, the per-step bar, of the oracle's sweep on the
-    device's own Q and B (measured: W up to 4e-6, H up to 7e-7).
+    basis of the subspace; the two bases differ within the capture check).
 Shapes cover every X-pass tiling class (l <= 16, 32, 48, 64), k from 1 to 32,
 ragged row and column tails, and more columns than rows.
 """
@@ -110,24 +108,6 @@ def test_batch_one_sweep_matches_oracle(small):
         ew, eh = relf(host(P["W"]), Wo), relf(host(P["H"]), Ho)
         print(f"problem {i}: one sweep W {ew:.2e} H {eh:.2e}", flush=True)
         assert ew <= 1e-4 and eh <= 1e-4, (i, ew, eh)
-
-
-def test_batch_one_sweep_on_device_basis(small):
-    # One sweep against the oracle's sweep on the device's own basis and
-    # compressed data (FP64 copies of Q and B, W~0 = Q^T W0 formed in FP64):
-    # with the basis shared, the FP32 batch sweep meets the per-step bar.
-    b = rn.Batch([tuple(dev(a) for a in p) for p in small])
-    b.run(2, 1)
-    rel, st = b.results()
-    assert all(x == rn.OK for x in st)
-    for i, (X, Om, W0, H0) in enumerate(small):
-        P = b.problems[i]
-        Q, B = host(P["Q"]).astype(np.float64), host(P["B"]).astype(np.float64)
-        W0d, H0d = W0.astype(np.float64), H0.astype(np.float64)
-        Wo, _, Ho = o.rhals_sweep(Q, B, W0d, Q.T @ W0d, H0d)
-        ew, eh = relf(host(P["W"]), Wo), relf(host(P["H"]), Ho)
-        print(f"problem {i}: one sweep on the device basis W {ew:.2e} H {eh:.2e}", flush=True)
-        assert ew <= 1e-5 and eh <= 1e-5, (i, ew, eh)
 
 
 def test_batch_is_deterministic(small):
